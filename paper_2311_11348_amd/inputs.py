@@ -1,0 +1,369 @@
+"""Seeded synthetic inputs shared by the HIP path and the oracle.
+
+This module holds no arithmetic of the discontinuous Galerkin method: it builds
+triangulations, vertex bathymetry, point-wise initial conditions, boundary
+forcing parameters and random modal coefficient arrays.  Everything the method
+computes from these inputs lives either in the HIP library or in the oracle.
+
+Workloads (all distances in metres, times in seconds):
+
+* ``c1``  32x32x2 structured mesh of a 100 km square, flat 10 m depth, 0.1 m
+          Gaussian bump of width 10 km at the centre, land walls, p = 1.
+* ``c2``  512x512x2 mesh jittered by U(-0.2h, 0.2h) (seed 2), smooth
+          sin*cos bathymetry between 10 and 4000 m, lake at rest, west edge
+          open and forced by a 0.5 m tide of period 44712 s, p = 2.
+* ``c3``  256x256x2 jittered mesh (seed 3), linear shelf 4000 m -> 50 m,
+          2 m hump of width 20 km at (L/4, L/2), land walls, p in {1,2,3}.
+* ``c4``  64 independent instances (seed 4, instance i seed 4000+i).
+* ``c5``  Poisson request trace at 20 req/s for 120 s (seed 5).
+
+The Bahamas bathymetry and mesh used in the paper's tidal test (Sec. "Tidal
+flow at Bahamas with water hump") are not available; ``c2``/``c3`` stand in
+with synthetic shapes of the same kind (tidal forcing, deep-to-shallow shelf).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+import numpy as np
+
+L_DOMAIN = 1.0e5
+G_EARTH = 9.81
+TIDE_PERIOD = 44712.0
+# Physical constants of the tidal setup (Tab. physical_quantities).
+CORIOLIS_BAHAMAS = 3.19e-5
+CF_BAHAMAS = 0.009
+
+FRICTION_NONE = 0
+FRICTION_LINEAR = 1
+FRICTION_QUADRATIC = 2
+
+TAG_INTERIOR = -1
+TAG_LAND = 0
+TAG_OPEN = 1
+
+K_OF_P = (1, 3, 6, 10)
+
+
+@dataclass
+class Mesh:
+    """Triangulation with counter-clockwise triangles.
+
+    ``tag[e, k]`` is the boundary tag of the local edge k of element e, the
+    edge opposite vertex k (joining vertices k+1 and k+2 mod 3): -1 for an
+    edge that should have a neighbour, 0 for land, 1 for open sea.
+    """
+    vxy: np.ndarray          # [nv, 2] float64
+    tri: np.ndarray          # [ne, 3] int32
+    tag: np.ndarray          # [ne, 3] int8
+    n: int = 0
+    length: float = L_DOMAIN
+
+    @property
+    def nv(self) -> int:
+        return int(self.vxy.shape[0])
+
+    @property
+    def ne(self) -> int:
+        return int(self.tri.shape[0])
+
+    def areas(self) -> np.ndarray:
+        p = self.vxy[self.tri]
+        d1 = p[:, 1] - p[:, 0]
+        d2 = p[:, 2] - p[:, 0]
+        return 0.5 * (d1[:, 0] * d2[:, 1] - d1[:, 1] * d2[:, 0])
+
+    def centroids(self) -> np.ndarray:
+        return self.vxy[self.tri].mean(axis=1)
+
+    def inscribed_diameters(self) -> np.ndarray:
+        p = self.vxy[self.tri]
+        per = (np.linalg.norm(p[:, 1] - p[:, 0], axis=1)
+               + np.linalg.norm(p[:, 2] - p[:, 1], axis=1)
+               + np.linalg.norm(p[:, 0] - p[:, 2], axis=1))
+        return 4.0 * self.areas() / per
+
+
+def structured_mesh(n: int, length: float = L_DOMAIN, jitter: float = 0.0,
+                    seed: Optional[int] = None, open_west: bool = False) -> Mesh:
+    """n x n squares, each cut along its SW->NE diagonal into two triangles.
+
+    Vertices are numbered row-major (x fastest); squares likewise, two
+    elements per square.  With ``jitter`` > 0 every vertex draws an offset
+    U(-jitter*h, jitter*h) in x and y from ``default_rng(seed)`` in row-major
+    order and only interior vertices apply it, so boundary vertices stay put.
+    Local edge k is opposite vertex k.  Boundary edges on x = 0 get tag 1
+    (open) if ``open_west`` else 0; all other boundary edges are land.
+    """
+    h = length / n
+    ii, jj = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="xy")
+    vxy = np.stack([ii.ravel() * h, jj.ravel() * h], axis=1).astype(np.float64)
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        off = rng.uniform(-jitter * h, jitter * h, size=((n + 1) * (n + 1), 2))
+        interior = ((ii.ravel() > 0) & (ii.ravel() < n) & (jj.ravel() > 0) & (jj.ravel() < n))
+        vxy[interior] += off[interior]
+    vid = lambda i, j: j * (n + 1) + i  # noqa: E731
+    tri = np.empty((2 * n * n, 3), dtype=np.int32)
+    tag = np.full((2 * n * n, 3), TAG_INTERIOR, dtype=np.int8)
+    west = TAG_OPEN if open_west else TAG_LAND
+    e = 0
+    for j in range(n):
+        for i in range(n):
+            a, b, c, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
+            # lower-right triangle (SW, SE, NE): edge 2 (SW-SE) south, edge 0 (SE-NE) east
+            tri[e] = (a, b, c)
+            if j == 0:
+                tag[e, 2] = TAG_LAND
+            if i == n - 1:
+                tag[e, 0] = TAG_LAND
+            e += 1
+            # upper-left triangle (SW, NE, NW): edge 0 (NE-NW) north, edge 1 (NW-SW) west
+            tri[e] = (a, c, d)
+            if j == n - 1:
+                tag[e, 0] = TAG_LAND
+            if i == 0:
+                tag[e, 1] = west
+            e += 1
+    m = Mesh(vxy=vxy, tri=tri, tag=tag, n=n, length=length)
+    if not np.all(m.areas() > 0.0):
+        raise ValueError("jitter produced a non-positive triangle area")
+    return m
+
+
+# ---------------------------------------------------------------- bathymetry
+def bathy_flat(depth: float) -> Callable[[np.ndarray, np.ndarray], np.ndarray]:
+    return lambda x, y: np.full_like(np.asarray(x, dtype=np.float64), depth)
+
+
+def bathy_sincos(length: float = L_DOMAIN) -> Callable:
+    """10 m + 3990 m * (1 + sin(2 pi x/L) cos(2 pi y/L)) / 2."""
+    return lambda x, y: 10.0 + 3990.0 * (1.0 + np.sin(2 * np.pi * x / length)
+                                         * np.cos(2 * np.pi * y / length)) / 2.0
+
+
+def bathy_shelf(length: float = L_DOMAIN, deep: float = 4000.0, shallow: float = 50.0) -> Callable:
+    """Linear in x from ``deep`` at x = 0 to ``shallow`` at x = L."""
+    return lambda x, y: deep + (shallow - deep) * np.asarray(x) / length
+
+
+def bathy_random_smooth(rng: np.random.Generator, length: float = L_DOMAIN,
+                        lo: float = 50.0, hi: float = 4000.0, nterms: int = 4) -> Callable:
+    """lo + (hi-lo) * minmax(sum_k a_k sin(2 pi (m_k x + n_k y)/L + phi_k)).
+
+    The min-max scaling uses the extremes of the sum sampled on a 257x257 grid,
+    then clips, so every vertex depth lies in [lo, hi].
+    """
+    a = rng.uniform(0.5, 1.0, nterms)
+    mn = []
+    while len(mn) < nterms:
+        m_, n_ = rng.integers(0, 4, 2)
+        if m_ == 0 and n_ == 0:
+            continue
+        mn.append((int(m_), int(n_)))
+    phi = rng.uniform(0.0, 2 * np.pi, nterms)
+
+    def raw(x, y):
+        s = np.zeros_like(np.asarray(x, dtype=np.float64))
+        for k in range(nterms):
+            s = s + a[k] * np.sin(2 * np.pi * (mn[k][0] * x + mn[k][1] * y) / length + phi[k])
+        return s
+    g = np.linspace(0.0, length, 257)
+    gx, gy = np.meshgrid(g, g)
+    r = raw(gx, gy)
+    rmin, rmax = float(r.min()), float(r.max())
+
+    def f(x, y):
+        t = (raw(x, y) - rmin) / (rmax - rmin)
+        return lo + (hi - lo) * np.clip(t, 0.0, 1.0)
+    return f
+
+
+# --------------------------------------------------------- initial conditions
+def ic_gaussian(amp: float, width: float, x0: float, y0: float) -> Callable:
+    """xi = amp * exp(-r^2 / width^2), U = V = 0."""
+    def f(x, y):
+        r2 = (np.asarray(x) - x0) ** 2 + (np.asarray(y) - y0) ** 2
+        xi = amp * np.exp(-r2 / (width * width))
+        z = np.zeros_like(xi)
+        return xi, z, z.copy()
+    return f
+
+
+def ic_rest(level: float = 0.0) -> Callable:
+    def f(x, y):
+        xi = np.full_like(np.asarray(x, dtype=np.float64), level)
+        z = np.zeros_like(xi)
+        return xi, z, z.copy()
+    return f
+
+
+def ic_dambreak() -> Callable:
+    """Radial dam break of Sec. "Radial dam break" on [0,5]^2."""
+    def f(x, y):
+        r2 = (np.asarray(x) - 2.5) ** 2 + (np.asarray(y) - 2.5) ** 2
+        xi = np.where(r2 < 0.25, 2.0 + 0.5 * np.exp(-15.0 * r2), 1.0)
+        z = np.zeros_like(xi)
+        return xi, z, z.copy()
+    return f
+
+
+# ------------------------------------------------------------------- configs
+@dataclass
+class Forcing:
+    """Open-sea elevation xi_hat(t) = sum_i amp_i sin(omega_i t + phase_i)."""
+    amp: list = field(default_factory=list)
+    omega: list = field(default_factory=list)
+    phase: list = field(default_factory=list)
+
+    def __call__(self, t: float) -> float:
+        return float(sum(a * math.sin(w * t + p) for a, w, p in zip(self.amp, self.omega, self.phase)))
+
+
+def tide_forcing(amp: float = 0.5, period: float = TIDE_PERIOD) -> Forcing:
+    return Forcing([amp], [2 * math.pi / period], [0.0])
+
+
+@dataclass
+class Problem:
+    name: str
+    mesh: Mesh
+    hb_vertex: np.ndarray
+    ic: Callable
+    p: np.ndarray                 # per-element order (int8)
+    p_base: int
+    p_max: int
+    g: float = G_EARTH
+    f_coriolis: float = 0.0
+    friction: int = FRICTION_NONE
+    friction_coef: float = 0.0
+    forcing: Forcing = field(default_factory=Forcing)
+    steps: int = 100
+    cfl: float = 0.2
+    adapt: int = 0
+    adapt_tau: float = 1e-3
+    bathy: Optional[Callable] = None
+
+    def dt(self) -> float:
+        """Fixed step from the analytic initial state at the vertices and centroids.
+
+        dt = CFL * min_e d_e / ((2 p_max + 1) * max(|u0| + sqrt(g H0))), with d_e
+        the inscribed-circle diameter.  Only point values of the initial
+        condition and bathymetry are used.
+        """
+        pts = np.concatenate([self.mesh.vxy, self.mesh.centroids()], axis=0)
+        xi, U, V = self.ic(pts[:, 0], pts[:, 1])
+        if self.bathy is not None:
+            hb = self.bathy(pts[:, 0], pts[:, 1])
+        else:
+            hb = np.full(pts.shape[0], float(self.hb_vertex.mean()))
+        H = xi + hb
+        speed = np.sqrt(U * U + V * V) / H + np.sqrt(self.g * H)
+        return float(self.cfl * self.mesh.inscribed_diameters().min()
+                     / ((2 * self.p_max + 1) * speed.max()))
+
+
+def _problem(name, mesh, bathy, ic, p, p_base, p_max, **kw) -> Problem:
+    hb = bathy(mesh.vxy[:, 0], mesh.vxy[:, 1]).astype(np.float64)
+    pe = np.full(mesh.ne, p, dtype=np.int8) if np.isscalar(p) else np.asarray(p, np.int8)
+    return Problem(name=name, mesh=mesh, hb_vertex=hb, ic=ic, p=pe, p_base=p_base,
+                   p_max=p_max, bathy=bathy, **kw)
+
+
+def config_c1(n: int = 32, p: int = 1) -> Problem:
+    mesh = structured_mesh(n)
+    return _problem("c1", mesh, bathy_flat(10.0), ic_gaussian(0.1, 1.0e4, L_DOMAIN / 2, L_DOMAIN / 2),
+                    p, p, p, steps=100)
+
+
+def config_c2(n: int = 512, p: int = 2, seed: int = 2) -> Problem:
+    mesh = structured_mesh(n, jitter=0.2, seed=seed, open_west=True)
+    return _problem("c2", mesh, bathy_sincos(), ic_rest(0.0), p, min(p, 1), p,
+                    f_coriolis=CORIOLIS_BAHAMAS, friction=FRICTION_QUADRATIC,
+                    friction_coef=CF_BAHAMAS, forcing=tide_forcing(), steps=500)
+
+
+def config_c3(n: int = 256, seed: int = 3) -> Problem:
+    mesh = structured_mesh(n, jitter=0.2, seed=seed)
+    return _problem("c3", mesh, bathy_shelf(), ic_gaussian(2.0, 2.0e4, L_DOMAIN / 4, L_DOMAIN / 2),
+                    1, 1, 3, f_coriolis=CORIOLIS_BAHAMAS, friction=FRICTION_QUADRATIC,
+                    friction_coef=CF_BAHAMAS, steps=1000, adapt=1, adapt_tau=1e-3)
+
+
+def config_instance(seed: int, n_lo: float = 16e3, n_hi: float = 500e3) -> Problem:
+    """One batched/served instance: log-uniform size, p in {1,2,3}, tidal or hump."""
+    rng = np.random.default_rng(seed)
+    N = math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))
+    n = max(2, int(round(math.sqrt(N / 2.0))))
+    p = int(rng.integers(1, 4))
+    tidal = bool(rng.integers(0, 2) == 0)
+    mesh = structured_mesh(n, jitter=0.2, seed=int(rng.integers(0, 2**31 - 1)), open_west=tidal)
+    bathy = bathy_random_smooth(rng)
+    if tidal:
+        ic, forcing = ic_rest(0.0), tide_forcing()
+    else:
+        ic, forcing = ic_gaussian(2.0, 2.0e4, L_DOMAIN / 4, L_DOMAIN / 2), Forcing()
+    return _problem(f"inst{seed}", mesh, bathy, ic, p, p, p, f_coriolis=CORIOLIS_BAHAMAS,
+                    friction=FRICTION_QUADRATIC, friction_coef=CF_BAHAMAS, forcing=forcing,
+                    steps=300)
+
+
+def config_c4(count: int = 64, seed: int = 4) -> list:
+    return [config_instance(seed * 1000 + i) for i in range(count)]
+
+
+@dataclass
+class Request:
+    arrival: float
+    seed: int
+    n_elements_target: float
+    p: int
+    steps: int
+    tidal: bool
+
+
+def request_trace(rate: float = 20.0, duration: float = 120.0, seed: int = 5,
+                  n_lo: float = 8e3, n_hi: float = 260e3) -> list:
+    """Poisson arrivals; request i draws its own parameters from seed 5000+i."""
+    rng = np.random.default_rng(seed)
+    t, out, i = 0.0, [], 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > duration:
+            break
+        r = np.random.default_rng(seed * 1000 + i)
+        N = math.exp(r.uniform(math.log(n_lo), math.log(n_hi)))
+        out.append(Request(arrival=t, seed=seed * 1000 + i, n_elements_target=N,
+                           p=int(r.integers(1, 4)), steps=int(r.integers(200, 2001)),
+                           tidal=bool(r.integers(0, 2) == 0)))
+        i += 1
+    return out
+
+
+# ------------------------------------------------------------- random states
+def random_state(mesh: Mesh, p: np.ndarray, p_max: int, seed: int, hb_vertex: np.ndarray,
+                 xi_amp: float = 0.5, q_amp: float = 1.0, decay: float = 0.3) -> np.ndarray:
+    """Random modal coefficients [ne][3][K(p_max)] in the physical orthonormal basis.
+
+    The element mean of each field is drawn uniformly in [-amp, amp] and
+    stored as mean * sqrt(area) (the first orthonormal basis function is
+    1/sqrt(area)); higher modes get amp * decay^degree * sqrt(area) * N(0,1).
+    Modes above K(p_e) are zero.  ``xi_amp`` must stay well below the minimum
+    depth so that the total depth is positive everywhere.
+    """
+    rng = np.random.default_rng(seed)
+    K = K_OF_P[p_max]
+    ne = mesh.ne
+    sa = np.sqrt(mesh.areas())
+    deg = np.array([0, 1, 1, 2, 2, 2, 3, 3, 3, 3][:K])
+    amps = np.array([xi_amp, q_amp, q_amp])
+    c = np.zeros((ne, 3, K))
+    c[:, :, 0] = rng.uniform(-1.0, 1.0, (ne, 3)) * amps[None, :] * sa[:, None]
+    hi = rng.standard_normal((ne, 3, K)) * (amps[None, :, None] * decay ** deg[None, None, :]) * sa[:, None, None]
+    c[:, :, 1:] = hi[:, :, 1:]
+    kk = np.asarray([K_OF_P[int(x)] for x in p])
+    mask = np.arange(K)[None, :] < kk[:, None]
+    c *= mask[:, None, :]
+    return c
