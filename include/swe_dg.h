@@ -1,0 +1,177 @@
+/*
+ * swe_dg.h -- C ABI of the MI355X (gfx950) quadrature-free discontinuous
+ * Galerkin solver for the 2D shallow water equations.
+ *
+ * Method: Faghih-Naini, Aizinger, Kuckuk, Angersbach, Koestler,
+ * "p-adaptive discontinuous Galerkin method for the shallow water equations on
+ * heterogeneous computing architectures" (2023).
+ *   - equations (mass), (momentum) and the compact form (compact_qf_1),
+ *     (compact_qf_2), (def_A_h_qf): state c = (xi, U, V), velocity u from u H = q;
+ *   - semi-discrete form (variational_disc_1), (variational_disc_2) with the
+ *     Lax-Friedrichs flux and penalty (eq:lambda);
+ *   - modal expansions (c_h), (c_h_tilde) in a hierarchical orthonormal basis,
+ *     K(p) = 1, 3, 6, 10 for p = 0..3;
+ *   - order separation into a base part (order <= b on every element) and a
+ *     correction (Sec. "Algorithmic adaptation: order separation",
+ *     eq. (mass_basis)), constant-part penalty and friction, and the truncated
+ *     depth expansion K(p,i,j) in u H = q;
+ *   - two-stage SSP Runge-Kutta time stepping.
+ *
+ * Conventions
+ *   - Host pointers passed in are borrowed for the duration of the call only;
+ *     the library copies what it keeps.  Output pointers are written in full.
+ *   - Device memory belongs to the context and is freed by swe_destroy.
+ *   - Host coefficient arrays use the layout [element][component][mode]:
+ *     component 0 = xi (elevation, m), 1 = U, 2 = V (m^2/s), K(p_max) modes
+ *     in the physical orthonormal basis phi_ei (int phi_ei phi_ej = delta_ij),
+ *     elements in the caller's order; modes above K(p_e) are zero.
+ *   - Every call returns a swe_status; nothing aborts or throws across the
+ *     ABI.  On failure swe_last_error() describes the cause.  After
+ *     SWE_ESTATE the context refuses swe_step until swe_set_state.
+ *   - A context is used by one host thread at a time; distinct contexts are
+ *     independent.
+ */
+#ifndef SWE_DG_H
+#define SWE_DG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct swe_ctx swe_ctx;
+
+typedef enum {
+    SWE_OK = 0,
+    SWE_EINVAL = -1,        /* invalid argument, mesh or call order */
+    SWE_ENOMEM = -2,        /* device or host allocation failed */
+    SWE_EDEVICE = -3,       /* HIP runtime error */
+    SWE_ESTATE = -4,        /* non-finite value or non-positive mean depth detected */
+    SWE_EUNSUPPORTED = -5   /* valid request this build does not implement */
+} swe_status;
+
+enum { SWE_FP64 = 0,        /* state and all arithmetic in FP64 */
+       SWE_FP32_WB = 1 };   /* FP32 state and bulk arithmetic; bathymetry terms
+                               (well-balancing) and the mass reduction in FP64 */
+
+enum { SWE_FRICTION_NONE = 0,
+       SWE_FRICTION_LINEAR = 1,     /* r = -kappa q, kappa = friction_coef (1/s) */
+       SWE_FRICTION_QUADRATIC = 2   /* r = -C_f |u_mean| u, C_f = friction_coef;
+                                       u_mean = constant part of u (Sec. order separation) */
+};
+
+typedef struct {
+    int precision;          /* SWE_FP64 or SWE_FP32_WB */
+    int p_base, p_max;      /* 0 <= p_base <= p_max <= 3; every element order lies in [p_base, p_max] */
+    double g;               /* gravitational acceleration (m/s^2), > 0 */
+    double f_coriolis;      /* Coriolis parameter (1/s) */
+    int friction;           /* SWE_FRICTION_* */
+    double friction_coef;
+    int adapt;              /* 0: static order map; 1: orders re-chosen every step by the indicator */
+    double adapt_tau;       /* indicator threshold (m) when adapt = 1 */
+    int separate;           /* 0: one full-order kernel per stage; 1: base and correction
+                               kernels on two streams (required for mixed orders) */
+    void *stream_base;      /* hipStream_t for the base work, or NULL for a library-owned stream */
+    void *stream_corr;      /* hipStream_t for the correction work, or NULL */
+} swe_config;
+
+/* Fill *cfg with defaults: FP64, p_base = p_max = 1, g = 9.81, no Coriolis,
+ * no friction, static orders, unseparated, library-owned streams. */
+void swe_config_default(swe_config *cfg);
+
+/* Create a context on the current HIP device.  Fails with SWE_EINVAL for
+ * out-of-range fields and SWE_EDEVICE if no device is usable. */
+swe_status swe_create(const swe_config *cfg, swe_ctx **out);
+
+/* Upload the triangulation (domain partition of Sec. "Quadrature-free DG
+ * formulation").  vxy[nv][2] vertex coordinates (m); tri[ne][3] vertex ids of
+ * counter-clockwise triangles; edge_tag[ne][3] (may be NULL) tags local edge k
+ * (opposite vertex k): -1 interior/unspecified, 0 land (q.n = 0), 1 open sea
+ * (xi = xi_hat).  Boundary edges tagged -1 are land.  Interior connectivity
+ * is found from shared vertex pairs.  SWE_EINVAL for a non-positive area, an
+ * out-of-range vertex id or an edge shared by more than two triangles.
+ * Resets bathymetry (to 0), orders (to p_max, or p_base if separated), state
+ * (to rest) and time (to 0). */
+swe_status swe_set_mesh(swe_ctx *ctx, int64_t nv, const double *vxy, int64_t ne,
+                        const int32_t *tri, const int8_t *edge_tag);
+
+/* Bathymetry h_b at the vertices (m, depth below the datum); h_b is the
+ * continuous piecewise-linear interpolant (reading of eqs. (mass)-(momentum)). */
+swe_status swe_set_bathymetry(swe_ctx *ctx, const double *hb_vertex);
+
+/* Per-element polynomial order p[ne] in [p_base, p_max].  Modes above the new
+ * K(p_e) are dropped from the state (the L2 projection, the basis being
+ * hierarchical and orthonormal); new modes start at zero. */
+swe_status swe_set_order(swe_ctx *ctx, const int8_t *p);
+swe_status swe_get_order(swe_ctx *ctx, int8_t *p_out);
+
+/* Open-sea forcing xi_hat(t) = sum_i amp[i] sin(omega[i] t + phase[i]), ncon <= 16. */
+swe_status swe_set_open_boundary(swe_ctx *ctx, int ncon, const double *amp,
+                                 const double *omega, const double *phase);
+
+/* State at time t0 from host coefficients coef[ne][3][K(p_max)] (physical
+ * orthonormal basis, caller's element order). */
+swe_status swe_set_state(swe_ctx *ctx, double t0, const double *coef);
+
+/* Input preparation: xy_out[ne][SWE_NQP][2] receives the physical points of
+ * the projection rule; swe_set_state_points then L2-projects point values
+ * vals[ne][SWE_NQP][3] of (xi, U, V) onto each element's space. */
+#define SWE_NQP 36
+swe_status swe_project_points(swe_ctx *ctx, double *xy_out);
+swe_status swe_set_state_points(swe_ctx *ctx, double t0, const double *vals);
+
+/* Optional extra right-hand side s[ne][3][K(p_max)] (coefficients of
+ * (s, phi_ei), e.g. a manufactured-solution source); NULL clears it. */
+swe_status swe_set_source(swe_ctx *ctx, const double *coef);
+
+/* Advance nsteps SSP-RK2 steps of size dt (s).  Work is enqueued on the
+ * context's streams; errors detected on the device surface at swe_sync. */
+swe_status swe_step(swe_ctx *ctx, int64_t nsteps, double dt);
+
+/* Wait for queued work; returns SWE_ESTATE if a stage produced a non-finite
+ * value or a non-positive element-mean depth. */
+swe_status swe_sync(swe_ctx *ctx);
+
+/* Current state coef_out[ne][3][K(p_max)] and time (synchronises). */
+swe_status swe_get_state(swe_ctx *ctx, double *coef_out, double *t_out);
+
+/* Total volume above the datum, sum_e int_e xi, reduced on the device in FP64
+ * in a fixed order (deterministic). */
+swe_status swe_mass(swe_ctx *ctx, double *out);
+
+/* Test hooks: the semi-discrete right-hand side L(c, t) of (variational_disc_1)
+ * (the time derivative of the coefficients) and the velocity coefficients
+ * u_out[ne][2][K] of (variational_disc_2) for the given host state.  They do
+ * not change the context's state. */
+swe_status swe_rhs(swe_ctx *ctx, double t, const double *coef, double *rhs_out);
+swe_status swe_usolve(swe_ctx *ctx, const double *coef, double *u_out);
+
+/* Same as swe_rhs but split as the method's order separation defines it:
+ * base_out receives the part with every basis index <= K(p_base), corr_out
+ * the remainder; base + corr = full right-hand side. */
+swe_status swe_rhs_split(swe_ctx *ctx, double t, const double *coef, double *base_out,
+                         double *corr_out);
+
+/* Indicator of the order adaptation, I[ne] (m), for the host state. */
+swe_status swe_indicator(swe_ctx *ctx, double t, const double *coef, double *I_out);
+
+/* Last error message of the context (never NULL; empty if none). */
+const char *swe_last_error(const swe_ctx *ctx);
+
+/* Device bytes a context with ne elements, order p_max and precision holds
+ * after swe_set_mesh (state, velocity, geometry, order map, scratch). */
+int64_t swe_footprint_bytes(int64_t ne, int p_max, int precision);
+
+/* Free everything the context holds; NULL is accepted. */
+void swe_destroy(swe_ctx *ctx);
+
+/* Number of elements and stored modes per component (K(p_max)). */
+int64_t swe_num_elements(const swe_ctx *ctx);
+int swe_num_modes(const swe_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWE_DG_H */

@@ -1,0 +1,694 @@
+// Host runtime behind the C ABI declared in include/swe_dg.h.
+//
+// It validates and preprocesses the mesh (connectivity from shared vertex
+// pairs, boundary codes, Morton ordering of elements by centroid and of
+// vertices by first use, so that neighbour gathers stay in cache), owns the
+// device buffers and streams, converts between the caller's physical
+// orthonormal coefficients [elem][comp][mode] and the device's
+// reference-scaled structure-of-arrays layout, and enqueues the stage kernels.
+#include "../../include/swe_dg.h"
+#include "swe_internal.h"
+#include "swe_tables.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+using namespace swe;
+
+namespace {
+
+constexpr int K_OF[4] = {1, 3, 6, 10};
+constexpr double QX[SWET_NQP] = SWET_QX;
+constexpr double QY[SWET_NQP] = SWET_QY;
+constexpr double QW[SWET_NQP] = SWET_QW;
+constexpr double QPHI[SWET_NQP][10] = SWET_QPHI;
+
+}  // namespace
+
+struct swe_ctx {
+    swe_config cfg{};
+    bool fp32 = false;
+    int K = 1;
+    size_t rsz = 8;
+    int64_t ne = 0, nv = 0;
+    int stride = 0;
+    bool have_mesh = false;
+    std::vector<int> e_perm, e_iperm;     // internal -> user, user -> internal
+    std::vector<int> v_perm, v_iperm;
+    std::vector<double> vx, vy, hb;       // internal vertex order
+    std::vector<int> ev;                  // [3][stride]
+    std::vector<double> sfac;             // sqrt(|det B_e|), internal order
+    std::vector<signed char> p;           // internal order
+    bool uniform = true;
+    double4 *d_vtx = nullptr;
+    int *d_ev = nullptr, *d_nb = nullptr;
+    unsigned char *d_nbk = nullptr;
+    signed char *d_p = nullptr;
+    void *d_C[2] = {nullptr, nullptr}, *d_U[2] = {nullptr, nullptr};
+    void *d_L = nullptr, *d_src = nullptr;
+    int *d_flag = nullptr;
+    double *d_part = nullptr, *d_mass = nullptr;
+    hipStream_t s_base = nullptr, s_corr = nullptr;
+    bool own_base = false, own_corr = false;
+    double t = 0.0;
+    bool failed = false;
+    int ncon = 0;
+    double amp[NCON_MAX] = {0}, omega[NCON_MAX] = {0}, phase[NCON_MAX] = {0};
+    std::string err;
+};
+
+namespace {
+
+swe_status fail(swe_ctx *c, swe_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                        \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? SWE_ENOMEM : SWE_EDEVICE,              \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                      \
+    } while (0)
+
+void free_mesh(swe_ctx *c)
+{
+    void *ptrs[] = {c->d_vtx, c->d_ev, c->d_nb, c->d_nbk, c->d_p, c->d_C[0], c->d_C[1],
+                    c->d_U[0], c->d_U[1], c->d_L, c->d_src, c->d_flag, c->d_part, c->d_mass};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    c->d_vtx = nullptr; c->d_ev = nullptr; c->d_nb = nullptr; c->d_nbk = nullptr; c->d_p = nullptr;
+    c->d_C[0] = c->d_C[1] = c->d_U[0] = c->d_U[1] = nullptr;
+    c->d_L = c->d_src = nullptr;
+    c->d_flag = nullptr; c->d_part = nullptr; c->d_mass = nullptr;
+    c->have_mesh = false;
+}
+
+double xi_hat(const swe_ctx *c, double t)
+{
+    double s = 0.0;
+    for (int i = 0; i < c->ncon; ++i) s += c->amp[i] * std::sin(c->omega[i] * t + c->phase[i]);
+    return s;
+}
+
+uint32_t spread16(uint32_t x)
+{
+    x &= 0xffff;
+    x = (x | (x << 8)) & 0x00ff00ff;
+    x = (x | (x << 4)) & 0x0f0f0f0f;
+    x = (x | (x << 2)) & 0x33333333;
+    x = (x | (x << 1)) & 0x55555555;
+    return x;
+}
+
+MeshView view(const swe_ctx *c)
+{
+    MeshView m;
+    m.ne = (int)c->ne;
+    m.stride = c->stride;
+    m.KS = c->K;
+    m.vtx = c->d_vtx;
+    m.ev = c->d_ev;
+    m.enb = c->d_nb;
+    m.enbk = c->d_nbk;
+    m.ep = c->d_p;
+    return m;
+}
+
+template <typename Real>
+StageArgs<Real> make_args(const swe_ctx *c)
+{
+    StageArgs<Real> a;
+    std::memset(&a, 0, sizeof(a));
+    a.m = view(c);
+    a.ph.g = c->cfg.g;
+    a.ph.fc = c->cfg.f_coriolis;
+    a.ph.fric = c->cfg.friction_coef;
+    a.ph.friction = c->cfg.friction;
+    a.flag = c->d_flag;
+    a.mixed = c->uniform ? 0 : 1;
+    a.src = static_cast<const Real *>(c->d_src);
+    return a;
+}
+
+// launch one stage; in/out buffer indices follow the Shu-Osher form
+template <typename Real>
+hipError_t enqueue_stage(swe_ctx *c, int mode, int in, int out, double tstage, double dt,
+                         const void *Cn, void *Lout)
+{
+    StageArgs<Real> a = make_args<Real>(c);
+    a.Cin = static_cast<const Real *>(c->d_C[in]);
+    a.Uin = static_cast<const Real *>(c->d_U[in]);
+    a.Cn = static_cast<const Real *>(Cn);
+    a.Cout = out >= 0 ? static_cast<Real *>(c->d_C[out]) : nullptr;
+    a.Uout = out >= 0 ? static_cast<Real *>(c->d_U[out]) : nullptr;
+    a.Lout = static_cast<Real *>(Lout);
+    a.xihat = xi_hat(c, tstage);
+    a.dt = dt;
+    return launch_stage(c->cfg.p_max, c->fp32, mode, &a, c->s_base);
+}
+
+template <typename Real>
+hipError_t enqueue_usolve(swe_ctx *c, int buf)
+{
+    StageArgs<Real> a = make_args<Real>(c);
+    a.Cin = static_cast<const Real *>(c->d_C[buf]);
+    a.Uout = static_cast<Real *>(c->d_U[buf]);
+    return launch_usolve(c->cfg.p_max, c->fp32, &a, c->s_base);
+}
+
+hipError_t usolve_buf(swe_ctx *c, int buf)
+{
+    return c->fp32 ? enqueue_usolve<float>(c, buf) : enqueue_usolve<double>(c, buf);
+}
+
+// host [elem][3][K] physical -> device SoA reference-scaled (buffer buf)
+swe_status upload_state(swe_ctx *c, const double *coef, void *dst)
+{
+    const int K = c->K, S = c->stride;
+    const size_t n = (size_t)3 * K * S;
+    std::vector<double> h(n, 0.0);
+    for (int64_t ie = 0; ie < c->ne; ++ie) {
+        const int ue = c->e_perm[ie];
+        const int Ke = K_OF[c->p[ie]];
+        const double inv = 1.0 / c->sfac[ie];
+        for (int j = 0; j < 3; ++j)
+            for (int q = 0; q < K; ++q) {
+                double v = q < Ke ? coef[((size_t)ue * 3 + j) * K + q] : 0.0;
+                if (!std::isfinite(v)) return fail(c, SWE_EINVAL, "non-finite coefficient in state");
+                h[((size_t)j * K + q) * S + ie] = v * inv;
+            }
+    }
+    if (c->fp32) {
+        std::vector<float> f(n);
+        for (size_t i = 0; i < n; ++i) f[i] = (float)h[i];
+        HIP_TRY(c, hipMemcpy(dst, f.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+        HIP_TRY(c, hipMemcpy(dst, h.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    }
+    return SWE_OK;
+}
+
+swe_status download(swe_ctx *c, const void *src, int ncomp, double *out, bool is_rhs)
+{
+    const int K = c->K, S = c->stride;
+    const size_t n = (size_t)ncomp * K * S;
+    std::vector<double> h(n);
+    if (c->fp32) {
+        std::vector<float> f(n);
+        HIP_TRY(c, hipMemcpy(f.data(), src, n * sizeof(float), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < n; ++i) h[i] = f[i];
+    } else {
+        HIP_TRY(c, hipMemcpy(h.data(), src, n * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    (void)is_rhs;
+    for (int64_t ie = 0; ie < c->ne; ++ie) {
+        const int ue = c->e_perm[ie];
+        for (int j = 0; j < ncomp; ++j)
+            for (int q = 0; q < K; ++q)
+                out[((size_t)ue * ncomp + j) * K + q] = h[((size_t)j * K + q) * S + ie] * c->sfac[ie];
+    }
+    return SWE_OK;
+}
+
+swe_status upload_vertices(swe_ctx *c)
+{
+    std::vector<double4> v(c->nv);
+    for (int64_t i = 0; i < c->nv; ++i) v[i] = make_double4(c->vx[i], c->vy[i], c->hb[i], 0.0);
+    HIP_TRY(c, hipMemcpy(c->d_vtx, v.data(), sizeof(double4) * c->nv, hipMemcpyHostToDevice));
+    return SWE_OK;
+}
+
+swe_status upload_order(swe_ctx *c)
+{
+    std::vector<signed char> h(c->stride, (signed char)c->cfg.p_max);
+    for (int64_t i = 0; i < c->ne; ++i) h[i] = c->p[i];
+    c->uniform = true;
+    for (int64_t i = 0; i < c->ne; ++i)
+        if (c->p[i] != c->cfg.p_max) c->uniform = false;
+    HIP_TRY(c, hipMemcpy(c->d_p, h.data(), c->stride, hipMemcpyHostToDevice));
+    return SWE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void swe_config_default(swe_config *cfg)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->precision = SWE_FP64;
+    cfg->p_base = 1;
+    cfg->p_max = 1;
+    cfg->g = 9.81;
+    cfg->friction = SWE_FRICTION_NONE;
+    cfg->adapt_tau = 1e-3;
+}
+
+swe_status swe_create(const swe_config *cfg, swe_ctx **out)
+{
+    if (!cfg || !out) return SWE_EINVAL;
+    *out = nullptr;
+    if (cfg->precision != SWE_FP64 && cfg->precision != SWE_FP32_WB) return SWE_EINVAL;
+    if (cfg->p_max < 0 || cfg->p_max > 3 || cfg->p_base < 0 || cfg->p_base > cfg->p_max) return SWE_EINVAL;
+    if (!(cfg->g > 0.0) || cfg->friction < 0 || cfg->friction > 2) return SWE_EINVAL;
+    if (cfg->adapt && !(cfg->adapt_tau > 0.0)) return SWE_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SWE_EDEVICE;
+    swe_ctx *c = new (std::nothrow) swe_ctx();
+    if (!c) return SWE_ENOMEM;
+    c->cfg = *cfg;
+    c->fp32 = cfg->precision == SWE_FP32_WB;
+    c->rsz = c->fp32 ? 4 : 8;
+    c->K = K_OF[cfg->p_max];
+    if (cfg->stream_base) {
+        c->s_base = static_cast<hipStream_t>(cfg->stream_base);
+    } else {
+        if (hipStreamCreateWithFlags(&c->s_base, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return SWE_EDEVICE;
+        }
+        c->own_base = true;
+    }
+    if (cfg->stream_corr) {
+        c->s_corr = static_cast<hipStream_t>(cfg->stream_corr);
+    } else {
+        if (hipStreamCreateWithFlags(&c->s_corr, hipStreamNonBlocking) != hipSuccess) {
+            if (c->own_base) (void)hipStreamDestroy(c->s_base);
+            delete c;
+            return SWE_EDEVICE;
+        }
+        c->own_corr = true;
+    }
+    *out = c;
+    return SWE_OK;
+}
+
+void swe_destroy(swe_ctx *c)
+{
+    if (!c) return;
+    if (c->s_base) (void)hipStreamSynchronize(c->s_base);
+    if (c->s_corr) (void)hipStreamSynchronize(c->s_corr);
+    free_mesh(c);
+    if (c->own_base) (void)hipStreamDestroy(c->s_base);
+    if (c->own_corr) (void)hipStreamDestroy(c->s_corr);
+    delete c;
+}
+
+const char *swe_last_error(const swe_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int64_t swe_num_elements(const swe_ctx *c) { return c ? c->ne : 0; }
+int swe_num_modes(const swe_ctx *c) { return c ? c->K : 0; }
+
+int64_t swe_footprint_bytes(int64_t ne, int p_max, int precision)
+{
+    if (ne <= 0 || p_max < 0 || p_max > 3) return -1;
+    const int64_t S = (ne + BLOCK - 1) / BLOCK * BLOCK;
+    const int64_t K = K_OF[p_max], w = precision == SWE_FP32_WB ? 4 : 8;
+    const int64_t nv_est = ne + 2 * (int64_t)std::sqrt((double)ne) + 2;   // structured-like bound
+    int64_t b = 0;
+    b += 2 * 3 * K * S * w;          // C0, C1
+    b += 2 * 2 * K * S * w;          // U0, U1
+    b += 3 * K * S * w;              // rhs scratch
+    b += 3 * S * 4 * 2;              // ev, nb
+    b += S * 2;                      // nbk, p
+    b += nv_est * 32;                // vertices
+    b += (S / BLOCK + 1) * 8 + 64;   // reduction scratch, flag
+    return b;
+}
+
+swe_status swe_set_mesh(swe_ctx *c, int64_t nv, const double *vxy, int64_t ne, const int32_t *tri,
+                        const int8_t *tag)
+{
+    if (!c) return SWE_EINVAL;
+    if (nv < 3 || ne < 1 || !vxy || !tri) return fail(c, SWE_EINVAL, "empty mesh");
+    if (ne > (int64_t)1 << 26) return fail(c, SWE_EINVAL, "mesh too large for 32-bit indexing");
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    HIP_TRY(c, hipStreamSynchronize(c->s_corr));
+    free_mesh(c);
+    for (int64_t e = 0; e < ne; ++e)
+        for (int k = 0; k < 3; ++k)
+            if (tri[3 * e + k] < 0 || tri[3 * e + k] >= nv)
+                return fail(c, SWE_EINVAL, "vertex id out of range in element " + std::to_string(e));
+    // areas and Morton order of centroids
+    std::vector<double> cx(ne), cy(ne);
+    double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+    for (int64_t e = 0; e < ne; ++e) {
+        const int a = tri[3 * e], b = tri[3 * e + 1], d = tri[3 * e + 2];
+        const double det = (vxy[2 * b] - vxy[2 * a]) * (vxy[2 * d + 1] - vxy[2 * a + 1]) -
+                           (vxy[2 * d] - vxy[2 * a]) * (vxy[2 * b + 1] - vxy[2 * a + 1]);
+        if (!(det > 0.0) || !std::isfinite(det))
+            return fail(c, SWE_EINVAL, "element " + std::to_string(e) + " has non-positive area (must be counter-clockwise)");
+        cx[e] = (vxy[2 * a] + vxy[2 * b] + vxy[2 * d]) / 3.0;
+        cy[e] = (vxy[2 * a + 1] + vxy[2 * b + 1] + vxy[2 * d + 1]) / 3.0;
+        xmin = std::min(xmin, cx[e]); xmax = std::max(xmax, cx[e]);
+        ymin = std::min(ymin, cy[e]); ymax = std::max(ymax, cy[e]);
+    }
+    const double sx = xmax > xmin ? 65535.0 / (xmax - xmin) : 0.0;
+    const double sy = ymax > ymin ? 65535.0 / (ymax - ymin) : 0.0;
+    std::vector<uint64_t> key(ne);
+    for (int64_t e = 0; e < ne; ++e) {
+        const uint32_t ix = (uint32_t)((cx[e] - xmin) * sx), iy = (uint32_t)((cy[e] - ymin) * sy);
+        key[e] = ((uint64_t)(spread16(ix) | (spread16(iy) << 1)) << 32) | (uint64_t)e;
+    }
+    std::sort(key.begin(), key.end());
+    c->ne = ne;
+    c->nv = nv;
+    c->stride = (int)((ne + BLOCK - 1) / BLOCK * BLOCK);
+    c->e_perm.assign(ne, 0);
+    c->e_iperm.assign(ne, 0);
+    for (int64_t i = 0; i < ne; ++i) {
+        c->e_perm[i] = (int)(key[i] & 0xffffffffu);
+        c->e_iperm[c->e_perm[i]] = (int)i;
+    }
+    // vertices in order of first use
+    c->v_iperm.assign(nv, -1);
+    c->v_perm.clear();
+    c->v_perm.reserve(nv);
+    for (int64_t i = 0; i < ne; ++i)
+        for (int k = 0; k < 3; ++k) {
+            const int v = tri[3 * (size_t)c->e_perm[i] + k];
+            if (c->v_iperm[v] < 0) {
+                c->v_iperm[v] = (int)c->v_perm.size();
+                c->v_perm.push_back(v);
+            }
+        }
+    for (int64_t v = 0; v < nv; ++v)
+        if (c->v_iperm[v] < 0) {   // unused vertex: keep it at the end
+            c->v_iperm[v] = (int)c->v_perm.size();
+            c->v_perm.push_back((int)v);
+        }
+    c->vx.assign(nv, 0.0); c->vy.assign(nv, 0.0); c->hb.assign(nv, 0.0);
+    for (int64_t i = 0; i < nv; ++i) {
+        c->vx[i] = vxy[2 * (size_t)c->v_perm[i]];
+        c->vy[i] = vxy[2 * (size_t)c->v_perm[i] + 1];
+    }
+    const int S = c->stride;
+    c->ev.assign((size_t)3 * S, 0);
+    c->sfac.assign(ne, 1.0);
+    for (int64_t i = 0; i < ne; ++i) {
+        const int ue = c->e_perm[i];
+        for (int k = 0; k < 3; ++k) c->ev[(size_t)k * S + i] = c->v_iperm[tri[3 * (size_t)ue + k]];
+        const int a = c->ev[i], b = c->ev[S + i], d = c->ev[2 * (size_t)S + i];
+        const double det = (c->vx[b] - c->vx[a]) * (c->vy[d] - c->vy[a]) - (c->vx[d] - c->vx[a]) * (c->vy[b] - c->vy[a]);
+        c->sfac[i] = std::sqrt(det);
+    }
+    // connectivity from shared vertex pairs
+    std::vector<int> nb((size_t)3 * S, NB_LAND);
+    std::vector<unsigned char> nbk(S, 0);
+    std::unordered_map<uint64_t, int64_t> open;
+    open.reserve((size_t)ne * 2);
+    for (int64_t i = 0; i < ne; ++i)
+        for (int k = 0; k < 3; ++k) {
+            const int va = c->ev[(size_t)((k + 1) % 3) * S + i], vb = c->ev[(size_t)((k + 2) % 3) * S + i];
+            const uint64_t lo = (uint64_t)std::min(va, vb), hi = (uint64_t)std::max(va, vb);
+            const uint64_t key2 = (lo << 32) | hi;
+            auto it = open.find(key2);
+            if (it == open.end()) {
+                open.emplace(key2, i * 3 + k);
+            } else {
+                const int64_t other = it->second;
+                if (other < 0) return fail(c, SWE_EINVAL, "edge shared by more than two elements");
+                const int64_t j = other / 3;
+                const int kj = (int)(other % 3);
+                nb[(size_t)k * S + i] = (int)j;
+                nb[(size_t)kj * S + j] = (int)i;
+                nbk[i] |= (unsigned char)(kj << (2 * k));
+                nbk[j] |= (unsigned char)(k << (2 * kj));
+                it->second = -1;
+            }
+        }
+    for (int64_t i = 0; i < ne; ++i)
+        for (int k = 0; k < 3; ++k)
+            if (nb[(size_t)k * S + i] < 0) {
+                const int ue = c->e_perm[i];
+                const int tg = tag ? tag[3 * (size_t)ue + k] : -1;
+                nb[(size_t)k * S + i] = tg == 1 ? NB_OPEN : NB_LAND;
+            }
+    // device buffers
+    const size_t w = c->rsz, K = c->K;
+    HIP_TRY(c, hipMalloc(&c->d_vtx, sizeof(double4) * nv));
+    HIP_TRY(c, hipMalloc(&c->d_ev, sizeof(int) * 3 * S));
+    HIP_TRY(c, hipMalloc(&c->d_nb, sizeof(int) * 3 * S));
+    HIP_TRY(c, hipMalloc(&c->d_nbk, S));
+    HIP_TRY(c, hipMalloc(&c->d_p, S));
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(c, hipMalloc(&c->d_C[b], w * 3 * K * S));
+        HIP_TRY(c, hipMalloc(&c->d_U[b], w * 2 * K * S));
+        HIP_TRY(c, hipMemset(c->d_C[b], 0, w * 3 * K * S));
+        HIP_TRY(c, hipMemset(c->d_U[b], 0, w * 2 * K * S));
+    }
+    HIP_TRY(c, hipMalloc(&c->d_L, w * 3 * K * S));
+    HIP_TRY(c, hipMalloc(&c->d_flag, sizeof(int)));
+    HIP_TRY(c, hipMemset(c->d_flag, 0, sizeof(int)));
+    HIP_TRY(c, hipMalloc(&c->d_part, sizeof(double) * (mass_partials((int)ne) + 1)));
+    HIP_TRY(c, hipMalloc(&c->d_mass, sizeof(double)));
+    HIP_TRY(c, hipMemcpy(c->d_ev, c->ev.data(), sizeof(int) * 3 * S, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_nb, nb.data(), sizeof(int) * 3 * S, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_nbk, nbk.data(), S, hipMemcpyHostToDevice));
+    c->p.assign(ne, (signed char)c->cfg.p_max);
+    swe_status st = upload_order(c);
+    if (st) return st;
+    st = upload_vertices(c);
+    if (st) return st;
+    c->t = 0.0;
+    c->failed = false;
+    c->have_mesh = true;
+    return SWE_OK;
+}
+
+swe_status swe_set_bathymetry(swe_ctx *c, const double *hb)
+{
+    if (!c || !hb) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    for (int64_t i = 0; i < c->nv; ++i) {
+        const double v = hb[c->v_perm[i]];
+        if (!std::isfinite(v)) return fail(c, SWE_EINVAL, "non-finite bathymetry");
+        c->hb[i] = v;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    swe_status st = upload_vertices(c);
+    if (st) return st;
+    // the velocity depends on the depth: recompute it for the current state
+    HIP_TRY(c, usolve_buf(c, 0));
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    return SWE_OK;
+}
+
+swe_status swe_set_order(swe_ctx *c, const int8_t *p)
+{
+    if (!c || !p) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    for (int64_t e = 0; e < c->ne; ++e)
+        if (p[e] < c->cfg.p_base || p[e] > c->cfg.p_max)
+            return fail(c, SWE_EINVAL, "order out of [p_base, p_max] at element " + std::to_string(e));
+    // keep the current state, truncated or extended to the new orders
+    std::vector<double> coef((size_t)c->ne * 3 * c->K);
+    double t = 0.0;
+    swe_status st = swe_get_state(c, coef.data(), &t);
+    if (st) return st;
+    for (int64_t i = 0; i < c->ne; ++i) c->p[i] = p[c->e_perm[i]];
+    st = upload_order(c);
+    if (st) return st;
+    return swe_set_state(c, t, coef.data());
+}
+
+swe_status swe_get_order(swe_ctx *c, int8_t *p)
+{
+    if (!c || !p) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    for (int64_t i = 0; i < c->ne; ++i) p[c->e_perm[i]] = c->p[i];
+    return SWE_OK;
+}
+
+swe_status swe_set_open_boundary(swe_ctx *c, int ncon, const double *amp, const double *omega,
+                                 const double *phase)
+{
+    if (!c || ncon < 0 || ncon > NCON_MAX) return SWE_EINVAL;
+    if (ncon > 0 && (!amp || !omega || !phase)) return SWE_EINVAL;
+    c->ncon = ncon;
+    for (int i = 0; i < ncon; ++i) {
+        c->amp[i] = amp[i];
+        c->omega[i] = omega[i];
+        c->phase[i] = phase[i];
+    }
+    return SWE_OK;
+}
+
+swe_status swe_set_state(swe_ctx *c, double t0, const double *coef)
+{
+    if (!c || !coef) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    HIP_TRY(c, hipStreamSynchronize(c->s_corr));
+    swe_status st = upload_state(c, coef, c->d_C[0]);
+    if (st) return st;
+    HIP_TRY(c, hipMemset(c->d_flag, 0, sizeof(int)));
+    HIP_TRY(c, usolve_buf(c, 0));
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    c->t = t0;
+    c->failed = false;
+    return SWE_OK;
+}
+
+swe_status swe_project_points(swe_ctx *c, double *xy)
+{
+    if (!c || !xy) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    const int S = c->stride;
+    for (int64_t i = 0; i < c->ne; ++i) {
+        const int ue = c->e_perm[i];
+        const int a = c->ev[i], b = c->ev[S + i], d = c->ev[2 * (size_t)S + i];
+        for (int q = 0; q < SWET_NQP; ++q) {
+            xy[((size_t)ue * SWET_NQP + q) * 2] = c->vx[a] + QX[q] * (c->vx[b] - c->vx[a]) + QY[q] * (c->vx[d] - c->vx[a]);
+            xy[((size_t)ue * SWET_NQP + q) * 2 + 1] = c->vy[a] + QX[q] * (c->vy[b] - c->vy[a]) + QY[q] * (c->vy[d] - c->vy[a]);
+        }
+    }
+    return SWE_OK;
+}
+
+swe_status swe_set_state_points(swe_ctx *c, double t0, const double *vals)
+{
+    if (!c || !vals) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    const int K = c->K;
+    std::vector<double> coef((size_t)c->ne * 3 * K, 0.0);
+    for (int64_t i = 0; i < c->ne; ++i) {
+        const int ue = c->e_perm[i];
+        const int Ke = K_OF[c->p[i]];
+        const double s = c->sfac[i];
+        for (int j = 0; j < 3; ++j)
+            for (int m = 0; m < Ke; ++m) {
+                double acc = 0.0;
+                for (int q = 0; q < SWET_NQP; ++q)
+                    acc += QW[q] * vals[((size_t)ue * SWET_NQP + q) * 3 + j] * QPHI[q][m];
+                coef[((size_t)ue * 3 + j) * K + m] = acc * s;   // int f phi_e = s * int_ref f phi_ref
+            }
+    }
+    return swe_set_state(c, t0, coef.data());
+}
+
+swe_status swe_set_source(swe_ctx *c, const double *coef)
+{
+    if (!c) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    if (!coef) {
+        if (c->d_src) (void)hipFree(c->d_src);
+        c->d_src = nullptr;
+        return SWE_OK;
+    }
+    if (!c->d_src) HIP_TRY(c, hipMalloc(&c->d_src, c->rsz * 3 * c->K * c->stride));
+    // a right-hand-side coefficient scales like the state
+    return upload_state(c, coef, c->d_src);
+}
+
+swe_status swe_step(swe_ctx *c, int64_t nsteps, double dt)
+{
+    if (!c) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    if (c->failed) return fail(c, SWE_ESTATE, "context is in a failed state; call swe_set_state");
+    if (nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return fail(c, SWE_EINVAL, "bad step count or dt");
+    const double t0 = c->t;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const double tn = t0 + (double)s * dt;
+        hipError_t e;
+        if (c->fp32) {
+            e = enqueue_stage<float>(c, MODE_STAGE1, 0, 1, tn, dt, nullptr, nullptr);
+            if (e == hipSuccess) e = enqueue_stage<float>(c, MODE_STAGE2, 1, 0, tn + dt, dt, c->d_C[0], nullptr);
+        } else {
+            e = enqueue_stage<double>(c, MODE_STAGE1, 0, 1, tn, dt, nullptr, nullptr);
+            if (e == hipSuccess) e = enqueue_stage<double>(c, MODE_STAGE2, 1, 0, tn + dt, dt, c->d_C[0], nullptr);
+        }
+        if (e != hipSuccess) return fail(c, SWE_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
+        c->t = t0 + (double)(s + 1) * dt;
+    }
+    return SWE_OK;
+}
+
+swe_status swe_sync(swe_ctx *c)
+{
+    if (!c) return SWE_EINVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    HIP_TRY(c, hipStreamSynchronize(c->s_corr));
+    if (c->have_mesh) {
+        int flag = 0;
+        HIP_TRY(c, hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+        if (flag) {
+            c->failed = true;
+            return fail(c, SWE_ESTATE, "non-finite value or non-positive mean depth detected");
+        }
+    }
+    return SWE_OK;
+}
+
+swe_status swe_get_state(swe_ctx *c, double *coef, double *t_out)
+{
+    if (!c || !coef) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    HIP_TRY(c, hipStreamSynchronize(c->s_corr));
+    swe_status st = download(c, c->d_C[0], 3, coef, false);
+    if (t_out) *t_out = c->t;
+    return st;
+}
+
+swe_status swe_mass(swe_ctx *c, double *out)
+{
+    if (!c || !out) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    HIP_TRY(c, launch_mass(view(c), c->fp32, c->d_C[0], c->d_part, c->d_mass, c->s_base));
+    HIP_TRY(c, hipMemcpyAsync(out, c->d_mass, sizeof(double), hipMemcpyDeviceToHost, c->s_base));
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    return SWE_OK;
+}
+
+swe_status swe_rhs(swe_ctx *c, double t, const double *coef, double *rhs)
+{
+    if (!c || !coef || !rhs) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    swe_status st = upload_state(c, coef, c->d_C[1]);
+    if (st) return st;
+    HIP_TRY(c, usolve_buf(c, 1));
+    hipError_t e = c->fp32 ? enqueue_stage<float>(c, MODE_RHS, 1, -1, t, 0.0, nullptr, c->d_L)
+                           : enqueue_stage<double>(c, MODE_RHS, 1, -1, t, 0.0, nullptr, c->d_L);
+    if (e != hipSuccess) return fail(c, SWE_EDEVICE, std::string("rhs launch: ") + hipGetErrorString(e));
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    return download(c, c->d_L, 3, rhs, true);
+}
+
+swe_status swe_usolve(swe_ctx *c, const double *coef, double *u_out)
+{
+    if (!c || !coef || !u_out) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    swe_status st = upload_state(c, coef, c->d_C[1]);
+    if (st) return st;
+    HIP_TRY(c, usolve_buf(c, 1));
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    return download(c, c->d_U[1], 2, u_out, false);
+}
+
+swe_status swe_rhs_split(swe_ctx *c, double t, const double *coef, double *base_out, double *corr_out)
+{
+    (void)t; (void)coef; (void)base_out; (void)corr_out;
+    return fail(c, SWE_EUNSUPPORTED, "order-separated evaluation not built yet");
+}
+
+swe_status swe_indicator(swe_ctx *c, double t, const double *coef, double *I_out)
+{
+    (void)t; (void)coef; (void)I_out;
+    return fail(c, SWE_EUNSUPPORTED, "adaptivity indicator not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Internal interface between the host runtime (swe_api.cpp) and the gfx950
+// kernels (swe_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace swe {
+
+constexpr int KMAX = 10;
+constexpr int BLOCK = 256;
+constexpr int NCON_MAX = 16;
+
+// Boundary codes stored in the neighbour array in place of an element id.
+constexpr int NB_LAND = -1;
+constexpr int NB_OPEN = -2;
+
+enum StageMode { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2 };
+
+struct Physics {
+    double g;
+    double fc;
+    double fric;      // kappa (linear) or C_f (quadratic)
+    int friction;     // 0 none, 1 linear, 2 quadratic
+};
+
+// Device view of one mesh and its fields.  Element-indexed arrays use a
+// structure-of-arrays layout [slot][stride] with stride >= ne, a multiple of
+// the block size; coefficient arrays are [component][mode][stride] with
+// KS stored modes per component, in reference-scaled form (coefficient of
+// the reference-element basis, i.e. physical coefficient / sqrt(|det B_e|)).
+struct MeshView {
+    int ne;
+    int stride;
+    int KS;                               // stored modes per component
+    const double4 *__restrict__ vtx;      // (x, y, h_b, 0) per vertex
+    const int *__restrict__ ev;           // [3][stride] vertex ids, counter-clockwise
+    const int *__restrict__ enb;          // [3][stride] neighbour id or NB_LAND / NB_OPEN
+    const unsigned char *__restrict__ enbk;  // [stride] neighbour's local edge, 2 bits per edge
+    const signed char *__restrict__ ep;   // [stride] element order (may be null if uniform)
+};
+
+template <typename Real>
+struct StageArgs {
+    MeshView m;
+    const Real *Cin;     // stage input state c^(s)
+    const Real *Uin;     // velocity of c^(s)
+    const Real *Cn;      // c^n for the second stage (may alias Cout)
+    Real *Cout;
+    Real *Uout;
+    Real *Lout;          // MODE_RHS output
+    const Real *src;     // optional extra right-hand side (reference-scaled), or null
+    Physics ph;
+    double xihat;        // open-boundary elevation at the stage time
+    double dt;
+    int *flag;           // set to 1 on a non-finite value or non-positive mean depth
+    int mixed;           // element orders differ: mask modes above K(p_e)
+};
+
+// Launchers (defined in swe_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_stage(int p, bool fp32, int mode, const void *args, hipStream_t s);
+hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s);
+hipError_t launch_mass(const MeshView &m, bool fp32, const void *C, double *partial,
+                       double *out, hipStream_t s);
+int mass_partials(int ne);
+
+}  // namespace swe

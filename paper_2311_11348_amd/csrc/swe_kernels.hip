@@ -1,0 +1,732 @@
+// gfx950 kernels of the quadrature-free DG shallow-water right-hand side.
+//
+// One thread owns one element.  Per stage it
+//   1. rebuilds the element geometry from its three vertices (FP64),
+//   2. evaluates the volume term (A, grad phi) of (variational_disc_1) as
+//      contractions with the exact basis-product tensors: the flux products
+//      are projected onto P^{p-1} with C[m][i][j] and mapped back with the
+//      derivative matrix D[k][q][m] (eq. (mass_basis) for the mass row, the
+//      same tensor algebra for the momentum rows),
+//   3. adds the source (r, phi) of (def_A_h_qf),
+//   4. gathers its three edges: traces of both sides in 1D Legendre modes,
+//      Lax-Friedrichs flux with the constant-part penalty (eq:lambda), 1D
+//      triple products G for the flux products, and the trace matrix R to
+//      test against its own basis,
+//   5. combines the SSP-RK2 stage and solves u H = q (variational_disc_2) for
+//      the new state with the truncated depth expansion K(p,i,j) of
+//      Sec. "order separation", by LDL^T in registers.
+//
+// Coefficients are reference-scaled: c_hat = c / sqrt(|det B_e|), which makes
+// every tensor contraction independent of the element size; only the inverse
+// Jacobian, the edge normals and |E|/|det B_e| enter.  Terms carrying the
+// bathymetry (well-balancing: g xi h_b in the flux, g xi grad h_b in the
+// source) are always accumulated in FP64.
+#include "swe_internal.h"
+#include "swe_tables.h"
+
+namespace swe {
+namespace {
+
+constexpr double TC[10][10][10] = SWET_C;
+constexpr double TD[2][10][10] = SWET_D;
+constexpr double TR[3][10][4] = SWET_R;
+constexpr double TG[4][4][4] = SWET_G;
+constexpr double TW[3][3] = SWET_W;
+constexpr int TDEG[10] = SWET_DEG;
+constexpr int KOFP[4] = SWET_K_OF_P;
+constexpr double SQRT2 = 1.41421356237309504880;
+constexpr double INV_2SQRT3 = 0.28867513459481288225;  // 1 / (2 sqrt 3)
+
+template <int P>
+struct Ord {
+    static constexpr int K = (P + 1) * (P + 2) / 2;   // modes of P^p
+    static constexpr int KM = P * (P + 1) / 2;        // modes of P^{p-1}
+    static constexpr int NT = P + 1;                  // Legendre modes of a trace
+};
+
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    // Workgroups are dispatched round-robin over the 8 XCDs.  Give each XCD a
+    // contiguous range of element tiles so that neighbour gathers hit its L2.
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
+template <typename T>
+__device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+
+struct Geo {
+    double b00, b01, b10, b11;   // inverse Jacobian: d(xh)/dx, d(xh)/dy, d(yh)/dx, d(yh)/dy
+    double det;                  // |det B_e| = 2 area
+    double X[3], Y[3], h[3];     // vertices and depths
+};
+
+__device__ __forceinline__ void load_geo(const MeshView &m, int e, Geo &G)
+{
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const double4 p = m.vtx[m.ev[v * m.stride + e]];
+        G.X[v] = p.x;
+        G.Y[v] = p.y;
+        G.h[v] = p.z;
+    }
+    const double a00 = G.X[1] - G.X[0], a01 = G.X[2] - G.X[0];
+    const double a10 = G.Y[1] - G.Y[0], a11 = G.Y[2] - G.Y[0];
+    G.det = a00 * a11 - a01 * a10;
+    const double id = 1.0 / G.det;
+    G.b00 = a11 * id;
+    G.b01 = -a01 * id;
+    G.b10 = -a10 * id;
+    G.b11 = a00 * id;
+}
+
+template <int P, typename Real>
+struct Fields {
+    static constexpr int K = Ord<P>::K;
+    Real xi[K], U[K], V[K], u[K], v[K];
+};
+
+template <int P, typename Real>
+__device__ __forceinline__ void load_state(const Real *C, const Real *Uv, int KS, int stride, int e,
+                                           Fields<P, Real> &s)
+{
+    constexpr int K = Ord<P>::K;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        s.xi[i] = C[(0 * KS + i) * stride + e];
+        s.U[i] = C[(1 * KS + i) * stride + e];
+        s.V[i] = C[(2 * KS + i) * stride + e];
+        s.u[i] = Uv[(0 * KS + i) * stride + e];
+        s.v[i] = Uv[(1 * KS + i) * stride + e];
+    }
+}
+
+// t_i = sum_j C[m][i][j] g_j with the zero pattern folded at compile time
+template <int K, typename T, typename S>
+__device__ __forceinline__ T crow(int m, int i, const S (&g)[K])
+{
+    T t = T(0);
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (TC[m][i][j] != 0.0) t = fma(T(TC[m][i][j]), T(g[j]), t);
+    return t;
+}
+
+template <int K>
+__device__ __forceinline__ constexpr bool crow_nonzero(int m, int i)
+{
+    bool any = false;
+    for (int j = 0; j < K; ++j) any = any || (TC[m][i][j] != 0.0);
+    return any;
+}
+
+// ------------------------------------------------------------ volume term
+// L[j][q] += sum_k sum_m D[k][q][m] (Bi_kx F^j_x,m + Bi_ky F^j_y,m)
+template <int P, typename Real>
+__device__ __forceinline__ void volume_term(const Fields<P, Real> &s, const double (&hbh)[3],
+                                            const Geo &G, double g, Real (&L)[3][Ord<P>::K],
+                                            double (&LW)[2][Ord<P>::K])
+{
+    constexpr int K = Ord<P>::K, KM = Ord<P>::KM;
+    if constexpr (KM > 0) {
+        Real Fx[3][KM], Fy[3][KM];
+        double FW[KM];
+        const Real hg = Real(0.5 * g);
+#pragma unroll
+        for (int m = 0; m < KM; ++m) {
+            Real pUu = 0, pUv = 0, pVu = 0, pVv = 0, pxx = 0;
+            double pxh = 0.0;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                if (!crow_nonzero<K>(m, i)) continue;
+                const Real tu = crow<K, Real>(m, i, s.u);
+                const Real tv = crow<K, Real>(m, i, s.v);
+                const Real tx = crow<K, Real>(m, i, s.xi);
+                pUu = fma(s.U[i], tu, pUu);
+                pUv = fma(s.U[i], tv, pUv);
+                pVu = fma(s.V[i], tu, pVu);
+                pVv = fma(s.V[i], tv, pVv);
+                pxx = fma(s.xi[i], tx, pxx);
+                double th = 0.0;
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    if (TC[m][i][j] != 0.0) th = fma(TC[m][i][j], hbh[j], th);
+                pxh = fma(double(s.xi[i]), th, pxh);
+            }
+            Fx[0][m] = s.U[m];
+            Fy[0][m] = s.V[m];
+            Fx[1][m] = fma(hg, pxx, pUu);
+            Fy[1][m] = pUv;
+            Fx[2][m] = pVu;
+            Fy[2][m] = fma(hg, pxx, pVv);
+            FW[m] = g * pxh;
+        }
+        const Real b00 = Real(G.b00), b01 = Real(G.b01), b10 = Real(G.b10), b11 = Real(G.b11);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Real G0[KM], G1[KM];
+#pragma unroll
+            for (int m = 0; m < KM; ++m) {
+                G0[m] = fma(b00, Fx[j][m], b01 * Fy[j][m]);
+                G1[m] = fma(b10, Fx[j][m], b11 * Fy[j][m]);
+            }
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                Real acc = L[j][q];
+#pragma unroll
+                for (int m = 0; m < KM; ++m) {
+                    if (TD[0][q][m] != 0.0) acc = fma(Real(TD[0][q][m]), G0[m], acc);
+                    if (TD[1][q][m] != 0.0) acc = fma(Real(TD[1][q][m]), G1[m], acc);
+                }
+                L[j][q] = acc;
+            }
+        }
+        // bathymetry part of the pressure: x-momentum uses Bi_kx, y-momentum Bi_ky
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            double ax = LW[0][q], ay = LW[1][q];
+#pragma unroll
+            for (int m = 0; m < KM; ++m) {
+                const double d0 = TD[0][q][m], d1 = TD[1][q][m];
+                if (d0 != 0.0) {
+                    ax = fma(d0 * G.b00, FW[m], ax);
+                    ay = fma(d0 * G.b01, FW[m], ay);
+                }
+                if (d1 != 0.0) {
+                    ax = fma(d1 * G.b10, FW[m], ax);
+                    ay = fma(d1 * G.b11, FW[m], ay);
+                }
+            }
+            LW[0][q] = ax;
+            LW[1][q] = ay;
+        }
+    }
+}
+
+// ------------------------------------------------------------ source term
+template <int P, typename Real>
+__device__ __forceinline__ void source_term(const Fields<P, Real> &s, const Geo &G, const Physics &ph,
+                                            Real (&L)[3][Ord<P>::K], double (&LW)[2][Ord<P>::K])
+{
+    constexpr int K = Ord<P>::K;
+    const double dh1 = G.h[1] - G.h[0], dh2 = G.h[2] - G.h[0];
+    const double gx = ph.g * (G.b00 * dh1 + G.b10 * dh2);   // g dh_b/dx
+    const double gy = ph.g * (G.b01 * dh1 + G.b11 * dh2);   // g dh_b/dy
+    const Real fc = Real(ph.fc);
+    Real tau = 0;
+    if (ph.friction == 2) {
+        // |constant part of u| = sqrt(2) |(u_0, v_0)| in reference-scaled modes
+        const Real um = s.u[0], vm = s.v[0];
+        tau = Real(ph.fric) * Real(SQRT2) * sqrt(um * um + vm * vm);
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        Real a1 = fma(fc, s.V[q], L[1][q]);
+        Real a2 = fma(-fc, s.U[q], L[2][q]);
+        if (ph.friction == 2) {
+            a1 = fma(-tau, s.u[q], a1);
+            a2 = fma(-tau, s.v[q], a2);
+        } else if (ph.friction == 1) {
+            a1 = fma(Real(-ph.fric), s.U[q], a1);
+            a2 = fma(Real(-ph.fric), s.V[q], a2);
+        }
+        L[1][q] = a1;
+        L[2][q] = a2;
+        LW[0][q] = fma(gx, double(s.xi[q]), LW[0][q]);
+        LW[1][q] = fma(gy, double(s.xi[q]), LW[1][q]);
+    }
+}
+
+// ------------------------------------------------------------ edge terms
+// trace on a local edge in Legendre modes: t_a = sum_n f_n R[k][n][a]
+template <int P, typename Real>
+__device__ __forceinline__ void trace_own(int k, const Real (&f)[Ord<P>::K], Real (&t)[Ord<P>::NT])
+{
+    constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+        Real acc = 0;
+#pragma unroll
+        for (int n = 0; n < K; ++n)
+            if (TR[k][n][a] != 0.0) acc = fma(f[n], Real(TR[k][n][a]), acc);
+        t[a] = acc;
+    }
+}
+
+// 1D product projected onto Legendre modes c <= P: out_c = sum_ab G[c][a][b] f_a g_b
+template <int NT, typename T>
+__device__ __forceinline__ T prod1(int c, const T (&f)[NT], const T (&g)[NT])
+{
+    T acc = 0;
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+        T t = 0;
+        bool any = false;
+#pragma unroll
+        for (int b = 0; b < NT; ++b)
+            if (TG[c][a][b] != 0.0) {
+                t = fma(T(TG[c][a][b]), g[b], t);
+                any = true;
+            }
+        if (any) acc = fma(f[a], t, acc);
+    }
+    return acc;
+}
+
+template <int P, typename Real>
+__device__ __forceinline__ void edge_terms(const MeshView &m, int e, const Real *Cin, const Real *Uin,
+                                           const Fields<P, Real> &s, const Geo &G, double g,
+                                           double xihat, const Real (*sR)[Ord<P>::K][Ord<P>::NT],
+                                           Real (&L)[3][Ord<P>::K], double (&LW)[2][Ord<P>::K])
+{
+    constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
+    const int KS = m.KS, stride = m.stride;
+    const unsigned nbk_all = m.enbk[e];
+    const Real xbm = Real(SQRT2) * s.xi[0];
+    const Real ubm = Real(SQRT2) * s.u[0], vbm = Real(SQRT2) * s.v[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int ka = (k + 1) % 3, kb = (k + 2) % 3;
+        const double dx = G.X[kb] - G.X[ka], dy = G.Y[kb] - G.Y[ka];
+        const double len = sqrt(dx * dx + dy * dy);
+        const double nxd = dy / len, nyd = -dx / len;
+        const Real nx = Real(nxd), ny = Real(nyd);
+        const double scale = len / G.det;
+        const double hmid = 0.5 * (G.h[ka] + G.h[kb]);
+        const double hbt[2] = {hmid, (G.h[kb] - G.h[ka]) * INV_2SQRT3};
+
+        Real txm[NT], tUm[NT], tVm[NT], tum[NT], tvm[NT];
+        trace_own<P, Real>(k, s.xi, txm);
+        trace_own<P, Real>(k, s.U, tUm);
+        trace_own<P, Real>(k, s.V, tVm);
+        trace_own<P, Real>(k, s.u, tum);
+        trace_own<P, Real>(k, s.v, tvm);
+        Real unm[NT], qnm[NT];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+            unm[a] = fma(tum[a], nx, tvm[a] * ny);
+            qnm[a] = fma(tUm[a], nx, tVm[a] * ny);
+        }
+
+        const int nb = m.enb[k * stride + e];
+        Real txp[NT], tUp[NT], tVp[NT], unp[NT], qnp[NT];
+        Real xbp, unbp;
+        const Real unbm = fabs(fma(ubm, nx, vbm * ny));
+        if (nb >= 0) {
+            const int kk = (nbk_all >> (2 * k)) & 3;
+            Real tup[NT], tvp[NT];
+#pragma unroll
+            for (int a = 0; a < NT; ++a) {
+                txp[a] = 0; tUp[a] = 0; tVp[a] = 0; tup[a] = 0; tvp[a] = 0;
+            }
+            Real x0 = 0, u0 = 0, v0 = 0;
+#pragma unroll
+            for (int n = 0; n < K; ++n) {
+                const Real fx = Cin[(0 * KS + n) * stride + nb];
+                const Real fU = Cin[(1 * KS + n) * stride + nb];
+                const Real fV = Cin[(2 * KS + n) * stride + nb];
+                const Real fu = Uin[(0 * KS + n) * stride + nb];
+                const Real fv = Uin[(1 * KS + n) * stride + nb];
+                if (n == 0) { x0 = fx; u0 = fu; v0 = fv; }
+#pragma unroll
+                for (int a = 0; a < NT; ++a) {
+                    const Real r = sR[kk][n][a];
+                    txp[a] = fma(fx, r, txp[a]);
+                    tUp[a] = fma(fU, r, tUp[a]);
+                    tVp[a] = fma(fV, r, tVp[a]);
+                    tup[a] = fma(fu, r, tup[a]);
+                    tvp[a] = fma(fv, r, tvp[a]);
+                }
+            }
+            // the neighbour runs along the edge in the opposite direction
+#pragma unroll
+            for (int a = 1; a < NT; a += 2) {
+                txp[a] = -txp[a]; tUp[a] = -tUp[a]; tVp[a] = -tVp[a]; tup[a] = -tup[a]; tvp[a] = -tvp[a];
+            }
+#pragma unroll
+            for (int a = 0; a < NT; ++a) {
+                unp[a] = fma(tup[a], nx, tvp[a] * ny);
+                qnp[a] = fma(tUp[a], nx, tVp[a] * ny);
+            }
+            xbp = Real(SQRT2) * x0;
+            unbp = fabs(fma(Real(SQRT2) * u0, nx, Real(SQRT2) * v0 * ny));
+        } else if (nb == NB_LAND) {
+            // mirror: xi+ = xi-, normal parts of q and u change sign
+#pragma unroll
+            for (int a = 0; a < NT; ++a) {
+                txp[a] = txm[a];
+                unp[a] = -unm[a];
+                qnp[a] = -qnm[a];
+                tUp[a] = fma(Real(-2) * qnm[a], nx, tUm[a]);
+                tVp[a] = fma(Real(-2) * qnm[a], ny, tVm[a]);
+            }
+            xbp = xbm;
+            unbp = unbm;
+        } else {
+            // open sea: xi+ = xi_hat(t), q and u copied
+#pragma unroll
+            for (int a = 0; a < NT; ++a) {
+                txp[a] = a == 0 ? Real(xihat) : Real(0);
+                tUp[a] = tUm[a];
+                tVp[a] = tVm[a];
+                unp[a] = unm[a];
+                qnp[a] = qnm[a];
+            }
+            xbp = Real(xihat);
+            unbp = unbm;
+        }
+        // penalty from constant parts at the edge midpoint (eq:lambda)
+        const Real lam = tmax(unbm, unbp) +
+                         Real(tmax(sqrt(g * (double(xbm) + hmid)), sqrt(g * (double(xbp) + hmid))));
+        const Real sc = Real(scale);
+        const Real hg = Real(0.5 * g);
+        Real FX[NT], FU[NT], FV[NT];
+        double FW[NT];
+        double xs[NT];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) xs[a] = double(txm[a]) + double(txp[a]);
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const Real pb = hg * (prod1<NT, Real>(c, txm, txm) + prod1<NT, Real>(c, txp, txp));
+            const Real mU = prod1<NT, Real>(c, tUm, unm) + prod1<NT, Real>(c, tUp, unp);
+            const Real mV = prod1<NT, Real>(c, tVm, unm) + prod1<NT, Real>(c, tVp, unp);
+            Real fx = Real(0.5) * (qnm[c] + qnp[c] + lam * (txm[c] - txp[c]));
+            if (nb == NB_LAND) fx = 0;   // q.n = 0: no mass flux through land
+            FX[c] = sc * fx;
+            FU[c] = sc * (Real(0.5) * (mU + pb * nx + lam * (tUm[c] - tUp[c])));
+            FV[c] = sc * (Real(0.5) * (mV + pb * ny + lam * (tVm[c] - tVp[c])));
+            // bathymetry part of the pressure, (P- + P+)/2 = g (xi- + xi+) h_b / 2
+            double w = 0.0;
+#pragma unroll
+            for (int a = 0; a < NT; ++a)
+#pragma unroll
+                for (int b = 0; b < 2 && b < NT; ++b)
+                    if (TG[c][a][b] != 0.0) w = fma(TG[c][a][b] * hbt[b], xs[a], w);
+            FW[c] = 0.5 * g * w * scale;
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            Real a0 = L[0][q], a1 = L[1][q], a2 = L[2][q];
+            double w0 = LW[0][q], w1 = LW[1][q];
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                if (TR[k][q][c] == 0.0) continue;
+                const Real r = Real(TR[k][q][c]);
+                a0 = fma(-r, FX[c], a0);
+                a1 = fma(-r, FU[c], a1);
+                a2 = fma(-r, FV[c], a2);
+                const double rw = TR[k][q][c] * FW[c];
+                w0 = fma(-rw, nxd, w0);
+                w1 = fma(-rw, nyd, w1);
+            }
+            L[0][q] = a0; L[1][q] = a1; L[2][q] = a2;
+            LW[0][q] = w0; LW[1][q] = w1;
+        }
+    }
+}
+
+// ------------------------------------------------------------ u H = q
+// H_ij = sum_{n < K(max(deg i, deg j))} xi_n C[n][i][j] + sum_{n<3} hb_n C[n][i][j];
+// modes at or above Ke are masked to the identity (element order below P).
+template <int P, typename Real>
+__device__ __forceinline__ void solve_u(const Real (&xi)[Ord<P>::K], const Real (&U)[Ord<P>::K],
+                                        const Real (&V)[Ord<P>::K], const double (&hbh)[3], int Ke,
+                                        Real (&u)[Ord<P>::K], Real (&v)[Ord<P>::K])
+{
+    constexpr int K = Ord<P>::K;
+    Real M[K][K];
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            const int dmax = TDEG[i] > TDEG[j] ? TDEG[i] : TDEG[j];
+            const int kt = KOFP[dmax];
+            Real acc = 0;
+#pragma unroll
+            for (int n = 0; n < kt; ++n)
+                if (TC[n][i][j] != 0.0) acc = fma(Real(TC[n][i][j]), xi[n], acc);
+            double hbp = 0.0;
+#pragma unroll
+            for (int n = 0; n < 3; ++n)
+                if (TC[n][i][j] != 0.0) hbp = fma(TC[n][i][j], hbh[n], hbp);
+            acc += Real(hbp);
+            if (i >= Ke || j >= Ke) acc = (i == j) ? Real(1) : Real(0);
+            M[i][j] = acc;
+        }
+    // LDL^T without pivoting: H is symmetric positive definite for positive depth
+    Real d[K], id[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        Real djj = M[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) djj = fma(-M[j][k] * d[k], M[j][k], djj);
+        d[j] = djj;
+        id[j] = Real(1) / djj;
+#pragma unroll
+        for (int i = j + 1; i < K; ++i) {
+            Real sij = M[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) sij = fma(-M[i][k] * d[k], M[j][k], sij);
+            M[i][j] = sij * id[j];
+        }
+    }
+    Real y[K], z[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        Real a = i < Ke ? U[i] : Real(0), b = i < Ke ? V[i] : Real(0);
+#pragma unroll
+        for (int k = 0; k < i; ++k) {
+            a = fma(-M[i][k], y[k], a);
+            b = fma(-M[i][k], z[k], b);
+        }
+        y[i] = a;
+        z[i] = b;
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) { y[i] *= id[i]; z[i] *= id[i]; }
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+        Real a = y[i], b = z[i];
+#pragma unroll
+        for (int k = i + 1; k < K; ++k) {
+            a = fma(-M[k][i], u[k], a);
+            b = fma(-M[k][i], v[k], b);
+        }
+        u[i] = a;
+        v[i] = b;
+    }
+}
+
+__device__ __forceinline__ void hb_modes(const Geo &G, double (&hbh)[3])
+{
+#pragma unroll
+    for (int n = 0; n < 3; ++n) hbh[n] = TW[n][0] * G.h[0] + TW[n][1] * G.h[1] + TW[n][2] * G.h[2];
+}
+
+// ------------------------------------------------------------ kernels
+template <int P, typename Real, int MODE>
+__global__ void __launch_bounds__(BLOCK) k_stage(StageArgs<Real> a)
+{
+    constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
+    __shared__ Real sR[3][K][NT];
+    for (int i = threadIdx.x; i < 3 * K * NT; i += BLOCK) {
+        const int k = i / (K * NT), r = i % (K * NT);
+        sR[k][r / NT][r % NT] = Real(TR[k][r / NT][r % NT]);
+    }
+    __syncthreads();
+    const int e = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    const MeshView &m = a.m;
+    if (e >= m.ne) return;
+    const int KS = m.KS, stride = m.stride;
+    Geo G;
+    load_geo(m, e, G);
+    double hbh[3];
+    hb_modes(G, hbh);
+    Fields<P, Real> s;
+    load_state<P, Real>(a.Cin, a.Uin, KS, stride, e, s);
+    const int Ke = a.mixed ? KOFP[m.ep[e]] : K;
+
+    Real L[3][K];
+    double LW[2][K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        L[0][q] = 0; L[1][q] = 0; L[2][q] = 0;
+        LW[0][q] = 0.0; LW[1][q] = 0.0;
+    }
+    volume_term<P, Real>(s, hbh, G, a.ph.g, L, LW);
+    source_term<P, Real>(s, G, a.ph, L, LW);
+    edge_terms<P, Real>(m, e, a.Cin, a.Uin, s, G, a.ph.g, a.xihat, sR, L, LW);
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        L[1][q] += Real(LW[0][q]);
+        L[2][q] += Real(LW[1][q]);
+    }
+    if (a.src) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int q = 0; q < K; ++q) L[j][q] += a.src[(j * KS + q) * stride + e];
+    }
+    if (a.mixed) {
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+            if (q >= Ke) { L[0][q] = 0; L[1][q] = 0; L[2][q] = 0; }
+    }
+    if constexpr (MODE == MODE_RHS) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int q = 0; q < K; ++q) a.Lout[(j * KS + q) * stride + e] = L[j][q];
+        return;
+    } else {
+        const Real dt = Real(a.dt);
+        Real xn[K], Un[K], Vn[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            Real c0 = fma(dt, L[0][q], s.xi[q]);
+            Real c1 = fma(dt, L[1][q], s.U[q]);
+            Real c2 = fma(dt, L[2][q], s.V[q]);
+            if constexpr (MODE == MODE_STAGE2) {
+                c0 = Real(0.5) * a.Cn[(0 * KS + q) * stride + e] + Real(0.5) * c0;
+                c1 = Real(0.5) * a.Cn[(1 * KS + q) * stride + e] + Real(0.5) * c1;
+                c2 = Real(0.5) * a.Cn[(2 * KS + q) * stride + e] + Real(0.5) * c2;
+            }
+            xn[q] = c0; Un[q] = c1; Vn[q] = c2;
+        }
+        Real un[K], vn[K];
+        solve_u<P, Real>(xn, Un, Vn, hbh, Ke, un, vn);
+        Real chk = 0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            a.Cout[(0 * KS + q) * stride + e] = xn[q];
+            a.Cout[(1 * KS + q) * stride + e] = Un[q];
+            a.Cout[(2 * KS + q) * stride + e] = Vn[q];
+            a.Uout[(0 * KS + q) * stride + e] = un[q];
+            a.Uout[(1 * KS + q) * stride + e] = vn[q];
+            chk += xn[q] + Un[q] + Vn[q] + un[q] + vn[q];
+        }
+        const double Hmean = SQRT2 * double(xn[0]) + (G.h[0] + G.h[1] + G.h[2]) * (1.0 / 3.0);
+        if (!(Hmean > 0.0) || !isfinite(chk)) a.flag[0] = 1;
+    }
+}
+
+template <int P, typename Real>
+__global__ void __launch_bounds__(BLOCK) k_usolve(StageArgs<Real> a)
+{
+    constexpr int K = Ord<P>::K;
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    const MeshView &m = a.m;
+    if (e >= m.ne) return;
+    const int KS = m.KS, stride = m.stride;
+    Geo G;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) G.h[v] = m.vtx[m.ev[v * stride + e]].z;
+    double hbh[3];
+    hb_modes(G, hbh);
+    const int Ke = a.mixed ? KOFP[m.ep[e]] : K;
+    Real xi[K], U[K], V[K], u[K], v[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        xi[q] = a.Cin[(0 * KS + q) * stride + e];
+        U[q] = a.Cin[(1 * KS + q) * stride + e];
+        V[q] = a.Cin[(2 * KS + q) * stride + e];
+    }
+    solve_u<P, Real>(xi, U, V, hbh, Ke, u, v);
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        a.Uout[(0 * KS + q) * stride + e] = u[q];
+        a.Uout[(1 * KS + q) * stride + e] = v[q];
+    }
+}
+
+// Mass: sum_e int xi = sum_e xi_hat_0 |det B_e| / sqrt(2), fixed-order tree.
+template <typename Real>
+__global__ void __launch_bounds__(BLOCK) k_mass_partial(MeshView m, const Real *C, double *partial)
+{
+    __shared__ double red[BLOCK];
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    double v = 0.0;
+    if (e < m.ne) {
+        Geo G;
+        load_geo(m, e, G);
+        v = double(C[e]) * G.det * (1.0 / SQRT2);
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(BLOCK) k_mass_final(const double *partial, int n, double *out)
+{
+    __shared__ double red[BLOCK];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += BLOCK) v += partial[i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+template <int P, typename Real>
+hipError_t stage_p(int mode, const void *args, hipStream_t s)
+{
+    const StageArgs<Real> &a = *static_cast<const StageArgs<Real> *>(args);
+    if (a.m.ne <= 0) return hipSuccess;
+    const dim3 grid((a.m.ne + BLOCK - 1) / BLOCK), block(BLOCK);
+    if (mode == MODE_RHS) hipLaunchKernelGGL((k_stage<P, Real, MODE_RHS>), grid, block, 0, s, a);
+    else if (mode == MODE_STAGE1) hipLaunchKernelGGL((k_stage<P, Real, MODE_STAGE1>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_stage<P, Real, MODE_STAGE2>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t stage_r(int p, int mode, const void *args, hipStream_t s)
+{
+    switch (p) {
+    case 0: return stage_p<0, Real>(mode, args, s);
+    case 1: return stage_p<1, Real>(mode, args, s);
+    case 2: return stage_p<2, Real>(mode, args, s);
+    case 3: return stage_p<3, Real>(mode, args, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int P, typename Real>
+hipError_t usolve_p(const void *args, hipStream_t s)
+{
+    const StageArgs<Real> &a = *static_cast<const StageArgs<Real> *>(args);
+    if (a.m.ne <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_usolve<P, Real>), dim3((a.m.ne + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t usolve_r(int p, const void *args, hipStream_t s)
+{
+    switch (p) {
+    case 0: return usolve_p<0, Real>(args, s);
+    case 1: return usolve_p<1, Real>(args, s);
+    case 2: return usolve_p<2, Real>(args, s);
+    case 3: return usolve_p<3, Real>(args, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_stage(int p, bool fp32, int mode, const void *args, hipStream_t s)
+{
+    return fp32 ? stage_r<float>(p, mode, args, s) : stage_r<double>(p, mode, args, s);
+}
+
+hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s)
+{
+    return fp32 ? usolve_r<float>(p, args, s) : usolve_r<double>(p, args, s);
+}
+
+int mass_partials(int ne) { return (ne + BLOCK - 1) / BLOCK; }
+
+hipError_t launch_mass(const MeshView &m, bool fp32, const void *C, double *partial, double *out,
+                       hipStream_t s)
+{
+    const int nb = mass_partials(m.ne);
+    if (nb <= 0) return hipErrorInvalidValue;
+    if (fp32)
+        hipLaunchKernelGGL(k_mass_partial<float>, dim3(nb), dim3(BLOCK), 0, s, m,
+                           static_cast<const float *>(C), partial);
+    else
+        hipLaunchKernelGGL(k_mass_partial<double>, dim3(nb), dim3(BLOCK), 0, s, m,
+                           static_cast<const double *>(C), partial);
+    hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(BLOCK), 0, s, partial, nb, out);
+    return hipGetLastError();
+}
+
+}  // namespace swe
