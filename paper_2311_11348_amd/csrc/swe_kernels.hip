@@ -24,6 +24,8 @@
 #include "swe_internal.h"
 #include "swe_tables.h"
 
+#include <type_traits>
+
 namespace swe {
 namespace {
 
@@ -36,6 +38,21 @@ constexpr int TDEG[10] = SWET_DEG;
 constexpr int KOFP[4] = SWET_K_OF_P;
 constexpr double SQRT2 = 1.41421356237309504880;
 constexpr double INV_2SQRT3 = 0.28867513459481288225;  // 1 / (2 sqrt 3)
+
+// Minimum resident waves per SIMD the register allocator must allow for the
+// stage kernel (more waves hide memory latency; fewer avoid spills).
+#ifndef SWE_WAVES_FP64
+#define SWE_WAVES_FP64 1
+#endif
+#ifndef SWE_WAVES_FP32
+#define SWE_WAVES_FP32 2
+#endif
+template <int P, typename Real>
+constexpr int waves_target()
+{
+    // the order-3 kernels spill below 512 registers per lane: leave them at one wave
+    return P >= 3 ? 1 : P <= 1 ? 2 : (std::is_same<Real, double>::value ? SWE_WAVES_FP64 : SWE_WAVES_FP32);
+}
 
 template <int P>
 struct Ord {
@@ -56,17 +73,56 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 template <typename T>
 __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
 
+// Element-indexed arrays are read and written through buffer resources: a
+// uniform descriptor (base, byte size) in scalar registers, a uniform byte
+// offset per (component, mode) slot and one 32-bit lane offset, so no load
+// needs per-lane 64-bit address arithmetic, and an access beyond the array
+// (which the host never issues) reads 0 instead of faulting.
+constexpr int RSRC_WORD3 = 0x00020000;   // raw 32-bit access, gfx9 family
+typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, RSRC_WORD3);
+}
+
+template <typename T>
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+    int slot_bytes;
+    __device__ __forceinline__ Buf(const T *p, int nslots, int stride)
+        : r(make_rsrc(p, (unsigned)nslots * (unsigned)stride * (unsigned)sizeof(T))),
+          slot_bytes(stride * (int)sizeof(T)) {}
+    // off = element index * sizeof(T)
+    __device__ __forceinline__ T ld(int slot, unsigned off) const
+    {
+        if constexpr (sizeof(T) == 8)
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, slot * slot_bytes, 0));
+        else
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, slot * slot_bytes, 0));
+    }
+    __device__ __forceinline__ void st(int slot, unsigned off, T v) const
+    {
+        if constexpr (sizeof(T) == 8)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off,
+                                                  slot * slot_bytes, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off,
+                                                  slot * slot_bytes, 0);
+    }
+};
+
 struct Geo {
     double b00, b01, b10, b11;   // inverse Jacobian: d(xh)/dx, d(xh)/dy, d(yh)/dx, d(yh)/dy
     double det;                  // |det B_e| = 2 area
     double X[3], Y[3], h[3];     // vertices and depths
 };
 
-__device__ __forceinline__ void load_geo(const MeshView &m, int e, Geo &G)
+__device__ __forceinline__ void load_geo(const double4 *vtx, const Buf<int> &ev, unsigned offi, Geo &G)
 {
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
-        const double4 p = m.vtx[m.ev[v * m.stride + e]];
+        const double4 p = vtx[(unsigned)ev.ld(v, offi)];
         G.X[v] = p.x;
         G.Y[v] = p.y;
         G.h[v] = p.z;
@@ -88,17 +144,17 @@ struct Fields {
 };
 
 template <int P, typename Real>
-__device__ __forceinline__ void load_state(const Real *C, const Real *Uv, int KS, int stride, int e,
+__device__ __forceinline__ void load_state(const Buf<Real> &C, const Buf<Real> &Uv, int KS, unsigned off,
                                            Fields<P, Real> &s)
 {
     constexpr int K = Ord<P>::K;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        s.xi[i] = C[(0 * KS + i) * stride + e];
-        s.U[i] = C[(1 * KS + i) * stride + e];
-        s.V[i] = C[(2 * KS + i) * stride + e];
-        s.u[i] = Uv[(0 * KS + i) * stride + e];
-        s.v[i] = Uv[(1 * KS + i) * stride + e];
+        s.xi[i] = C.ld(0 * KS + i, off);
+        s.U[i] = C.ld(1 * KS + i, off);
+        s.V[i] = C.ld(2 * KS + i, off);
+        s.u[i] = Uv.ld(0 * KS + i, off);
+        s.v[i] = Uv.ld(1 * KS + i, off);
     }
 }
 
@@ -121,12 +177,28 @@ __device__ __forceinline__ constexpr bool crow_nonzero(int m, int i)
     return any;
 }
 
+// ------------------------------------------------------------ accumulator
+// acc = c + dt * L(c), built term by term (every geometric factor carries dt).
+// Bathymetry terms go to W: FP64 always; for Real = double W is the momentum
+// rows of L itself, for Real = float a separate FP64 array added at the end.
+template <int P, typename Real>
+struct Acc {
+    static constexpr int K = Ord<P>::K;
+    static constexpr bool SPLIT = !std::is_same<Real, double>::value;
+    Real L[3][K];
+    double W[SPLIT ? 2 : 1][SPLIT ? K : 1];
+    __device__ __forceinline__ double &w(int j, int q)
+    {
+        if constexpr (SPLIT) return W[j][q];
+        else return L[1 + j][q];
+    }
+};
+
 // ------------------------------------------------------------ volume term
-// L[j][q] += sum_k sum_m D[k][q][m] (Bi_kx F^j_x,m + Bi_ky F^j_y,m)
+// acc[j][q] += dt sum_k sum_m D[k][q][m] (Bi_kx F^j_x,m + Bi_ky F^j_y,m)
 template <int P, typename Real>
 __device__ __forceinline__ void volume_term(const Fields<P, Real> &s, const double (&hbh)[3],
-                                            const Geo &G, double g, Real (&L)[3][Ord<P>::K],
-                                            double (&LW)[2][Ord<P>::K])
+                                            const Geo &G, double g, double dt, Acc<P, Real> &A)
 {
     constexpr int K = Ord<P>::K, KM = Ord<P>::KM;
     if constexpr (KM > 0) {
@@ -160,9 +232,10 @@ __device__ __forceinline__ void volume_term(const Fields<P, Real> &s, const doub
             Fy[1][m] = pUv;
             Fx[2][m] = pVu;
             Fy[2][m] = fma(hg, pxx, pVv);
-            FW[m] = g * pxh;
+            FW[m] = g * dt * pxh;
         }
-        const Real b00 = Real(G.b00), b01 = Real(G.b01), b10 = Real(G.b10), b11 = Real(G.b11);
+        const Real b00 = Real(G.b00 * dt), b01 = Real(G.b01 * dt);
+        const Real b10 = Real(G.b10 * dt), b11 = Real(G.b11 * dt);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             Real G0[KM], G1[KM];
@@ -173,33 +246,40 @@ __device__ __forceinline__ void volume_term(const Fields<P, Real> &s, const doub
             }
 #pragma unroll
             for (int q = 0; q < K; ++q) {
-                Real acc = L[j][q];
+                Real acc = A.L[j][q];
 #pragma unroll
                 for (int m = 0; m < KM; ++m) {
                     if (TD[0][q][m] != 0.0) acc = fma(Real(TD[0][q][m]), G0[m], acc);
                     if (TD[1][q][m] != 0.0) acc = fma(Real(TD[1][q][m]), G1[m], acc);
                 }
-                L[j][q] = acc;
+                A.L[j][q] = acc;
             }
         }
         // bathymetry part of the pressure: x-momentum uses Bi_kx, y-momentum Bi_ky
+        double Wx[KM], Wy[KM], Zx[KM], Zy[KM];
+#pragma unroll
+        for (int m = 0; m < KM; ++m) {
+            Wx[m] = G.b00 * FW[m];
+            Wy[m] = G.b01 * FW[m];
+            Zx[m] = G.b10 * FW[m];
+            Zy[m] = G.b11 * FW[m];
+        }
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            double ax = LW[0][q], ay = LW[1][q];
+            double ax = A.w(0, q), ay = A.w(1, q);
 #pragma unroll
             for (int m = 0; m < KM; ++m) {
-                const double d0 = TD[0][q][m], d1 = TD[1][q][m];
-                if (d0 != 0.0) {
-                    ax = fma(d0 * G.b00, FW[m], ax);
-                    ay = fma(d0 * G.b01, FW[m], ay);
+                if (TD[0][q][m] != 0.0) {
+                    ax = fma(TD[0][q][m], Wx[m], ax);
+                    ay = fma(TD[0][q][m], Wy[m], ay);
                 }
-                if (d1 != 0.0) {
-                    ax = fma(d1 * G.b10, FW[m], ax);
-                    ay = fma(d1 * G.b11, FW[m], ay);
+                if (TD[1][q][m] != 0.0) {
+                    ax = fma(TD[1][q][m], Zx[m], ax);
+                    ay = fma(TD[1][q][m], Zy[m], ay);
                 }
             }
-            LW[0][q] = ax;
-            LW[1][q] = ay;
+            A.w(0, q) = ax;
+            A.w(1, q) = ay;
         }
     }
 }
@@ -207,34 +287,36 @@ __device__ __forceinline__ void volume_term(const Fields<P, Real> &s, const doub
 // ------------------------------------------------------------ source term
 template <int P, typename Real>
 __device__ __forceinline__ void source_term(const Fields<P, Real> &s, const Geo &G, const Physics &ph,
-                                            Real (&L)[3][Ord<P>::K], double (&LW)[2][Ord<P>::K])
+                                            double dt, Acc<P, Real> &A)
 {
     constexpr int K = Ord<P>::K;
     const double dh1 = G.h[1] - G.h[0], dh2 = G.h[2] - G.h[0];
-    const double gx = ph.g * (G.b00 * dh1 + G.b10 * dh2);   // g dh_b/dx
-    const double gy = ph.g * (G.b01 * dh1 + G.b11 * dh2);   // g dh_b/dy
-    const Real fc = Real(ph.fc);
+    const double gx = ph.g * dt * (G.b00 * dh1 + G.b10 * dh2);   // dt g dh_b/dx
+    const double gy = ph.g * dt * (G.b01 * dh1 + G.b11 * dh2);   // dt g dh_b/dy
+    const Real fc = Real(ph.fc * dt);
     Real tau = 0;
     if (ph.friction == 2) {
         // |constant part of u| = sqrt(2) |(u_0, v_0)| in reference-scaled modes
         const Real um = s.u[0], vm = s.v[0];
-        tau = Real(ph.fric) * Real(SQRT2) * sqrt(um * um + vm * vm);
+        tau = Real(ph.fric * dt * SQRT2) * sqrt(um * um + vm * vm);
+    } else if (ph.friction == 1) {
+        tau = Real(ph.fric * dt);
     }
 #pragma unroll
     for (int q = 0; q < K; ++q) {
-        Real a1 = fma(fc, s.V[q], L[1][q]);
-        Real a2 = fma(-fc, s.U[q], L[2][q]);
+        Real a1 = fma(fc, s.V[q], A.L[1][q]);
+        Real a2 = fma(-fc, s.U[q], A.L[2][q]);
         if (ph.friction == 2) {
             a1 = fma(-tau, s.u[q], a1);
             a2 = fma(-tau, s.v[q], a2);
         } else if (ph.friction == 1) {
-            a1 = fma(Real(-ph.fric), s.U[q], a1);
-            a2 = fma(Real(-ph.fric), s.V[q], a2);
+            a1 = fma(-tau, s.U[q], a1);
+            a2 = fma(-tau, s.V[q], a2);
         }
-        L[1][q] = a1;
-        L[2][q] = a2;
-        LW[0][q] = fma(gx, double(s.xi[q]), LW[0][q]);
-        LW[1][q] = fma(gy, double(s.xi[q]), LW[1][q]);
+        A.L[1][q] = a1;
+        A.L[2][q] = a2;
+        A.w(0, q) = fma(gx, double(s.xi[q]), A.w(0, q));
+        A.w(1, q) = fma(gy, double(s.xi[q]), A.w(1, q));
     }
 }
 
@@ -275,41 +357,46 @@ __device__ __forceinline__ T prod1(int c, const T (&f)[NT], const T (&g)[NT])
 }
 
 template <int P, typename Real>
-__device__ __forceinline__ void edge_terms(const MeshView &m, int e, const Real *Cin, const Real *Uin,
+__device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const Buf<Real> &bC, const Buf<Real> &bU,
+                                           const Buf<int> &bNb,
                                            const Fields<P, Real> &s, const Geo &G, double g,
-                                           double xihat, const Real (*sR)[Ord<P>::K][Ord<P>::NT],
-                                           Real (&L)[3][Ord<P>::K], double (&LW)[2][Ord<P>::K])
+                                           double xihat, double dt, const Real (*sR)[Ord<P>::K][Ord<P>::NT],
+                                           Acc<P, Real> &A)
 {
     constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
-    const int KS = m.KS, stride = m.stride;
+    const int KS = m.KS;
     const unsigned nbk_all = m.enbk[e];
     const Real xbm = Real(SQRT2) * s.xi[0];
     const Real ubm = Real(SQRT2) * s.u[0], vbm = Real(SQRT2) * s.v[0];
+    const double dt_det = dt / G.det;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int ka = (k + 1) % 3, kb = (k + 2) % 3;
         const double dx = G.X[kb] - G.X[ka], dy = G.Y[kb] - G.Y[ka];
         const double len = sqrt(dx * dx + dy * dy);
-        const double nxd = dy / len, nyd = -dx / len;
+        const double il = 1.0 / len;
+        const double nxd = dy * il, nyd = -dx * il;
         const Real nx = Real(nxd), ny = Real(nyd);
-        const double scale = len / G.det;
+        const double scale = len * dt_det;                 // dt |E| / |det B|
         const double hmid = 0.5 * (G.h[ka] + G.h[kb]);
         const double hbt[2] = {hmid, (G.h[kb] - G.h[ka]) * INV_2SQRT3};
 
-        Real txm[NT], tUm[NT], tVm[NT], tum[NT], tvm[NT];
-        trace_own<P, Real>(k, s.xi, txm);
-        trace_own<P, Real>(k, s.U, tUm);
-        trace_own<P, Real>(k, s.V, tVm);
-        trace_own<P, Real>(k, s.u, tum);
-        trace_own<P, Real>(k, s.v, tvm);
-        Real unm[NT], qnm[NT];
+        Real txm[NT], tUm[NT], tVm[NT], unm[NT], qnm[NT];
+        {
+            Real tum[NT], tvm[NT];
+            trace_own<P, Real>(k, s.xi, txm);
+            trace_own<P, Real>(k, s.U, tUm);
+            trace_own<P, Real>(k, s.V, tVm);
+            trace_own<P, Real>(k, s.u, tum);
+            trace_own<P, Real>(k, s.v, tvm);
 #pragma unroll
-        for (int a = 0; a < NT; ++a) {
-            unm[a] = fma(tum[a], nx, tvm[a] * ny);
-            qnm[a] = fma(tUm[a], nx, tVm[a] * ny);
+            for (int a = 0; a < NT; ++a) {
+                unm[a] = fma(tum[a], nx, tvm[a] * ny);
+                qnm[a] = fma(tUm[a], nx, tVm[a] * ny);
+            }
         }
 
-        const int nb = m.enb[k * stride + e];
+        const int nb = bNb.ld(k, e * 4u);
         Real txp[NT], tUp[NT], tVp[NT], unp[NT], qnp[NT];
         Real xbp, unbp;
         const Real unbm = fabs(fma(ubm, nx, vbm * ny));
@@ -320,17 +407,19 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, int e, const Real 
             for (int a = 0; a < NT; ++a) {
                 txp[a] = 0; tUp[a] = 0; tVp[a] = 0; tup[a] = 0; tvp[a] = 0;
             }
+            const unsigned un_ = (unsigned)nb * (unsigned)sizeof(Real);
             Real x0 = 0, u0 = 0, v0 = 0;
 #pragma unroll
             for (int n = 0; n < K; ++n) {
-                const Real fx = Cin[(0 * KS + n) * stride + nb];
-                const Real fU = Cin[(1 * KS + n) * stride + nb];
-                const Real fV = Cin[(2 * KS + n) * stride + nb];
-                const Real fu = Uin[(0 * KS + n) * stride + nb];
-                const Real fv = Uin[(1 * KS + n) * stride + nb];
+                const Real fx = bC.ld(0 * KS + n, un_);
+                const Real fU = bC.ld(1 * KS + n, un_);
+                const Real fV = bC.ld(2 * KS + n, un_);
+                const Real fu = bU.ld(0 * KS + n, un_);
+                const Real fv = bU.ld(1 * KS + n, un_);
                 if (n == 0) { x0 = fx; u0 = fu; v0 = fv; }
+                // the trace of a degree-d basis function has no Legendre mode above d
 #pragma unroll
-                for (int a = 0; a < NT; ++a) {
+                for (int a = 0; a < NT && a <= TDEG[n]; ++a) {
                     const Real r = sR[kk][n][a];
                     txp[a] = fma(fx, r, txp[a]);
                     tUp[a] = fma(fU, r, tUp[a]);
@@ -377,8 +466,11 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, int e, const Real 
             unbp = unbm;
         }
         // penalty from constant parts at the edge midpoint (eq:lambda)
-        const Real lam = tmax(unbm, unbp) +
-                         Real(tmax(sqrt(g * (double(xbm) + hmid)), sqrt(g * (double(xbp) + hmid))));
+        Real lam;
+        if constexpr (std::is_same<Real, double>::value)
+            lam = tmax(unbm, unbp) + sqrt(g * (tmax(xbm, xbp) + hmid));
+        else
+            lam = tmax(unbm, unbp) + Real(sqrt(g * (double(tmax(xbm, xbp)) + hmid)));
         const Real sc = Real(scale);
         const Real hg = Real(0.5 * g);
         Real FX[NT], FU[NT], FV[NT];
@@ -405,10 +497,15 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, int e, const Real 
                     if (TG[c][a][b] != 0.0) w = fma(TG[c][a][b] * hbt[b], xs[a], w);
             FW[c] = 0.5 * g * w * scale;
         }
+        double FWx[NT], FWy[NT];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            FWx[c] = FW[c] * nxd;
+            FWy[c] = FW[c] * nyd;
+        }
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            Real a0 = L[0][q], a1 = L[1][q], a2 = L[2][q];
-            double w0 = LW[0][q], w1 = LW[1][q];
+            Real a0 = A.L[0][q], a1 = A.L[1][q], a2 = A.L[2][q];
 #pragma unroll
             for (int c = 0; c < NT; ++c) {
                 if (TR[k][q][c] == 0.0) continue;
@@ -416,12 +513,16 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, int e, const Real 
                 a0 = fma(-r, FX[c], a0);
                 a1 = fma(-r, FU[c], a1);
                 a2 = fma(-r, FV[c], a2);
-                const double rw = TR[k][q][c] * FW[c];
-                w0 = fma(-rw, nxd, w0);
-                w1 = fma(-rw, nyd, w1);
             }
-            L[0][q] = a0; L[1][q] = a1; L[2][q] = a2;
-            LW[0][q] = w0; LW[1][q] = w1;
+            A.L[0][q] = a0; A.L[1][q] = a1; A.L[2][q] = a2;
+            double w0 = A.w(0, q), w1 = A.w(1, q);
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                if (TR[k][q][c] == 0.0) continue;
+                w0 = fma(-TR[k][q][c], FWx[c], w0);
+                w1 = fma(-TR[k][q][c], FWy[c], w1);
+            }
+            A.w(0, q) = w0; A.w(1, q) = w1;
         }
     }
 }
@@ -506,7 +607,8 @@ __device__ __forceinline__ void hb_modes(const Geo &G, double (&hbh)[3])
 
 // ------------------------------------------------------------ kernels
 template <int P, typename Real, int MODE>
-__global__ void __launch_bounds__(BLOCK) k_stage(StageArgs<Real> a)
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_target<P, Real>(), 8)))
+k_stage(StageArgs<Real> a)
 {
     constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
     __shared__ Real sR[3][K][NT];
@@ -515,75 +617,84 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs<Real> a)
         sR[k][r / NT][r % NT] = Real(TR[k][r / NT][r % NT]);
     }
     __syncthreads();
-    const int e = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    const unsigned e = (unsigned)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     const MeshView &m = a.m;
-    if (e >= m.ne) return;
+    if (e >= (unsigned)m.ne) return;
     const int KS = m.KS, stride = m.stride;
+    const unsigned off = e * (unsigned)sizeof(Real);
+    const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
+    const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
     Geo G;
-    load_geo(m, e, G);
+    load_geo(m.vtx, bEv, e * 4u, G);
     double hbh[3];
     hb_modes(G, hbh);
     Fields<P, Real> s;
-    load_state<P, Real>(a.Cin, a.Uin, KS, stride, e, s);
+    load_state<P, Real>(bC, bU, KS, off, s);
     const int Ke = a.mixed ? KOFP[m.ep[e]] : K;
 
-    Real L[3][K];
-    double LW[2][K];
+    const double dt = MODE == MODE_RHS ? 1.0 : a.dt;
+    Acc<P, Real> A;
 #pragma unroll
     for (int q = 0; q < K; ++q) {
-        L[0][q] = 0; L[1][q] = 0; L[2][q] = 0;
-        LW[0][q] = 0.0; LW[1][q] = 0.0;
+        A.L[0][q] = MODE == MODE_RHS ? Real(0) : s.xi[q];
+        A.L[1][q] = MODE == MODE_RHS ? Real(0) : s.U[q];
+        A.L[2][q] = MODE == MODE_RHS ? Real(0) : s.V[q];
+        if constexpr (Acc<P, Real>::SPLIT) { A.W[0][q] = 0.0; A.W[1][q] = 0.0; }
     }
-    volume_term<P, Real>(s, hbh, G, a.ph.g, L, LW);
-    source_term<P, Real>(s, G, a.ph, L, LW);
-    edge_terms<P, Real>(m, e, a.Cin, a.Uin, s, G, a.ph.g, a.xihat, sR, L, LW);
+    volume_term<P, Real>(s, hbh, G, a.ph.g, dt, A);
+    source_term<P, Real>(s, G, a.ph, dt, A);
+    edge_terms<P, Real>(m, e, bC, bU, bNb, s, G, a.ph.g, a.xihat, dt, sR, A);
+    if constexpr (Acc<P, Real>::SPLIT) {
 #pragma unroll
-    for (int q = 0; q < K; ++q) {
-        L[1][q] += Real(LW[0][q]);
-        L[2][q] += Real(LW[1][q]);
+        for (int q = 0; q < K; ++q) {
+            A.L[1][q] += Real(A.W[0][q]);
+            A.L[2][q] += Real(A.W[1][q]);
+        }
     }
     if (a.src) {
+        const Buf<Real> bS(a.src, 3 * KS, stride);
+        const Real rdt = Real(dt);
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int q = 0; q < K; ++q) L[j][q] += a.src[(j * KS + q) * stride + e];
+            for (int q = 0; q < K; ++q) A.L[j][q] = fma(rdt, bS.ld(j * KS + q, off), A.L[j][q]);
     }
     if (a.mixed) {
+        // modes above the element's order stay zero
 #pragma unroll
         for (int q = 0; q < K; ++q)
-            if (q >= Ke) { L[0][q] = 0; L[1][q] = 0; L[2][q] = 0; }
+            if (q >= Ke) { A.L[0][q] = 0; A.L[1][q] = 0; A.L[2][q] = 0; }
     }
     if constexpr (MODE == MODE_RHS) {
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int q = 0; q < K; ++q) a.Lout[(j * KS + q) * stride + e] = L[j][q];
+            for (int q = 0; q < K; ++q) Buf<Real>(a.Lout, 3 * KS, stride).st(j * KS + q, off, A.L[j][q]);
         return;
     } else {
-        const Real dt = Real(a.dt);
         Real xn[K], Un[K], Vn[K];
+        const Buf<Real> bN(a.Cn, 3 * KS, stride);
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            Real c0 = fma(dt, L[0][q], s.xi[q]);
-            Real c1 = fma(dt, L[1][q], s.U[q]);
-            Real c2 = fma(dt, L[2][q], s.V[q]);
+            Real c0 = A.L[0][q], c1 = A.L[1][q], c2 = A.L[2][q];
             if constexpr (MODE == MODE_STAGE2) {
-                c0 = Real(0.5) * a.Cn[(0 * KS + q) * stride + e] + Real(0.5) * c0;
-                c1 = Real(0.5) * a.Cn[(1 * KS + q) * stride + e] + Real(0.5) * c1;
-                c2 = Real(0.5) * a.Cn[(2 * KS + q) * stride + e] + Real(0.5) * c2;
+                c0 = Real(0.5) * bN.ld(0 * KS + q, off) + Real(0.5) * c0;
+                c1 = Real(0.5) * bN.ld(1 * KS + q, off) + Real(0.5) * c1;
+                c2 = Real(0.5) * bN.ld(2 * KS + q, off) + Real(0.5) * c2;
             }
             xn[q] = c0; Un[q] = c1; Vn[q] = c2;
         }
         Real un[K], vn[K];
         solve_u<P, Real>(xn, Un, Vn, hbh, Ke, un, vn);
         Real chk = 0;
+        const Buf<Real> bO(a.Cout, 3 * KS, stride), bV(a.Uout, 2 * KS, stride);
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            a.Cout[(0 * KS + q) * stride + e] = xn[q];
-            a.Cout[(1 * KS + q) * stride + e] = Un[q];
-            a.Cout[(2 * KS + q) * stride + e] = Vn[q];
-            a.Uout[(0 * KS + q) * stride + e] = un[q];
-            a.Uout[(1 * KS + q) * stride + e] = vn[q];
+            bO.st(0 * KS + q, off, xn[q]);
+            bO.st(1 * KS + q, off, Un[q]);
+            bO.st(2 * KS + q, off, Vn[q]);
+            bV.st(0 * KS + q, off, un[q]);
+            bV.st(1 * KS + q, off, vn[q]);
             chk += xn[q] + Un[q] + Vn[q] + un[q] + vn[q];
         }
         const double Hmean = SQRT2 * double(xn[0]) + (G.h[0] + G.h[1] + G.h[2]) * (1.0 / 3.0);
@@ -629,7 +740,7 @@ __global__ void __launch_bounds__(BLOCK) k_mass_partial(MeshView m, const Real *
     double v = 0.0;
     if (e < m.ne) {
         Geo G;
-        load_geo(m, e, G);
+        load_geo(m.vtx, Buf<int>(m.ev, 3, m.stride), (unsigned)e * 4u, G);
         v = double(C[e]) * G.det * (1.0 / SQRT2);
     }
     red[threadIdx.x] = v;
