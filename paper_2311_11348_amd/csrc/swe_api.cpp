@@ -11,6 +11,7 @@
 #include "swe_tables.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -331,7 +332,12 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t nv, const double *vxy, int64_t ne, c
 {
     if (!c) return SWE_EINVAL;
     if (nv < 3 || ne < 1 || !vxy || !tri) return fail(c, SWE_EINVAL, "empty mesh");
-    if (ne > (int64_t)1 << 26) return fail(c, SWE_EINVAL, "mesh too large for 32-bit indexing");
+    {
+        // element arrays are addressed with 32-bit byte offsets (buffer resources)
+        const int64_t S = (ne + BLOCK - 1) / BLOCK * BLOCK;
+        if ((int64_t)3 * c->K * S * (int64_t)c->rsz > (int64_t)INT32_MAX)
+            return fail(c, SWE_EUNSUPPORTED, "mesh too large: a coefficient array would exceed 2 GiB");
+    }
     HIP_TRY(c, hipStreamSynchronize(c->s_base));
     HIP_TRY(c, hipStreamSynchronize(c->s_corr));
     free_mesh(c);
