@@ -55,6 +55,14 @@ struct swe_ctx {
     void *d_L = nullptr, *d_src = nullptr;
     int *d_flag = nullptr;
     double *d_part = nullptr, *d_mass = nullptr;
+    // order-separated scheme: elements with a correction, grouped by order
+    unsigned char *d_inlist = nullptr;
+    void *d_Lb = nullptr, *d_Lc = nullptr;
+    int *d_list = nullptr, *d_cnt = nullptr;
+    int list_off[5] = {0, 0, 0, 0, 0};
+    int list_cnt[4] = {0, 0, 0, 0};
+    std::vector<int> nb_host;             // [3][stride] neighbour ids / boundary codes
+    hipEvent_t ev_ready = nullptr, ev_corr = nullptr;
     hipStream_t s_base = nullptr, s_corr = nullptr;
     bool own_base = false, own_corr = false;
     double t = 0.0;
@@ -83,13 +91,15 @@ swe_status fail(swe_ctx *c, swe_status s, const std::string &msg)
 void free_mesh(swe_ctx *c)
 {
     void *ptrs[] = {c->d_vtx, c->d_ev, c->d_nb, c->d_nbk, c->d_p, c->d_C[0], c->d_C[1],
-                    c->d_U[0], c->d_U[1], c->d_L, c->d_src, c->d_flag, c->d_part, c->d_mass};
+                    c->d_U[0], c->d_U[1], c->d_L, c->d_src, c->d_flag, c->d_part, c->d_mass,
+                    c->d_inlist, c->d_Lb, c->d_Lc, c->d_list, c->d_cnt};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     c->d_vtx = nullptr; c->d_ev = nullptr; c->d_nb = nullptr; c->d_nbk = nullptr; c->d_p = nullptr;
     c->d_C[0] = c->d_C[1] = c->d_U[0] = c->d_U[1] = nullptr;
     c->d_L = c->d_src = nullptr;
     c->d_flag = nullptr; c->d_part = nullptr; c->d_mass = nullptr;
+    c->d_inlist = nullptr; c->d_Lb = nullptr; c->d_Lc = nullptr; c->d_list = nullptr; c->d_cnt = nullptr;
     c->have_mesh = false;
 }
 
@@ -154,7 +164,88 @@ hipError_t enqueue_stage(swe_ctx *c, int mode, int in, int out, double tstage, d
     a.Lout = static_cast<Real *>(Lout);
     a.xihat = xi_hat(c, tstage);
     a.dt = dt;
-    return launch_stage(c->cfg.p_max, c->fp32, mode, &a, c->s_base);
+    return launch_stage(c->cfg.p_max, c->fp32, mode, false, &a, c->s_base);
+}
+
+bool separated(const swe_ctx *c) { return c->cfg.separate && c->cfg.p_base < c->cfg.p_max; }
+
+// Order-separated stage: base kernel over all elements (stream A) while the
+// corrections of the listed elements run on stream B; the epilogue of the
+// listed elements joins both on stream A.
+template <typename Real>
+hipError_t enqueue_separated(swe_ctx *c, int mode, int in, int out, double tstage, double dt)
+{
+    const int b = c->cfg.p_base, pm = c->cfg.p_max;
+    StageArgs<Real> a = make_args<Real>(c);
+    a.mixed = 0;
+    a.Cin = static_cast<const Real *>(c->d_C[in]);
+    a.Uin = static_cast<const Real *>(c->d_U[in]);
+    a.Cn = static_cast<const Real *>(c->d_C[0]);
+    a.Cout = static_cast<Real *>(c->d_C[out]);
+    a.Uout = static_cast<Real *>(c->d_U[out]);
+    a.xihat = xi_hat(c, tstage);
+    a.dt = dt;
+    a.inlist = c->d_inlist;
+    a.Lb = static_cast<Real *>(c->d_Lb);
+    a.Lc = static_cast<Real *>(c->d_Lc);
+    hipError_t e = hipEventRecord(c->ev_ready, c->s_base);
+    if (e != hipSuccess) return e;
+    e = launch_stage(b, c->fp32, mode, true, &a, c->s_base);
+    if (e != hipSuccess) return e;
+    e = hipStreamWaitEvent(c->s_corr, c->ev_ready, 0);
+    if (e != hipSuccess) return e;
+    for (int p = b; p <= pm; ++p) {
+        if (c->list_cnt[p] == 0) continue;
+        a.list = c->d_list + c->list_off[p];
+        a.count = c->d_cnt + p;
+        e = launch_corr(p, b, pm, c->fp32, &a, dt, (c->list_cnt[p] + BLOCK - 1) / BLOCK, c->s_corr);
+        if (e != hipSuccess) return e;
+    }
+    e = hipEventRecord(c->ev_corr, c->s_corr);
+    if (e != hipSuccess) return e;
+    e = hipStreamWaitEvent(c->s_base, c->ev_corr, 0);
+    if (e != hipSuccess) return e;
+    for (int p = b; p <= pm; ++p) {
+        if (c->list_cnt[p] == 0) continue;
+        a.list = c->d_list + c->list_off[p];
+        a.count = c->d_cnt + p;
+        e = launch_epi(p, b, c->fp32, mode, &a, (c->list_cnt[p] + BLOCK - 1) / BLOCK, c->s_base);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Elements whose right-hand side has a correction: order above p_base, or a
+// neighbour above p_base.  Lists are grouped by order, ascending element index.
+swe_status build_lists(swe_ctx *c)
+{
+    if (!separated(c)) return SWE_OK;
+    const int b = c->cfg.p_base, S = c->stride;
+    std::vector<unsigned char> in(S, 0);
+    std::vector<std::vector<int>> L(4);
+    for (int64_t i = 0; i < c->ne; ++i) {
+        bool listed = c->p[i] > b;
+        for (int k = 0; k < 3 && !listed; ++k) {
+            const int nb = c->nb_host[(size_t)k * S + i];
+            if (nb >= 0 && c->p[nb] > b) listed = true;
+        }
+        if (listed) {
+            in[i] = 1;
+            L[c->p[i]].push_back((int)i);
+        }
+    }
+    std::vector<int> flat;
+    for (int p = 0; p < 4; ++p) {
+        c->list_off[p] = (int)flat.size();
+        c->list_cnt[p] = (int)L[p].size();
+        flat.insert(flat.end(), L[p].begin(), L[p].end());
+    }
+    c->list_off[4] = (int)flat.size();
+    if (flat.empty()) flat.push_back(0);
+    HIP_TRY(c, hipMemcpy(c->d_inlist, in.data(), S, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_list, flat.data(), sizeof(int) * flat.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_cnt, c->list_cnt, sizeof(int) * 4, hipMemcpyHostToDevice));
+    return SWE_OK;
 }
 
 template <typename Real>
@@ -239,6 +330,28 @@ swe_status upload_order(swe_ctx *c)
     return SWE_OK;
 }
 
+template <typename Real>
+hipError_t enqueue_rhs_split(swe_ctx *c, double t)
+{
+    const int b = c->cfg.p_base, pm = c->cfg.p_max;
+    StageArgs<Real> a = make_args<Real>(c);
+    a.mixed = 0;
+    a.Cin = static_cast<const Real *>(c->d_C[1]);
+    a.Uin = static_cast<const Real *>(c->d_U[1]);
+    a.Lout = static_cast<Real *>(c->d_L);
+    a.Lc = static_cast<Real *>(c->d_Lc);
+    a.xihat = xi_hat(c, t);
+    a.dt = 0.0;
+    hipError_t e = launch_stage(b, c->fp32, MODE_RHS, false, &a, c->s_base);
+    for (int p = b; p <= pm && e == hipSuccess; ++p) {
+        if (c->list_cnt[p] == 0) continue;
+        a.list = c->d_list + c->list_off[p];
+        a.count = c->d_cnt + p;
+        e = launch_corr(p, b, pm, c->fp32, &a, 1.0, (c->list_cnt[p] + BLOCK - 1) / BLOCK, c->s_base);
+    }
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -290,6 +403,13 @@ swe_status swe_create(const swe_config *cfg, swe_ctx **out)
         }
         c->own_corr = true;
     }
+    if (hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_corr, hipEventDisableTiming) != hipSuccess) {
+        if (c->own_base) (void)hipStreamDestroy(c->s_base);
+        if (c->own_corr) (void)hipStreamDestroy(c->s_corr);
+        delete c;
+        return SWE_EDEVICE;
+    }
     *out = c;
     return SWE_OK;
 }
@@ -300,6 +420,8 @@ void swe_destroy(swe_ctx *c)
     if (c->s_base) (void)hipStreamSynchronize(c->s_base);
     if (c->s_corr) (void)hipStreamSynchronize(c->s_corr);
     free_mesh(c);
+    if (c->ev_ready) (void)hipEventDestroy(c->ev_ready);
+    if (c->ev_corr) (void)hipEventDestroy(c->ev_corr);
     if (c->own_base) (void)hipStreamDestroy(c->s_base);
     if (c->own_corr) (void)hipStreamDestroy(c->s_corr);
     delete c;
@@ -461,8 +583,19 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t nv, const double *vxy, int64_t ne, c
     HIP_TRY(c, hipMemcpy(c->d_ev, c->ev.data(), sizeof(int) * 3 * S, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->d_nb, nb.data(), sizeof(int) * 3 * S, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->d_nbk, nbk.data(), S, hipMemcpyHostToDevice));
-    c->p.assign(ne, (signed char)c->cfg.p_max);
+    c->nb_host = nb;
+    if (separated(c)) {
+        const int KB = K_OF[c->cfg.p_base];
+        HIP_TRY(c, hipMalloc(&c->d_inlist, S));
+        HIP_TRY(c, hipMalloc(&c->d_Lb, w * 3 * KB * S));
+        HIP_TRY(c, hipMalloc(&c->d_Lc, w * 3 * K * S));
+        HIP_TRY(c, hipMalloc(&c->d_list, sizeof(int) * (ne + 1)));
+        HIP_TRY(c, hipMalloc(&c->d_cnt, sizeof(int) * 4));
+    }
+    c->p.assign(ne, (signed char)(separated(c) ? c->cfg.p_base : c->cfg.p_max));
     swe_status st = upload_order(c);
+    if (st) return st;
+    st = build_lists(c);
     if (st) return st;
     st = upload_vertices(c);
     if (st) return st;
@@ -505,6 +638,8 @@ swe_status swe_set_order(swe_ctx *c, const int8_t *p)
     for (int64_t i = 0; i < c->ne; ++i) c->p[i] = p[c->e_perm[i]];
     st = upload_order(c);
     if (st) return st;
+    st = build_lists(c);
+    if (st) return st;
     return swe_set_state(c, t, coef.data());
 }
 
@@ -538,6 +673,9 @@ swe_status swe_set_state(swe_ctx *c, double t0, const double *coef)
     HIP_TRY(c, hipStreamSynchronize(c->s_corr));
     swe_status st = upload_state(c, coef, c->d_C[0]);
     if (st) return st;
+    // modes above each element's order are zero in every state buffer
+    HIP_TRY(c, hipMemset(c->d_C[1], 0, c->rsz * 3 * c->K * c->stride));
+    HIP_TRY(c, hipMemset(c->d_U[1], 0, c->rsz * 2 * c->K * c->stride));
     HIP_TRY(c, hipMemset(c->d_flag, 0, sizeof(int)));
     HIP_TRY(c, usolve_buf(c, 0));
     HIP_TRY(c, hipStreamSynchronize(c->s_base));
@@ -608,7 +746,15 @@ swe_status swe_step(swe_ctx *c, int64_t nsteps, double dt)
     for (int64_t s = 0; s < nsteps; ++s) {
         const double tn = t0 + (double)s * dt;
         hipError_t e;
-        if (c->fp32) {
+        if (separated(c)) {
+            if (c->fp32) {
+                e = enqueue_separated<float>(c, MODE_STAGE1, 0, 1, tn, dt);
+                if (e == hipSuccess) e = enqueue_separated<float>(c, MODE_STAGE2, 1, 0, tn + dt, dt);
+            } else {
+                e = enqueue_separated<double>(c, MODE_STAGE1, 0, 1, tn, dt);
+                if (e == hipSuccess) e = enqueue_separated<double>(c, MODE_STAGE2, 1, 0, tn + dt, dt);
+            }
+        } else if (c->fp32) {
             e = enqueue_stage<float>(c, MODE_STAGE1, 0, 1, tn, dt, nullptr, nullptr);
             if (e == hipSuccess) e = enqueue_stage<float>(c, MODE_STAGE2, 1, 0, tn + dt, dt, c->d_C[0], nullptr);
         } else {
@@ -687,8 +833,22 @@ swe_status swe_usolve(swe_ctx *c, const double *coef, double *u_out)
 
 swe_status swe_rhs_split(swe_ctx *c, double t, const double *coef, double *base_out, double *corr_out)
 {
-    (void)t; (void)coef; (void)base_out; (void)corr_out;
-    return fail(c, SWE_EUNSUPPORTED, "order-separated evaluation not built yet");
+    if (!c || !coef || !base_out || !corr_out) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    if (!separated(c)) return fail(c, SWE_EINVAL, "context is not order-separated (separate = 1, p_base < p_max)");
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    HIP_TRY(c, hipStreamSynchronize(c->s_corr));
+    swe_status st = upload_state(c, coef, c->d_C[1]);
+    if (st) return st;
+    HIP_TRY(c, usolve_buf(c, 1));
+    HIP_TRY(c, hipMemsetAsync(c->d_L, 0, c->rsz * 3 * c->K * c->stride, c->s_base));
+    HIP_TRY(c, hipMemsetAsync(c->d_Lc, 0, c->rsz * 3 * c->K * c->stride, c->s_base));
+    hipError_t e = c->fp32 ? enqueue_rhs_split<float>(c, t) : enqueue_rhs_split<double>(c, t);
+    if (e != hipSuccess) return fail(c, SWE_EDEVICE, std::string("split rhs launch: ") + hipGetErrorString(e));
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    st = download(c, c->d_L, 3, base_out, true);
+    if (st) return st;
+    return download(c, c->d_Lc, 3, corr_out, true);
 }
 
 swe_status swe_indicator(swe_ctx *c, double t, const double *coef, double *I_out)

@@ -55,10 +55,18 @@ struct StageArgs {
     double dt;
     int *flag;           // set to 1 on a non-finite value or non-positive mean depth
     int mixed;           // element orders differ: mask modes above K(p_e)
+    // order-separated scheme
+    const unsigned char *inlist;   // [stride] 1 if the element has a correction
+    Real *Lb;            // [3][K(p_base)][stride] base partial stage values of listed elements
+    Real *Lc;            // [3][KS][stride] dt * correction of listed elements
+    const int *list;     // listed elements of one order
+    const int *count;    // device-side length of list
 };
 
 // Launchers (defined in swe_kernels.hip).  Return hipSuccess or the launch error.
-hipError_t launch_stage(int p, bool fp32, int mode, const void *args, hipStream_t s);
+hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, hipStream_t s);
+hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, hipStream_t s);
+hipError_t launch_epi(int p, int b, bool fp32, int mode, const void *args, int grid, hipStream_t s);
 hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s);
 hipError_t launch_mass(const MeshView &m, bool fp32, const void *C, double *partial,
                        double *out, hipStream_t s);

@@ -356,14 +356,20 @@ __device__ __forceinline__ T prod1(int c, const T (&f)[NT], const T (&g)[NT])
     return acc;
 }
 
-template <int P, typename Real>
+// Edge terms of one element of order P whose neighbours have order <= PN
+// (their stored modes above their own order are zero).  Both traces are
+// expanded to NX = max(P, PN) + 1 Legendre modes; the flux is projected onto
+// the own test space (modes <= P).
+template <int P, int PN, typename Real>
 __device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const Buf<Real> &bC, const Buf<Real> &bU,
                                            const Buf<int> &bNb,
                                            const Fields<P, Real> &s, const Geo &G, double g,
-                                           double xihat, double dt, const Real (*sR)[Ord<P>::K][Ord<P>::NT],
+                                           double xihat, double dt,
+                                           const Real (*sR)[Ord<PN>::K][(P > PN ? P : PN) + 1],
                                            Acc<P, Real> &A)
 {
-    constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
+    constexpr int K = Ord<P>::K, NT = Ord<P>::NT, KN = Ord<PN>::K;
+    constexpr int NX = (P > PN ? P : PN) + 1;
     const int KS = m.KS;
     const unsigned nbk_all = m.enbk[e];
     const Real xbm = Real(SQRT2) * s.xi[0];
@@ -381,36 +387,43 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const 
         const double hmid = 0.5 * (G.h[ka] + G.h[kb]);
         const double hbt[2] = {hmid, (G.h[kb] - G.h[ka]) * INV_2SQRT3};
 
-        Real txm[NT], tUm[NT], tVm[NT], unm[NT], qnm[NT];
+        Real txm[NX], tUm[NX], tVm[NX], unm[NX], qnm[NX];
         {
-            Real tum[NT], tvm[NT];
-            trace_own<P, Real>(k, s.xi, txm);
-            trace_own<P, Real>(k, s.U, tUm);
-            trace_own<P, Real>(k, s.V, tVm);
-            trace_own<P, Real>(k, s.u, tum);
-            trace_own<P, Real>(k, s.v, tvm);
+            Real tx[NT], tU[NT], tV[NT], tu[NT], tv[NT];
+            trace_own<P, Real>(k, s.xi, tx);
+            trace_own<P, Real>(k, s.U, tU);
+            trace_own<P, Real>(k, s.V, tV);
+            trace_own<P, Real>(k, s.u, tu);
+            trace_own<P, Real>(k, s.v, tv);
 #pragma unroll
             for (int a = 0; a < NT; ++a) {
-                unm[a] = fma(tum[a], nx, tvm[a] * ny);
-                qnm[a] = fma(tUm[a], nx, tVm[a] * ny);
+                txm[a] = tx[a];
+                tUm[a] = tU[a];
+                tVm[a] = tV[a];
+                unm[a] = fma(tu[a], nx, tv[a] * ny);
+                qnm[a] = fma(tU[a], nx, tV[a] * ny);
+            }
+#pragma unroll
+            for (int a = NT; a < NX; ++a) {
+                txm[a] = 0; tUm[a] = 0; tVm[a] = 0; unm[a] = 0; qnm[a] = 0;
             }
         }
 
         const int nb = bNb.ld(k, e * 4u);
-        Real txp[NT], tUp[NT], tVp[NT], unp[NT], qnp[NT];
+        Real txp[NX], tUp[NX], tVp[NX], unp[NX], qnp[NX];
         Real xbp, unbp;
         const Real unbm = fabs(fma(ubm, nx, vbm * ny));
         if (nb >= 0) {
             const int kk = (nbk_all >> (2 * k)) & 3;
-            Real tup[NT], tvp[NT];
+            Real tup[NX], tvp[NX];
 #pragma unroll
-            for (int a = 0; a < NT; ++a) {
+            for (int a = 0; a < NX; ++a) {
                 txp[a] = 0; tUp[a] = 0; tVp[a] = 0; tup[a] = 0; tvp[a] = 0;
             }
             const unsigned un_ = (unsigned)nb * (unsigned)sizeof(Real);
             Real x0 = 0, u0 = 0, v0 = 0;
 #pragma unroll
-            for (int n = 0; n < K; ++n) {
+            for (int n = 0; n < KN; ++n) {
                 const Real fx = bC.ld(0 * KS + n, un_);
                 const Real fU = bC.ld(1 * KS + n, un_);
                 const Real fV = bC.ld(2 * KS + n, un_);
@@ -419,7 +432,7 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const 
                 if (n == 0) { x0 = fx; u0 = fu; v0 = fv; }
                 // the trace of a degree-d basis function has no Legendre mode above d
 #pragma unroll
-                for (int a = 0; a < NT && a <= TDEG[n]; ++a) {
+                for (int a = 0; a < NX && a <= TDEG[n]; ++a) {
                     const Real r = sR[kk][n][a];
                     txp[a] = fma(fx, r, txp[a]);
                     tUp[a] = fma(fU, r, tUp[a]);
@@ -430,11 +443,11 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const 
             }
             // the neighbour runs along the edge in the opposite direction
 #pragma unroll
-            for (int a = 1; a < NT; a += 2) {
+            for (int a = 1; a < NX; a += 2) {
                 txp[a] = -txp[a]; tUp[a] = -tUp[a]; tVp[a] = -tVp[a]; tup[a] = -tup[a]; tvp[a] = -tvp[a];
             }
 #pragma unroll
-            for (int a = 0; a < NT; ++a) {
+            for (int a = 0; a < NX; ++a) {
                 unp[a] = fma(tup[a], nx, tvp[a] * ny);
                 qnp[a] = fma(tUp[a], nx, tVp[a] * ny);
             }
@@ -443,7 +456,7 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const 
         } else if (nb == NB_LAND) {
             // mirror: xi+ = xi-, normal parts of q and u change sign
 #pragma unroll
-            for (int a = 0; a < NT; ++a) {
+            for (int a = 0; a < NX; ++a) {
                 txp[a] = txm[a];
                 unp[a] = -unm[a];
                 qnp[a] = -qnm[a];
@@ -455,7 +468,7 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const 
         } else {
             // open sea: xi+ = xi_hat(t), q and u copied
 #pragma unroll
-            for (int a = 0; a < NT; ++a) {
+            for (int a = 0; a < NX; ++a) {
                 txp[a] = a == 0 ? Real(xihat) : Real(0);
                 tUp[a] = tUm[a];
                 tVp[a] = tVm[a];
@@ -475,14 +488,14 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const 
         const Real hg = Real(0.5 * g);
         Real FX[NT], FU[NT], FV[NT];
         double FW[NT];
-        double xs[NT];
+        double xs[NX];
 #pragma unroll
-        for (int a = 0; a < NT; ++a) xs[a] = double(txm[a]) + double(txp[a]);
+        for (int a = 0; a < NX; ++a) xs[a] = double(txm[a]) + double(txp[a]);
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
-            const Real pb = hg * (prod1<NT, Real>(c, txm, txm) + prod1<NT, Real>(c, txp, txp));
-            const Real mU = prod1<NT, Real>(c, tUm, unm) + prod1<NT, Real>(c, tUp, unp);
-            const Real mV = prod1<NT, Real>(c, tVm, unm) + prod1<NT, Real>(c, tVp, unp);
+            const Real pb = hg * (prod1<NX, Real>(c, txm, txm) + prod1<NX, Real>(c, txp, txp));
+            const Real mU = prod1<NX, Real>(c, tUm, unm) + prod1<NX, Real>(c, tUp, unp);
+            const Real mV = prod1<NX, Real>(c, tVm, unm) + prod1<NX, Real>(c, tVp, unp);
             Real fx = Real(0.5) * (qnm[c] + qnp[c] + lam * (txm[c] - txp[c]));
             if (nb == NB_LAND) fx = 0;   // q.n = 0: no mass flux through land
             FX[c] = sc * fx;
@@ -491,9 +504,9 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const 
             // bathymetry part of the pressure, (P- + P+)/2 = g (xi- + xi+) h_b / 2
             double w = 0.0;
 #pragma unroll
-            for (int a = 0; a < NT; ++a)
+            for (int a = 0; a < NX; ++a)
 #pragma unroll
-                for (int b = 0; b < 2 && b < NT; ++b)
+                for (int b = 0; b < 2 && b < NX; ++b)
                     if (TG[c][a][b] != 0.0) w = fma(TG[c][a][b] * hbt[b], xs[a], w);
             FW[c] = 0.5 * g * w * scale;
         }
@@ -605,17 +618,107 @@ __device__ __forceinline__ void hb_modes(const Geo &G, double (&hbh)[3])
     for (int n = 0; n < 3; ++n) hbh[n] = TW[n][0] * G.h[0] + TW[n][1] * G.h[1] + TW[n][2] * G.h[2];
 }
 
-// ------------------------------------------------------------ kernels
+// ------------------------------------------------------------ kernel pieces
+template <int KN, int NX, typename Real>
+__device__ __forceinline__ void load_trace_table(Real (*sR)[KN][NX])
+{
+    for (int i = threadIdx.x; i < 3 * KN * NX; i += BLOCK) {
+        const int k = i / (KN * NX), r = i % (KN * NX);
+        sR[k][r / NX][r % NX] = (r % NX) < 4 ? Real(TR[k][r / NX][r % NX]) : Real(0);
+    }
+}
+
+template <int P, typename Real>
+__device__ __forceinline__ void acc_init(Acc<P, Real> &A, const Fields<P, Real> &s, bool with_state)
+{
+#pragma unroll
+    for (int q = 0; q < Ord<P>::K; ++q) {
+        A.L[0][q] = with_state ? s.xi[q] : Real(0);
+        A.L[1][q] = with_state ? s.U[q] : Real(0);
+        A.L[2][q] = with_state ? s.V[q] : Real(0);
+        if constexpr (Acc<P, Real>::SPLIT) { A.W[0][q] = 0.0; A.W[1][q] = 0.0; }
+    }
+}
+
+// acc += dt L(c) for one element of order P with neighbours of order <= PN
+template <int P, int PN, typename Real>
+__device__ __forceinline__ void element_rhs(const StageArgs<Real> &a, unsigned e, const Buf<Real> &bC,
+                                            const Buf<Real> &bU, const Buf<int> &bNb,
+                                            const Fields<P, Real> &s, const Geo &G, const double (&hbh)[3],
+                                            double dt, const Real (*sR)[Ord<PN>::K][(P > PN ? P : PN) + 1],
+                                            Acc<P, Real> &A)
+{
+    constexpr int K = Ord<P>::K;
+    volume_term<P, Real>(s, hbh, G, a.ph.g, dt, A);
+    source_term<P, Real>(s, G, a.ph, dt, A);
+    edge_terms<P, PN, Real>(a.m, e, bC, bU, bNb, s, G, a.ph.g, a.xihat, dt, sR, A);
+    if constexpr (Acc<P, Real>::SPLIT) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            A.L[1][q] += Real(A.W[0][q]);
+            A.L[2][q] += Real(A.W[1][q]);
+        }
+    }
+    if (a.src) {
+        const Buf<Real> bS(a.src, 3 * a.m.KS, a.m.stride);
+        const Real rdt = Real(dt);
+        const unsigned off = e * (unsigned)sizeof(Real);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int q = 0; q < K; ++q) A.L[j][q] = fma(rdt, bS.ld(j * a.m.KS + q, off), A.L[j][q]);
+    }
+}
+
+// SSP-RK2 combine of acc = c + dt L, u-solve of the new state, store, depth check
 template <int P, typename Real, int MODE>
+__device__ __forceinline__ void finish_stage(const StageArgs<Real> &a, unsigned e, const Geo &G,
+                                             const double (&hbh)[3], int Ke, const Real (&L)[3][Ord<P>::K])
+{
+    constexpr int K = Ord<P>::K;
+    const int KS = a.m.KS, stride = a.m.stride;
+    const unsigned off = e * (unsigned)sizeof(Real);
+    Real xn[K], Un[K], Vn[K];
+    const Buf<Real> bN(a.Cn, 3 * KS, stride);
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        Real c0 = L[0][q], c1 = L[1][q], c2 = L[2][q];
+        if constexpr (MODE == MODE_STAGE2) {
+            c0 = Real(0.5) * bN.ld(0 * KS + q, off) + Real(0.5) * c0;
+            c1 = Real(0.5) * bN.ld(1 * KS + q, off) + Real(0.5) * c1;
+            c2 = Real(0.5) * bN.ld(2 * KS + q, off) + Real(0.5) * c2;
+        }
+        xn[q] = c0; Un[q] = c1; Vn[q] = c2;
+    }
+    Real un[K], vn[K];
+    solve_u<P, Real>(xn, Un, Vn, hbh, Ke, un, vn);
+    Real chk = 0;
+    const Buf<Real> bO(a.Cout, 3 * KS, stride), bV(a.Uout, 2 * KS, stride);
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        bO.st(0 * KS + q, off, xn[q]);
+        bO.st(1 * KS + q, off, Un[q]);
+        bO.st(2 * KS + q, off, Vn[q]);
+        bV.st(0 * KS + q, off, un[q]);
+        bV.st(1 * KS + q, off, vn[q]);
+        chk += xn[q] + Un[q] + Vn[q] + un[q] + vn[q];
+    }
+    const double Hmean = SQRT2 * double(xn[0]) + (G.h[0] + G.h[1] + G.h[2]) * (1.0 / 3.0);
+    if (!(Hmean > 0.0) || !isfinite(chk)) a.flag[0] = 1;
+}
+
+// ------------------------------------------------------------ kernels
+// Full stage of every element at one order P (unseparated scheme), or, with
+// SEP, the base part of the order-separated scheme: every element evaluated
+// with its first K(P) modes (P = p_base); elements whose right-hand side also
+// has a correction store their partial stage value in Lb for the epilogue.
+template <int P, typename Real, int MODE, bool SEP>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_target<P, Real>(), 8)))
 k_stage(StageArgs<Real> a)
 {
     constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
     __shared__ Real sR[3][K][NT];
-    for (int i = threadIdx.x; i < 3 * K * NT; i += BLOCK) {
-        const int k = i / (K * NT), r = i % (K * NT);
-        sR[k][r / NT][r % NT] = Real(TR[k][r / NT][r % NT]);
-    }
+    load_trace_table<K, NT, Real>(sR);
     __syncthreads();
     const unsigned e = (unsigned)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     const MeshView &m = a.m;
@@ -630,75 +733,128 @@ k_stage(StageArgs<Real> a)
     hb_modes(G, hbh);
     Fields<P, Real> s;
     load_state<P, Real>(bC, bU, KS, off, s);
-    const int Ke = a.mixed ? KOFP[m.ep[e]] : K;
+    const int Ke = (!SEP && a.mixed) ? KOFP[m.ep[e]] : K;
 
     const double dt = MODE == MODE_RHS ? 1.0 : a.dt;
     Acc<P, Real> A;
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        A.L[0][q] = MODE == MODE_RHS ? Real(0) : s.xi[q];
-        A.L[1][q] = MODE == MODE_RHS ? Real(0) : s.U[q];
-        A.L[2][q] = MODE == MODE_RHS ? Real(0) : s.V[q];
-        if constexpr (Acc<P, Real>::SPLIT) { A.W[0][q] = 0.0; A.W[1][q] = 0.0; }
-    }
-    volume_term<P, Real>(s, hbh, G, a.ph.g, dt, A);
-    source_term<P, Real>(s, G, a.ph, dt, A);
-    edge_terms<P, Real>(m, e, bC, bU, bNb, s, G, a.ph.g, a.xihat, dt, sR, A);
-    if constexpr (Acc<P, Real>::SPLIT) {
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-            A.L[1][q] += Real(A.W[0][q]);
-            A.L[2][q] += Real(A.W[1][q]);
-        }
-    }
-    if (a.src) {
-        const Buf<Real> bS(a.src, 3 * KS, stride);
-        const Real rdt = Real(dt);
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int q = 0; q < K; ++q) A.L[j][q] = fma(rdt, bS.ld(j * KS + q, off), A.L[j][q]);
-    }
-    if (a.mixed) {
+    acc_init<P, Real>(A, s, MODE != MODE_RHS);
+    element_rhs<P, P, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A);
+    if (!SEP && a.mixed) {
         // modes above the element's order stay zero
 #pragma unroll
         for (int q = 0; q < K; ++q)
             if (q >= Ke) { A.L[0][q] = 0; A.L[1][q] = 0; A.L[2][q] = 0; }
     }
     if constexpr (MODE == MODE_RHS) {
+        const Buf<Real> bL(a.Lout, 3 * KS, stride);
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int q = 0; q < K; ++q) Buf<Real>(a.Lout, 3 * KS, stride).st(j * KS + q, off, A.L[j][q]);
+            for (int q = 0; q < K; ++q) bL.st(j * KS + q, off, A.L[j][q]);
         return;
     } else {
-        Real xn[K], Un[K], Vn[K];
-        const Buf<Real> bN(a.Cn, 3 * KS, stride);
+        if constexpr (SEP) {
+            if (a.inlist[e]) {
+                const Buf<Real> bB(a.Lb, 3 * K, stride);
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
-            Real c0 = A.L[0][q], c1 = A.L[1][q], c2 = A.L[2][q];
-            if constexpr (MODE == MODE_STAGE2) {
-                c0 = Real(0.5) * bN.ld(0 * KS + q, off) + Real(0.5) * c0;
-                c1 = Real(0.5) * bN.ld(1 * KS + q, off) + Real(0.5) * c1;
-                c2 = Real(0.5) * bN.ld(2 * KS + q, off) + Real(0.5) * c2;
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int q = 0; q < K; ++q) bB.st(j * K + q, off, A.L[j][q]);
+                return;
             }
-            xn[q] = c0; Un[q] = c1; Vn[q] = c2;
         }
-        Real un[K], vn[K];
-        solve_u<P, Real>(xn, Un, Vn, hbh, Ke, un, vn);
-        Real chk = 0;
-        const Buf<Real> bO(a.Cout, 3 * KS, stride), bV(a.Uout, 2 * KS, stride);
+        finish_stage<P, Real, MODE>(a, e, G, hbh, Ke, A.L);
+    }
+}
+
+// Correction of the order-separated scheme for the listed elements of order P
+// (base order B, neighbours of order <= PN): dt times the full right-hand
+// side minus its base part (rows below K(B)), and the full rows from K(B) on.
+template <int P, int B, int PN, typename Real>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
+k_corr(StageArgs<Real> a, double dt)
+{
+    constexpr int K = Ord<P>::K, KB = Ord<B>::K, NTB = Ord<B>::NT;
+    constexpr int KN = Ord<PN>::K, NX = (P > PN ? P : PN) + 1;
+    __shared__ Real sR[3][KN][NX];
+    __shared__ Real sRb[3][KB][NTB];
+    load_trace_table<KN, NX, Real>(sR);
+    load_trace_table<KB, NTB, Real>(sRb);
+    __syncthreads();
+    const MeshView &m = a.m;
+    const int KS = m.KS, stride = m.stride;
+    const int count = a.count[0];
+    const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
+    const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
+    const Buf<Real> bL(a.Lc, 3 * KS, stride);
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
+        const unsigned e = (unsigned)a.list[i];
+        const unsigned off = e * (unsigned)sizeof(Real);
+        Geo G;
+        load_geo(m.vtx, bEv, e * 4u, G);
+        double hbh[3];
+        hb_modes(G, hbh);
+        Fields<P, Real> s;
+        load_state<P, Real>(bC, bU, KS, off, s);
+        // base part first (first K(B) modes of the element and its neighbours) ...
+        Acc<P, Real> A;
+        {
+            Fields<B, Real> sb;
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
-            bO.st(0 * KS + q, off, xn[q]);
-            bO.st(1 * KS + q, off, Un[q]);
-            bO.st(2 * KS + q, off, Vn[q]);
-            bV.st(0 * KS + q, off, un[q]);
-            bV.st(1 * KS + q, off, vn[q]);
-            chk += xn[q] + Un[q] + Vn[q] + un[q] + vn[q];
+            for (int q = 0; q < KB; ++q) {
+                sb.xi[q] = s.xi[q]; sb.U[q] = s.U[q]; sb.V[q] = s.V[q]; sb.u[q] = s.u[q]; sb.v[q] = s.v[q];
+            }
+            Acc<B, Real> Ab;
+            acc_init<B, Real>(Ab, sb, false);
+            element_rhs<B, B, Real>(a, e, bC, bU, bNb, sb, G, hbh, dt, sRb, Ab);
+            // ... then the full part accumulates on top of its negation
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) A.L[j][q] = Real(0);
+                if constexpr (Acc<P, Real>::SPLIT) { A.W[0][q] = 0.0; A.W[1][q] = 0.0; }
+            }
+#pragma unroll
+            for (int q = 0; q < KB; ++q) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) A.L[j][q] = -Ab.L[j][q];
+            }
         }
-        const double Hmean = SQRT2 * double(xn[0]) + (G.h[0] + G.h[1] + G.h[2]) * (1.0 / 3.0);
-        if (!(Hmean > 0.0) || !isfinite(chk)) a.flag[0] = 1;
+        element_rhs<P, PN, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int q = 0; q < K; ++q) bL.st(j * KS + q, off, A.L[j][q]);
+    }
+}
+
+// Epilogue of the order-separated scheme for the listed elements of order P:
+// stage value = (base partial value, or c for modes >= K(B)) + correction.
+template <int P, typename Real, int MODE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
+k_epi(StageArgs<Real> a, int KB)
+{
+    constexpr int K = Ord<P>::K;
+    const MeshView &m = a.m;
+    const int KS = m.KS, stride = m.stride;
+    const int count = a.count[0];
+    const Buf<Real> bC(a.Cin, 3 * KS, stride), bL(a.Lc, 3 * KS, stride), bB(a.Lb, 3 * KB, stride);
+    const Buf<int> bEv(m.ev, 3, stride);
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
+        const unsigned e = (unsigned)a.list[i];
+        const unsigned off = e * (unsigned)sizeof(Real);
+        Geo G;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) G.h[v] = m.vtx[(unsigned)bEv.ld(v, e * 4u)].z;
+        double hbh[3];
+        hb_modes(G, hbh);
+        Real L[3][K];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int q = 0; q < K; ++q)
+                L[j][q] = (q < KB ? bB.ld(j * KB + q, off) : bC.ld(j * KS + q, off)) + bL.ld(j * KS + q, off);
+        finish_stage<P, Real, MODE>(a, e, G, hbh, K, L);
     }
 }
 
@@ -766,27 +922,85 @@ __global__ void __launch_bounds__(BLOCK) k_mass_final(const double *partial, int
     if (threadIdx.x == 0) out[0] = red[0];
 }
 
-template <int P, typename Real>
+template <int P, typename Real, bool SEP>
 hipError_t stage_p(int mode, const void *args, hipStream_t s)
 {
     const StageArgs<Real> &a = *static_cast<const StageArgs<Real> *>(args);
     if (a.m.ne <= 0) return hipSuccess;
     const dim3 grid((a.m.ne + BLOCK - 1) / BLOCK), block(BLOCK);
-    if (mode == MODE_RHS) hipLaunchKernelGGL((k_stage<P, Real, MODE_RHS>), grid, block, 0, s, a);
-    else if (mode == MODE_STAGE1) hipLaunchKernelGGL((k_stage<P, Real, MODE_STAGE1>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_stage<P, Real, MODE_STAGE2>), grid, block, 0, s, a);
+    if (mode == MODE_RHS) hipLaunchKernelGGL((k_stage<P, Real, MODE_RHS, false>), grid, block, 0, s, a);
+    else if (mode == MODE_STAGE1) hipLaunchKernelGGL((k_stage<P, Real, MODE_STAGE1, SEP>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_stage<P, Real, MODE_STAGE2, SEP>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
 template <typename Real>
-hipError_t stage_r(int p, int mode, const void *args, hipStream_t s)
+hipError_t stage_r(int p, int mode, bool sep, const void *args, hipStream_t s)
 {
-    switch (p) {
-    case 0: return stage_p<0, Real>(mode, args, s);
-    case 1: return stage_p<1, Real>(mode, args, s);
-    case 2: return stage_p<2, Real>(mode, args, s);
-    case 3: return stage_p<3, Real>(mode, args, s);
+    if (sep) {
+        switch (p) {
+        case 0: return stage_p<0, Real, true>(mode, args, s);
+        case 1: return stage_p<1, Real, true>(mode, args, s);
+        case 2: return stage_p<2, Real, true>(mode, args, s);
+        }
+        return hipErrorInvalidValue;
     }
+    switch (p) {
+    case 0: return stage_p<0, Real, false>(mode, args, s);
+    case 1: return stage_p<1, Real, false>(mode, args, s);
+    case 2: return stage_p<2, Real, false>(mode, args, s);
+    case 3: return stage_p<3, Real, false>(mode, args, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int P, int B, int PN, typename Real>
+hipError_t corr_pbn(const StageArgs<Real> &a, double dt, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_corr<P, B, PN, Real>), dim3(grid), dim3(BLOCK), 0, s, a, dt);
+    return hipGetLastError();
+}
+
+template <int B, int PN, typename Real>
+hipError_t corr_bn(int p, const StageArgs<Real> &a, double dt, int grid, hipStream_t s)
+{
+    if (p < B || p > PN) return hipErrorInvalidValue;
+    if constexpr (B <= 0 && 0 <= PN) if (p == 0) return corr_pbn<0, B, PN, Real>(a, dt, grid, s);
+    if constexpr (B <= 1 && 1 <= PN) if (p == 1) return corr_pbn<1, B, PN, Real>(a, dt, grid, s);
+    if constexpr (B <= 2 && 2 <= PN) if (p == 2) return corr_pbn<2, B, PN, Real>(a, dt, grid, s);
+    if constexpr (B <= 3 && 3 <= PN) if (p == 3) return corr_pbn<3, B, PN, Real>(a, dt, grid, s);
+    return hipErrorInvalidValue;
+}
+
+template <typename Real>
+hipError_t corr_r(int p, int b, int pn, const void *args, double dt, int grid, hipStream_t s)
+{
+    const StageArgs<Real> &a = *static_cast<const StageArgs<Real> *>(args);
+    if (b == 0 && pn == 1) return corr_bn<0, 1, Real>(p, a, dt, grid, s);
+    if (b == 0 && pn == 2) return corr_bn<0, 2, Real>(p, a, dt, grid, s);
+    if (b == 0 && pn == 3) return corr_bn<0, 3, Real>(p, a, dt, grid, s);
+    if (b == 1 && pn == 2) return corr_bn<1, 2, Real>(p, a, dt, grid, s);
+    if (b == 1 && pn == 3) return corr_bn<1, 3, Real>(p, a, dt, grid, s);
+    if (b == 2 && pn == 3) return corr_bn<2, 3, Real>(p, a, dt, grid, s);
+    return hipErrorInvalidValue;
+}
+
+template <typename Real>
+hipError_t epi_r(int p, int mode, int KB, const void *args, int grid, hipStream_t s)
+{
+    const StageArgs<Real> &a = *static_cast<const StageArgs<Real> *>(args);
+    const dim3 g(grid), b(BLOCK);
+#define SWE_EPI(PP)                                                                                  \
+    if (p == PP) {                                                                                   \
+        if (mode == MODE_STAGE1) hipLaunchKernelGGL((k_epi<PP, Real, MODE_STAGE1>), g, b, 0, s, a, KB); \
+        else hipLaunchKernelGGL((k_epi<PP, Real, MODE_STAGE2>), g, b, 0, s, a, KB);                 \
+        return hipGetLastError();                                                                    \
+    }
+    SWE_EPI(0)
+    SWE_EPI(1)
+    SWE_EPI(2)
+    SWE_EPI(3)
+#undef SWE_EPI
     return hipErrorInvalidValue;
 }
 
@@ -813,9 +1027,22 @@ hipError_t usolve_r(int p, const void *args, hipStream_t s)
 
 }  // namespace
 
-hipError_t launch_stage(int p, bool fp32, int mode, const void *args, hipStream_t s)
+hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, hipStream_t s)
 {
-    return fp32 ? stage_r<float>(p, mode, args, s) : stage_r<double>(p, mode, args, s);
+    return fp32 ? stage_r<float>(p, mode, sep, args, s) : stage_r<double>(p, mode, sep, args, s);
+}
+
+hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, hipStream_t s)
+{
+    if (grid <= 0) return hipSuccess;
+    return fp32 ? corr_r<float>(p, b, pn, args, dt, grid, s) : corr_r<double>(p, b, pn, args, dt, grid, s);
+}
+
+hipError_t launch_epi(int p, int b, bool fp32, int mode, const void *args, int grid, hipStream_t s)
+{
+    if (grid <= 0) return hipSuccess;
+    const int KB = (b + 1) * (b + 2) / 2;
+    return fp32 ? epi_r<float>(p, mode, KB, args, grid, s) : epi_r<double>(p, mode, KB, args, grid, s);
 }
 
 hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s)

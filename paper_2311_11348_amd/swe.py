@@ -264,6 +264,7 @@ def context_for(problem, precision=SWE_FP64, separate=0, stream_base=None, strea
     ctx.set_bathymetry(problem.hb_vertex)
     if problem.forcing is not None and len(problem.forcing.amp):
         ctx.set_open_boundary(problem.forcing.amp, problem.forcing.omega, problem.forcing.phase)
-    if np.any(problem.p != problem.p_max):
+    # separated contexts start at p_base, unseparated ones at p_max
+    if separate or np.any(problem.p != problem.p_max):
         ctx.set_order(problem.p)
     return ctx

@@ -36,6 +36,8 @@ def problem(n=20, p=2, seed=5, open_west=True, friction=2, fc=3.19e-5, bathy=Non
 
 
 def rel_max_err(a, b):
+    assert np.all(np.isfinite(a)), "non-finite values in the GPU result"
+    assert np.all(np.isfinite(b)), "non-finite values in the reference"
     out = 0.0
     for j in range(3):
         s = np.max(np.abs(b[:, j]))
