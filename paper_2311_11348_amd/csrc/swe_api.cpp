@@ -57,6 +57,8 @@ struct swe_ctx {
     double *d_part = nullptr, *d_mass = nullptr;
     // order-separated scheme: elements with a correction, grouped by order
     unsigned char *d_inlist = nullptr;
+    signed char *d_pnew = nullptr;
+    double *d_I = nullptr;
     void *d_Lb = nullptr, *d_Lc = nullptr;
     int *d_list = nullptr, *d_cnt = nullptr;
     int list_off[5] = {0, 0, 0, 0, 0};
@@ -92,7 +94,7 @@ void free_mesh(swe_ctx *c)
 {
     void *ptrs[] = {c->d_vtx, c->d_ev, c->d_nb, c->d_nbk, c->d_p, c->d_C[0], c->d_C[1],
                     c->d_U[0], c->d_U[1], c->d_L, c->d_src, c->d_flag, c->d_part, c->d_mass,
-                    c->d_inlist, c->d_Lb, c->d_Lc, c->d_list, c->d_cnt};
+                    c->d_inlist, c->d_Lb, c->d_Lc, c->d_list, c->d_cnt, c->d_pnew, c->d_I};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     c->d_vtx = nullptr; c->d_ev = nullptr; c->d_nb = nullptr; c->d_nbk = nullptr; c->d_p = nullptr;
@@ -100,6 +102,7 @@ void free_mesh(swe_ctx *c)
     c->d_L = c->d_src = nullptr;
     c->d_flag = nullptr; c->d_part = nullptr; c->d_mass = nullptr;
     c->d_inlist = nullptr; c->d_Lb = nullptr; c->d_Lc = nullptr; c->d_list = nullptr; c->d_cnt = nullptr;
+    c->d_pnew = nullptr; c->d_I = nullptr;
     c->have_mesh = false;
 }
 
@@ -169,6 +172,35 @@ hipError_t enqueue_stage(swe_ctx *c, int mode, int in, int out, double tstage, d
 
 bool separated(const swe_ctx *c) { return c->cfg.separate && c->cfg.p_base < c->cfg.p_max; }
 
+// Grid of a correction/epilogue launch: exact for static lists; with
+// adaptivity the list lengths live on the device and the kernels loop over them.
+int list_grid(const swe_ctx *c, int p)
+{
+    if (c->cfg.adapt) return std::min<int>((int)((c->ne + BLOCK - 1) / BLOCK), 1024);
+    return (c->list_cnt[p] + BLOCK - 1) / BLOCK;
+}
+
+// Order adaptation at the start of a step, from the state in buffer 0.
+template <typename Real>
+hipError_t enqueue_adapt(swe_ctx *c, double tn)
+{
+    StageArgs<Real> a = make_args<Real>(c);
+    a.Cin = static_cast<const Real *>(c->d_C[0]);
+    a.xihat = xi_hat(c, tn);
+    a.cntw = c->d_cnt;
+    hipError_t e = launch_indicator(c->fp32, &a, c->cfg.adapt_tau, c->cfg.p_base, c->cfg.p_max, nullptr,
+                                    c->d_pnew, c->s_base);
+    if (e != hipSuccess) return e;
+    a.Cout = static_cast<Real *>(c->d_C[0]);
+    a.Calt = static_cast<Real *>(c->d_C[1]);
+    a.Uout = static_cast<Real *>(c->d_U[0]);
+    a.Ualt = static_cast<Real *>(c->d_U[1]);
+    a.inlist = c->d_inlist;
+    a.listw = c->d_list;
+    return launch_apply_order(c->cfg.p_max, c->fp32, &a, c->d_pnew, c->d_p, c->cfg.p_base, (int)c->ne,
+                              c->s_base);
+}
+
 // Order-separated stage: base kernel over all elements (stream A) while the
 // corrections of the listed elements run on stream B; the epilogue of the
 // listed elements joins both on stream A.
@@ -195,10 +227,10 @@ hipError_t enqueue_separated(swe_ctx *c, int mode, int in, int out, double tstag
     e = hipStreamWaitEvent(c->s_corr, c->ev_ready, 0);
     if (e != hipSuccess) return e;
     for (int p = b; p <= pm; ++p) {
-        if (c->list_cnt[p] == 0) continue;
+        if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
         a.list = c->d_list + c->list_off[p];
         a.count = c->d_cnt + p;
-        e = launch_corr(p, b, pm, c->fp32, &a, dt, (c->list_cnt[p] + BLOCK - 1) / BLOCK, c->s_corr);
+        e = launch_corr(p, b, pm, c->fp32, &a, dt, list_grid(c, p), c->s_corr);
         if (e != hipSuccess) return e;
     }
     e = hipEventRecord(c->ev_corr, c->s_corr);
@@ -206,10 +238,10 @@ hipError_t enqueue_separated(swe_ctx *c, int mode, int in, int out, double tstag
     e = hipStreamWaitEvent(c->s_base, c->ev_corr, 0);
     if (e != hipSuccess) return e;
     for (int p = b; p <= pm; ++p) {
-        if (c->list_cnt[p] == 0) continue;
+        if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
         a.list = c->d_list + c->list_off[p];
         a.count = c->d_cnt + p;
-        e = launch_epi(p, b, c->fp32, mode, &a, (c->list_cnt[p] + BLOCK - 1) / BLOCK, c->s_base);
+        e = launch_epi(p, b, c->fp32, mode, &a, list_grid(c, p), c->s_base);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -234,16 +266,14 @@ swe_status build_lists(swe_ctx *c)
             L[c->p[i]].push_back((int)i);
         }
     }
-    std::vector<int> flat;
-    for (int p = 0; p < 4; ++p) {
-        c->list_off[p] = (int)flat.size();
-        c->list_cnt[p] = (int)L[p].size();
-        flat.insert(flat.end(), L[p].begin(), L[p].end());
-    }
-    c->list_off[4] = (int)flat.size();
-    if (flat.empty()) flat.push_back(0);
+    for (int p = 0; p < 4; ++p) c->list_cnt[p] = (int)L[p].size();
     HIP_TRY(c, hipMemcpy(c->d_inlist, in.data(), S, hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->d_list, flat.data(), sizeof(int) * flat.size(), hipMemcpyHostToDevice));
+    for (int p = 0; p < 4; ++p) {
+        c->list_off[p] = p * (int)c->ne;
+        if (!L[p].empty())
+            HIP_TRY(c, hipMemcpy(c->d_list + c->list_off[p], L[p].data(), sizeof(int) * L[p].size(),
+                                 hipMemcpyHostToDevice));
+    }
     HIP_TRY(c, hipMemcpy(c->d_cnt, c->list_cnt, sizeof(int) * 4, hipMemcpyHostToDevice));
     return SWE_OK;
 }
@@ -344,10 +374,10 @@ hipError_t enqueue_rhs_split(swe_ctx *c, double t)
     a.dt = 0.0;
     hipError_t e = launch_stage(b, c->fp32, MODE_RHS, false, &a, c->s_base);
     for (int p = b; p <= pm && e == hipSuccess; ++p) {
-        if (c->list_cnt[p] == 0) continue;
+        if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
         a.list = c->d_list + c->list_off[p];
         a.count = c->d_cnt + p;
-        e = launch_corr(p, b, pm, c->fp32, &a, 1.0, (c->list_cnt[p] + BLOCK - 1) / BLOCK, c->s_base);
+        e = launch_corr(p, b, pm, c->fp32, &a, 1.0, list_grid(c, p), c->s_base);
     }
     return e;
 }
@@ -584,13 +614,17 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t nv, const double *vxy, int64_t ne, c
     HIP_TRY(c, hipMemcpy(c->d_nb, nb.data(), sizeof(int) * 3 * S, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->d_nbk, nbk.data(), S, hipMemcpyHostToDevice));
     c->nb_host = nb;
-    if (separated(c)) {
+    if (separated(c) || c->cfg.adapt) {
         const int KB = K_OF[c->cfg.p_base];
         HIP_TRY(c, hipMalloc(&c->d_inlist, S));
+        HIP_TRY(c, hipMemset(c->d_inlist, 0, S));
         HIP_TRY(c, hipMalloc(&c->d_Lb, w * 3 * KB * S));
         HIP_TRY(c, hipMalloc(&c->d_Lc, w * 3 * K * S));
-        HIP_TRY(c, hipMalloc(&c->d_list, sizeof(int) * (ne + 1)));
+        HIP_TRY(c, hipMalloc(&c->d_list, sizeof(int) * 4 * (size_t)ne));
         HIP_TRY(c, hipMalloc(&c->d_cnt, sizeof(int) * 4));
+        HIP_TRY(c, hipMemset(c->d_cnt, 0, sizeof(int) * 4));
+        HIP_TRY(c, hipMalloc(&c->d_pnew, S));
+        HIP_TRY(c, hipMalloc(&c->d_I, sizeof(double) * S));
     }
     c->p.assign(ne, (signed char)(separated(c) ? c->cfg.p_base : c->cfg.p_max));
     swe_status st = upload_order(c);
@@ -647,6 +681,11 @@ swe_status swe_get_order(swe_ctx *c, int8_t *p)
 {
     if (!c || !p) return SWE_EINVAL;
     if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    if (c->cfg.adapt) {
+        // orders change on the device every step
+        HIP_TRY(c, hipStreamSynchronize(c->s_base));
+        HIP_TRY(c, hipMemcpy(c->p.data(), c->d_p, c->ne, hipMemcpyDeviceToHost));
+    }
     for (int64_t i = 0; i < c->ne; ++i) p[c->e_perm[i]] = c->p[i];
     return SWE_OK;
 }
@@ -745,7 +784,12 @@ swe_status swe_step(swe_ctx *c, int64_t nsteps, double dt)
     const double t0 = c->t;
     for (int64_t s = 0; s < nsteps; ++s) {
         const double tn = t0 + (double)s * dt;
-        hipError_t e;
+        hipError_t e = hipSuccess;
+        if (c->cfg.adapt) {
+            e = c->fp32 ? enqueue_adapt<float>(c, tn) : enqueue_adapt<double>(c, tn);
+            if (e != hipSuccess) return fail(c, SWE_EDEVICE, std::string("adapt launch: ") + hipGetErrorString(e));
+            c->uniform = false;
+        }
         if (separated(c)) {
             if (c->fp32) {
                 e = enqueue_separated<float>(c, MODE_STAGE1, 0, 1, tn, dt);
@@ -853,8 +897,31 @@ swe_status swe_rhs_split(swe_ctx *c, double t, const double *coef, double *base_
 
 swe_status swe_indicator(swe_ctx *c, double t, const double *coef, double *I_out)
 {
-    (void)t; (void)coef; (void)I_out;
-    return fail(c, SWE_EUNSUPPORTED, "adaptivity indicator not built yet");
+    if (!c || !coef || !I_out) return SWE_EINVAL;
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    if (!c->d_I) return fail(c, SWE_EINVAL, "indicator needs a context with adapt = 1");
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    HIP_TRY(c, hipStreamSynchronize(c->s_corr));
+    swe_status st = upload_state(c, coef, c->d_C[1]);
+    if (st) return st;
+    hipError_t e;
+    if (c->fp32) {
+        StageArgs<float> a = make_args<float>(c);
+        a.Cin = static_cast<const float *>(c->d_C[1]);
+        a.xihat = xi_hat(c, t);
+        e = launch_indicator(true, &a, 1.0, 0, 0, c->d_I, nullptr, c->s_base);
+    } else {
+        StageArgs<double> a = make_args<double>(c);
+        a.Cin = static_cast<const double *>(c->d_C[1]);
+        a.xihat = xi_hat(c, t);
+        e = launch_indicator(false, &a, 1.0, 0, 0, c->d_I, nullptr, c->s_base);
+    }
+    if (e != hipSuccess) return fail(c, SWE_EDEVICE, std::string("indicator launch: ") + hipGetErrorString(e));
+    std::vector<double> h(c->ne);
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    HIP_TRY(c, hipMemcpy(h.data(), c->d_I, sizeof(double) * c->ne, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < c->ne; ++i) I_out[c->e_perm[i]] = h[i];
+    return SWE_OK;
 }
 
 }  // extern "C"

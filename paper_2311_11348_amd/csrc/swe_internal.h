@@ -56,11 +56,14 @@ struct StageArgs {
     int *flag;           // set to 1 on a non-finite value or non-positive mean depth
     int mixed;           // element orders differ: mask modes above K(p_e)
     // order-separated scheme
-    const unsigned char *inlist;   // [stride] 1 if the element has a correction
+    unsigned char *inlist;         // [stride] 1 if the element has a correction
     Real *Lb;            // [3][K(p_base)][stride] base partial stage values of listed elements
     Real *Lc;            // [3][KS][stride] dt * correction of listed elements
     const int *list;     // listed elements of one order
     const int *count;    // device-side length of list
+    int *listw;          // [4][lcap] lists being rebuilt by the order update
+    int *cntw;           // [4] their lengths
+    Real *Calt, *Ualt;   // the other state/velocity buffer (order update clears dropped modes)
 };
 
 // Launchers (defined in swe_kernels.hip).  Return hipSuccess or the launch error.
@@ -68,6 +71,10 @@ hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, 
 hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, hipStream_t s);
 hipError_t launch_epi(int p, int b, bool fp32, int mode, const void *args, int grid, hipStream_t s);
 hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s);
+hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, int p_hi, double *I_out,
+                            signed char *p_new, hipStream_t s);
+hipError_t launch_apply_order(int pm, bool fp32, const void *args, const signed char *p_new, signed char *p_cur,
+                              int p_base, int lcap, hipStream_t s);
 hipError_t launch_mass(const MeshView &m, bool fp32, const void *C, double *partial,
                        double *out, hipStream_t s);
 int mass_partials(int ne);

@@ -34,6 +34,7 @@ constexpr double TD[2][10][10] = SWET_D;
 constexpr double TR[3][10][4] = SWET_R;
 constexpr double TG[4][4][4] = SWET_G;
 constexpr double TW[3][3] = SWET_W;
+constexpr double TPMID[3][3] = SWET_PMID;
 constexpr int TDEG[10] = SWET_DEG;
 constexpr int KOFP[4] = SWET_K_OF_P;
 constexpr double SQRT2 = 1.41421356237309504880;
@@ -858,6 +859,132 @@ k_epi(StageArgs<Real> a, int KB)
     }
 }
 
+// ------------------------------------------------------------ p-adaptivity
+// Indicator (stand-in for the paper's JRL indicator, which its text only
+// cites): the largest jump of the P1 part of xi at the edge midpoints; land
+// edges contribute 0, open edges compare with xi_hat(t).  New order: p_hi if
+// I >= tau, one less for each further factor 10 below tau, never below p_lo.
+template <typename Real>
+__global__ void __launch_bounds__(BLOCK) k_indicator(StageArgs<Real> a, double tau, int p_lo, int p_hi,
+                                                     double *I_out, signed char *p_new)
+{
+    const MeshView &m = a.m;
+    const int KS = m.KS, stride = m.stride;
+    if (a.cntw && blockIdx.x == 0 && threadIdx.x < 4) a.cntw[threadIdx.x] = 0;   // list counts of the next pass
+    const unsigned e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= (unsigned)m.ne) return;
+    const Buf<Real> bC(a.Cin, 3 * KS, stride);
+    const Buf<int> bNb(m.enb, 3, stride);
+    const unsigned off = e * (unsigned)sizeof(Real);
+    const double x0 = bC.ld(0, off), x1 = bC.ld(1, off), x2 = bC.ld(2, off);
+    const unsigned nbk_all = m.enbk[e];
+    double I = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double own = TPMID[k][0] * x0 + TPMID[k][1] * x1 + TPMID[k][2] * x2;
+        const int nb = bNb.ld(k, e * 4u);
+        double other = own;
+        if (nb >= 0) {
+            const int kk = (nbk_all >> (2 * k)) & 3;
+            const unsigned on = (unsigned)nb * (unsigned)sizeof(Real);
+            const double y0 = bC.ld(0, on), y1 = bC.ld(1, on), y2 = bC.ld(2, on);
+            other = TPMID[kk][0] * y0 + TPMID[kk][1] * y1 + TPMID[kk][2] * y2;
+        } else if (nb == NB_OPEN) {
+            other = a.xihat;
+        }
+        const double j = fabs(own - other);
+        I = j > I ? j : I;
+    }
+    if (I_out) I_out[e] = I;
+    if (p_new) {
+        int pn = p_lo;
+        double thr = tau;
+        for (int pp = p_hi; pp > p_lo; --pp) {
+            if (I >= thr) { pn = pp; break; }
+            thr *= 0.1;
+        }
+        p_new[e] = (signed char)pn;
+    }
+}
+
+// Apply the new orders: drop modes above K(p_new) from every state buffer,
+// re-solve u of changed elements, flag elements that need a correction and
+// append them to the list of their order (one atomic per wave and order).
+template <int PM, typename Real>
+__global__ void __launch_bounds__(BLOCK) k_apply_order(StageArgs<Real> a, const signed char *p_new,
+                                                       signed char *p_cur, int p_base, int lcap)
+{
+    constexpr int K = Ord<PM>::K;
+    const MeshView &m = a.m;
+    const int KS = m.KS, stride = m.stride;
+    const unsigned e = blockIdx.x * BLOCK + threadIdx.x;
+    const bool live = e < (unsigned)m.ne;
+    int pn = 0;
+    bool listed = false;
+    if (live) {
+        const unsigned off = e * (unsigned)sizeof(Real);
+        pn = p_new[e];
+        const int po = p_cur[e];
+        const Buf<int> bNb(m.enb, 3, stride);
+        listed = pn > p_base;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int nb = bNb.ld(k, e * 4u);
+            if (nb >= 0 && p_new[nb] > p_base) listed = true;
+        }
+        a.inlist[e] = listed ? 1 : 0;
+        if (pn != po) {
+            const int Kn = KOFP[pn];
+            Buf<Real> b0(a.Cout, 3 * KS, stride), b1(a.Calt, 3 * KS, stride);
+            Buf<Real> u1(a.Ualt, 2 * KS, stride);
+            Real xi[K], U[K], V[K];
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const bool keep = q < Kn;
+                xi[q] = keep ? b0.ld(0 * KS + q, off) : Real(0);
+                U[q] = keep ? b0.ld(1 * KS + q, off) : Real(0);
+                V[q] = keep ? b0.ld(2 * KS + q, off) : Real(0);
+                if (!keep) {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) { b0.st(j * KS + q, off, Real(0)); b1.st(j * KS + q, off, Real(0)); }
+                    u1.st(0 * KS + q, off, Real(0));
+                    u1.st(1 * KS + q, off, Real(0));
+                }
+            }
+            Geo G;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) G.h[v] = m.vtx[(unsigned)Buf<int>(m.ev, 3, stride).ld(v, e * 4u)].z;
+            double hbh[3];
+            hb_modes(G, hbh);
+            Real u[K], v[K];
+            solve_u<PM, Real>(xi, U, V, hbh, Kn, u, v);
+            Buf<Real> bu(a.Uout, 2 * KS, stride);
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                bu.st(0 * KS + q, off, u[q]);
+                bu.st(1 * KS + q, off, v[q]);
+            }
+            p_cur[e] = (signed char)pn;
+        }
+    }
+    // wave-aggregated append to the list of order pn
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const bool mine = live && listed && pn == p;
+        const unsigned long long mask = __ballot(mine);
+        if (mask == 0ull) continue;
+        const int leader = __ffsll((long long)mask) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&a.cntw[p], __popcll(mask));
+        base = __shfl(base, leader);
+        if (mine) {
+            const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+            a.listw[p * lcap + base + rank] = (int)e;
+        }
+    }
+}
+
 template <int P, typename Real>
 __global__ void __launch_bounds__(BLOCK) k_usolve(StageArgs<Real> a)
 {
@@ -1051,6 +1178,43 @@ hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s)
 }
 
 int mass_partials(int ne) { return (ne + BLOCK - 1) / BLOCK; }
+
+hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, int p_hi, double *I_out,
+                            signed char *p_new, hipStream_t s)
+{
+    const int ne = static_cast<const StageArgs<double> *>(args)->m.ne;
+    const dim3 g((ne + BLOCK - 1) / BLOCK), b(BLOCK);
+    if (fp32)
+        hipLaunchKernelGGL(k_indicator<float>, g, b, 0, s, *static_cast<const StageArgs<float> *>(args), tau,
+                           p_lo, p_hi, I_out, p_new);
+    else
+        hipLaunchKernelGGL(k_indicator<double>, g, b, 0, s, *static_cast<const StageArgs<double> *>(args), tau,
+                           p_lo, p_hi, I_out, p_new);
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t apply_r(int pm, const void *args, const signed char *p_new, signed char *p_cur, int p_base, int lcap,
+                   hipStream_t s)
+{
+    const StageArgs<Real> &a = *static_cast<const StageArgs<Real> *>(args);
+    const dim3 g((a.m.ne + BLOCK - 1) / BLOCK), b(BLOCK);
+    switch (pm) {
+    case 0: hipLaunchKernelGGL((k_apply_order<0, Real>), g, b, 0, s, a, p_new, p_cur, p_base, lcap); break;
+    case 1: hipLaunchKernelGGL((k_apply_order<1, Real>), g, b, 0, s, a, p_new, p_cur, p_base, lcap); break;
+    case 2: hipLaunchKernelGGL((k_apply_order<2, Real>), g, b, 0, s, a, p_new, p_cur, p_base, lcap); break;
+    case 3: hipLaunchKernelGGL((k_apply_order<3, Real>), g, b, 0, s, a, p_new, p_cur, p_base, lcap); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_order(int pm, bool fp32, const void *args, const signed char *p_new, signed char *p_cur,
+                              int p_base, int lcap, hipStream_t s)
+{
+    return fp32 ? apply_r<float>(pm, args, p_new, p_cur, p_base, lcap, s)
+                : apply_r<double>(pm, args, p_new, p_cur, p_base, lcap, s);
+}
 
 hipError_t launch_mass(const MeshView &m, bool fp32, const void *C, double *partial, double *out,
                        hipStream_t s)
