@@ -1,21 +1,29 @@
 """Throughput of the DG shallow-water hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tidal|tsunami|static32]
 
-Workload (default): 512x512x2 triangulation of a 100 km square, nodes jittered
-by U(-0.2h, 0.2h) (seed 2), uniform order p = 2, bathymetry
-10 m + 3990 m (1 + sin(2 pi x/L) cos(2 pi y/L))/2, lake at rest, west edge
-open and forced by a 0.5 m tide of period 44712 s, Coriolis 3.19e-5 1/s,
-quadratic friction 0.009.  A step is one SSP-RK2 step (two stages) of the
-whole hot path: volume + source + edge fluxes + stage update + u H = q.
-Metric: DOF-updates per second per RK stage, DOF = 3 * sum_e K(p_e).
-Inputs are resident in HBM before the timed region.  Prints one JSON line.
+tidal (default): 512x512x2 triangulation of a 100 km square, nodes jittered
+  by U(-0.2h, 0.2h) (seed 2), uniform order p = 2, bathymetry
+  10 m + 3990 m (1 + sin(2 pi x/L) cos(2 pi y/L))/2, lake at rest, west edge
+  open and forced by a 0.5 m tide of period 44712 s, Coriolis 3.19e-5 1/s,
+  quadratic friction 0.009.  The headline value is the FP32 path (FP32 state
+  and bulk arithmetic, FP64 bathymetry terms); the FP64 path is measured on
+  the same workload and reported beside it.
+tsunami: 256x256x2 jittered (seed 3), linear shelf 4000 m -> 50 m, 2 m hump,
+  orders in {1,2,3} re-chosen every step by the indicator (threshold 1e-3 m),
+  base order 1 and corrections on a second stream, FP32 path.
+static32: the tidal mesh with base order 1 and every 32nd element at order 2,
+  order-separated on two streams, FP32 path.
+
+A step is one SSP-RK2 step (two stages) of the whole hot path: volume +
+source + edge fluxes + stage update + u H = q (+ order update when adaptive).
+Metric: DOF-updates per second per RK stage, DOF = 3 * sum_e K(p_e).  Inputs
+are resident in HBM before the timed region.  Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -28,12 +36,12 @@ K_OF_P = (1, 3, 6, 10)
 
 
 def stage_bytes_per_element(p: int, word: int, nv: int, ne: int) -> float:
-    """Algorithmic HBM bytes one element moves in one stage kernel (average of
-    the two SSP-RK2 stages): read c (3K) and u (2K), read c^n (3K) in the
-    second stage only, write c (3K) and u (2K); geometry: 3 vertex ids, 3
-    neighbour ids, 1 packed neighbour-edge byte, and the element's share of
-    the 32-byte vertex records.  Neighbour coefficients are counted once (as
-    their owner's read): they are served from cache."""
+    """Algorithmic HBM bytes one element moves in one fused stage kernel
+    (average of the two SSP-RK2 stages): read c (3K) and u (2K), read c^n (3K)
+    in the second stage only, write c (3K) and u (2K); geometry: 3 vertex ids,
+    3 neighbour ids, 1 packed neighbour-edge byte and the element's share of
+    the 32-byte vertex records.  Neighbour coefficients are counted once, as
+    their owner's read (they are served from cache)."""
     K = K_OF_P[p]
     state = (3 * K + 2 * K + 0.5 * 3 * K + 3 * K + 2 * K) * word
     geo = 3 * 4 + 3 * 4 + 1 + 32.0 * nv / ne
@@ -42,7 +50,7 @@ def stage_bytes_per_element(p: int, word: int, nv: int, ne: int) -> float:
 
 def cpu_baseline(p: int, budget_s: float = 15.0):
     """The FP64 oracle (single thread) on a bounded sample of the same workload:
-    the same problem family on a coarser mesh, timed over whole SSP-RK2 steps."""
+    the same problem family on a 64x64x2 mesh, timed over whole SSP-RK2 steps."""
     from oracle.oracle import Oracle
     from paper_2311_11348_amd import inputs as I
     n = 64
@@ -58,10 +66,81 @@ def cpu_baseline(p: int, budget_s: float = 15.0):
     orc.step(c, steps, dt, t0=dt)
     el = time.perf_counter() - t0
     dof = 3 * K_OF_P[p] * prob.mesh.ne
-    return {"value": dof * 2 * steps / el, "unit": "DOF-updates/s per RK stage", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{n}x{n}x2 mesh of the same workload family ({prob.mesh.ne} elements, p={p}), "
+    return {"value": dof * 2 * steps / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n}x{n}x2 mesh of the tidal workload family ({prob.mesh.ne} elements, p={p}), "
                       f"{steps} SSP-RK2 steps, FP64, single thread, {el:.1f} s"}
+
+
+def timed_steps(ctx, stream, steps, dt):
+    import torch
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    ctx.step(steps, dt)
+    ev1.record(stream)
+    ctx.sync()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1)
+
+
+def run_uniform(prob, precision, steps, warmup):
+    """Fused full-order stage kernel on a uniform-order workload."""
+    import torch
+    from paper_2311_11348_amd import swe
+    stream = torch.cuda.Stream()
+    ctx = swe.context_for(prob, precision=precision, stream_base=stream.cuda_stream)
+    ctx.set_state_fn(prob.ic)
+    dt = prob.dt()
+    ctx.step(warmup, dt)
+    ctx.sync()
+    torch.cuda.synchronize()
+    ms = timed_steps(ctx, stream, steps, dt)
+    ctx.close()
+    p = int(prob.p_max)
+    ne, nv = prob.mesh.ne, prob.mesh.nv
+    word = 8 if precision == swe.SWE_FP64 else 4
+    dof = 3 * K_OF_P[p] * ne
+    launch_s = ms * 1e-3 / (2 * steps)
+    bpe = stage_bytes_per_element(p, word, nv, ne)
+    achieved = bpe * ne / launch_s / 1e9
+    return {"value": dof / launch_s, "ms_per_step": ms / steps,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": f"k_stage<{p},{'double' if word == 8 else 'float'}>",
+                         "bytes_per_launch": bpe * ne, "avg_launch_us": launch_s * 1e6}}
+
+
+def run_separated(prob, precision, steps, warmup, chunk=50):
+    """Order-separated scheme (base + corrections on two streams), optionally adaptive.
+    DOF counts follow the order map, read between timed chunks."""
+    import numpy as np
+    import torch
+    from paper_2311_11348_amd import swe
+    stream = torch.cuda.Stream()
+    stream2 = torch.cuda.Stream()
+    ctx = swe.context_for(prob, precision=precision, separate=1, stream_base=stream.cuda_stream,
+                          stream_corr=stream2.cuda_stream)
+    ctx.set_state_fn(prob.ic)
+    dt = prob.dt()
+    ctx.step(warmup, dt)
+    ctx.sync()
+    torch.cuda.synchronize()
+    done, ms, dof_stages = 0, 0.0, 0.0
+    kdist = np.zeros(4)
+    while done < steps:
+        n = min(chunk, steps - done)
+        p = ctx.order()
+        K = np.asarray(K_OF_P)[p]
+        ms += timed_steps(ctx, stream, n, dt)
+        p2 = ctx.order()
+        K2 = np.asarray(K_OF_P)[p2]
+        dof_stages += 3 * 0.5 * (K.sum() + K2.sum()) * 2 * n
+        kdist += np.bincount(p2, minlength=4)
+        done += n
+    ctx.close()
+    frac = kdist / kdist.sum()
+    return {"value": dof_stages / (ms * 1e-3), "ms_per_step": ms / steps,
+            "order_fractions": {f"p{i}": float(frac[i]) for i in range(4) if frac[i] > 0}}
 
 
 def main() -> int:
@@ -69,14 +148,14 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--workload", choices=["tidal", "tsunami", "static32"], default="tidal")
+    ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--p", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (instances and "
-              "meshes shard without communication across GPUs, see the design notes)",
+              "meshes would shard without a collective in the time loop; see the design notes)",
               file=sys.stderr)
         return 2
 
@@ -87,60 +166,48 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    prec = swe.SWE_FP64 if args.precision == "fp64" else swe.SWE_FP32_WB
-    word = 8 if prec == swe.SWE_FP64 else 4
-    prob = I.config_c2(n=args.n, p=args.p)
-    stream = torch.cuda.Stream()
-    print(f"bench: building {prob.mesh.ne} elements, p={args.p}, {args.precision}", file=sys.stderr, flush=True)
-    ctx = swe.context_for(prob, precision=prec, stream_base=stream.cuda_stream)
-    ctx.set_state_fn(prob.ic)
-    dt = prob.dt()
-    ctx.step(args.warmup, dt)
-    ctx.sync()
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     t_wall0 = time.perf_counter()
-    ev0.record(stream)
-    ctx.step(args.steps, dt)
-    ev1.record(stream)
-    ctx.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall0
-    gpu_ms = ev0.elapsed_time(ev1)
-    ne, nv = prob.mesh.ne, prob.mesh.nv
-    dof = 3 * K_OF_P[args.p] * ne
-    stages = 2 * args.steps
-    value = dof * stages / (gpu_ms * 1e-3)
-    launch_s = gpu_ms * 1e-3 / stages
-    bpe = stage_bytes_per_element(args.p, word, nv, ne)
-    achieved = bpe * ne / launch_s / 1e9
-    out = {
-        "metric": "DOF-updates/s per RK stage",
-        "value": value,
-        "unit": "DOF-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": gpu_ms / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == swe.SWE_FP64 else "f32 (f64 bathymetry terms)",
-        "data": "synthetic",
-        "config": {"workload": f"tidal: {args.n}x{args.n}x2 jittered triangulation, {ne} elements, "
-                               f"p={args.p} uniform, sin*cos bathymetry 10-4000 m, west tide",
-                   "elements": ne, "order": args.p, "dof": dof, "precision": args.precision},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_stage (fused volume+source+edges+RK+u-solve)",
-                     "bytes_per_launch": bpe * ne, "avg_launch_us": launch_s * 1e6},
-        "wall_s": wall,
-    }
-    if not args.no_cpu_baseline:
-        print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.p)
-    ctx.close()
+    out = {"metric": "DOF-updates/s per RK stage", "unit": "DOF-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic"}
+    if args.workload == "tidal":
+        n = args.n or 512
+        prob = I.config_c2(n=n, p=args.p)
+        print(f"bench: tidal {prob.mesh.ne} elements p={args.p}", file=sys.stderr, flush=True)
+        r32 = run_uniform(prob, swe.SWE_FP32_WB, args.steps, args.warmup)
+        r64 = run_uniform(prob, swe.SWE_FP64, args.steps, args.warmup)
+        out.update(value=r32["value"], ms_per_step=r32["ms_per_step"], dtype="f32 (f64 bathymetry terms)",
+                   config={"workload": f"tidal: {n}x{n}x2 jittered triangulation, {prob.mesh.ne} elements, "
+                                       f"p={args.p} uniform, sin*cos bathymetry 10-4000 m, west tide",
+                           "elements": prob.mesh.ne, "order": args.p, "dof": 3 * K_OF_P[args.p] * prob.mesh.ne},
+                   roofline=r32["roofline"],
+                   fp64={"value": r64["value"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
+                         "roofline": r64["roofline"]})
+        if not args.no_cpu_baseline:
+            print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
+            out["cpu_baseline"] = cpu_baseline(args.p)
+    elif args.workload == "tsunami":
+        n = args.n or 256
+        prob = I.config_c3(n=n)
+        print(f"bench: tsunami {prob.mesh.ne} elements adaptive", file=sys.stderr, flush=True)
+        r = run_separated(prob, swe.SWE_FP32_WB, args.steps, args.warmup)
+        out.update(value=r["value"], ms_per_step=r["ms_per_step"], dtype="f32 (f64 bathymetry terms)",
+                   config={"workload": f"tsunami: {n}x{n}x2 jittered, shelf 4000-50 m, 2 m hump, "
+                                       "p in {1,2,3} by indicator (1e-3 m), base p=1 + corrections on 2 streams",
+                           "elements": prob.mesh.ne, "order_fractions": r["order_fractions"]})
+    else:
+        n = args.n or 512
+        prob = I.config_c2(n=n, p=2)
+        prob.p_base = 1
+        prob.p = np.full(prob.mesh.ne, 1, np.int8)
+        prob.p[::32] = 2
+        print(f"bench: static32 {prob.mesh.ne} elements", file=sys.stderr, flush=True)
+        r = run_separated(prob, swe.SWE_FP32_WB, args.steps, args.warmup)
+        out.update(value=r["value"], ms_per_step=r["ms_per_step"], dtype="f32 (f64 bathymetry terms)",
+                   config={"workload": f"static32: tidal {n}x{n}x2 mesh, base p=1, every 32nd element p=2, "
+                                       "corrections on a second stream",
+                           "elements": prob.mesh.ne, "order_fractions": r["order_fractions"]})
+    out["wall_s"] = time.perf_counter() - t_wall0
     print(json.dumps(out), flush=True)
     return 0
 

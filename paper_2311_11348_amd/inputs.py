@@ -105,28 +105,22 @@ def structured_mesh(n: int, length: float = L_DOMAIN, jitter: float = 0.0,
         off = rng.uniform(-jitter * h, jitter * h, size=((n + 1) * (n + 1), 2))
         interior = ((ii.ravel() > 0) & (ii.ravel() < n) & (jj.ravel() > 0) & (jj.ravel() < n))
         vxy[interior] += off[interior]
-    vid = lambda i, j: j * (n + 1) + i  # noqa: E731
+    jj2, ii2 = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")   # square (i, j), i fastest
+    i1, j1 = ii2.ravel(), jj2.ravel()
+    a = j1 * (n + 1) + i1           # SW
+    b = a + 1                       # SE
+    c = a + n + 2                   # NE
+    d = a + n + 1                   # NW
     tri = np.empty((2 * n * n, 3), dtype=np.int32)
+    tri[0::2] = np.stack([a, b, c], 1)   # lower-right (SW, SE, NE): edge 2 south, edge 0 east
+    tri[1::2] = np.stack([a, c, d], 1)   # upper-left (SW, NE, NW): edge 0 north, edge 1 west
     tag = np.full((2 * n * n, 3), TAG_INTERIOR, dtype=np.int8)
-    west = TAG_OPEN if open_west else TAG_LAND
-    e = 0
-    for j in range(n):
-        for i in range(n):
-            a, b, c, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
-            # lower-right triangle (SW, SE, NE): edge 2 (SW-SE) south, edge 0 (SE-NE) east
-            tri[e] = (a, b, c)
-            if j == 0:
-                tag[e, 2] = TAG_LAND
-            if i == n - 1:
-                tag[e, 0] = TAG_LAND
-            e += 1
-            # upper-left triangle (SW, NE, NW): edge 0 (NE-NW) north, edge 1 (NW-SW) west
-            tri[e] = (a, c, d)
-            if j == n - 1:
-                tag[e, 0] = TAG_LAND
-            if i == 0:
-                tag[e, 1] = west
-            e += 1
+    lo, up = tag[0::2], tag[1::2]
+    lo[j1 == 0, 2] = TAG_LAND
+    lo[i1 == n - 1, 0] = TAG_LAND
+    up[j1 == n - 1, 0] = TAG_LAND
+    up[i1 == 0, 1] = TAG_OPEN if open_west else TAG_LAND
+    tag[0::2], tag[1::2] = lo, up
     m = Mesh(vxy=vxy, tri=tri, tag=tag, n=n, length=length)
     if not np.all(m.areas() > 0.0):
         raise ValueError("jitter produced a non-positive triangle area")
