@@ -166,6 +166,59 @@ int64_t swe_footprint_bytes(int64_t ne, int p_max, int precision);
 /* Free everything the context holds; NULL is accepted. */
 void swe_destroy(swe_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent instances advanced together.  Every resident
+ * instance of one order is covered by one persistent launch per RK stage;
+ * each instance keeps its own time, step size, forcing and step budget on
+ * the device, so one captured step (a HIP graph) serves any resident set.
+ * Members are ordinary contexts (precision equal to the batch's, one uniform
+ * order p_max, not separated, not adaptive, no extra source) prepared with
+ * swe_set_mesh / swe_set_bathymetry / swe_set_open_boundary (at most 4
+ * constituents) / swe_set_state.  While resident, a member refuses
+ * swe_step, swe_set_* and the test hooks; swe_get_state and swe_mass wait
+ * for the batch.  Admission is by device footprint (swe_footprint_bytes)
+ * against the budget given at creation.
+ * ------------------------------------------------------------------------ */
+typedef struct swe_batch swe_batch;
+
+/* cfg supplies the precision and the streams (stream_base, or NULL for a
+ * library-owned stream); physics comes from each member.  max_instances
+ * bounds the resident set (slots 0 .. max_instances-1). */
+swe_status swe_batch_create(const swe_config *cfg, int64_t hbm_budget_bytes, int max_instances,
+                            swe_batch **out);
+
+/* Make ctx resident for nsteps steps of size dt from its current state and
+ * time.  SWE_ENOMEM if its footprint exceeds the free budget or no slot is
+ * free; SWE_EINVAL if ctx does not qualify.  *slot receives the slot. */
+swe_status swe_batch_admit(swe_batch *b, swe_ctx *ctx, int64_t nsteps, double dt, int32_t *slot);
+
+/* Enqueue nsteps steps of every resident instance (each stops at its own
+ * budget).  Asynchronous. */
+swe_status swe_batch_tick(swe_batch *b, int64_t nsteps);
+
+/* Wait for queued steps. */
+swe_status swe_batch_sync(swe_batch *b);
+
+/* Steps left, current time and failure flag (non-finite value or
+ * non-positive mean depth) of the instance in slot; synchronises. */
+swe_status swe_batch_query(swe_batch *b, int32_t slot, int64_t *steps_left, double *t, int *failed);
+
+/* Release the slot; the member context keeps its state and gets back its
+ * time (and the failed state if flagged) and can be used on its own again. */
+swe_status swe_batch_retire(swe_batch *b, int32_t slot);
+
+/* Time the candidate tile sizes (64/128/256 elements) and grid sizes on the
+ * resident set and keep the fastest per order; reps timed launches each. */
+swe_status swe_batch_tune(swe_batch *b, int reps);
+
+/* Tuned tile size and grid of an order (after swe_batch_tune). */
+swe_status swe_batch_tile_config(const swe_batch *b, int p, int *tile, int *grid);
+
+int64_t swe_batch_free_bytes(const swe_batch *b);
+int swe_batch_resident(const swe_batch *b);
+const char *swe_batch_last_error(const swe_batch *b);
+void swe_batch_destroy(swe_batch *b);
+
 /* Number of elements and stored modes per component (K(p_max)). */
 int64_t swe_num_elements(const swe_ctx *ctx);
 int swe_num_modes(const swe_ctx *ctx);

@@ -19,6 +19,9 @@ SOURCES = ["swe_kernels.hip", "swe_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
+         # contract a*b+c only within one expression: every kernel that inlines the
+         # same element code rounds identically (batched == single instance, bitwise)
+         "-ffp-contract=on",
          # packed FP32 instructions are kept out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(os.path.dirname(HERE), "include")]

@@ -65,6 +65,8 @@ struct swe_ctx {
     int list_cnt[4] = {0, 0, 0, 0};
     std::vector<int> nb_host;             // [3][stride] neighbour ids / boundary codes
     hipEvent_t ev_ready = nullptr, ev_corr = nullptr;
+    swe_batch *batch = nullptr;           // resident in this batch, or null
+    int slot = -1;
     hipStream_t s_base = nullptr, s_corr = nullptr;
     bool own_base = false, own_corr = false;
     double t = 0.0;
@@ -483,6 +485,7 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t nv, const double *vxy, int64_t ne, c
                         const int8_t *tag)
 {
     if (!c) return SWE_EINVAL;
+    if (c->batch) return fail(c, SWE_EINVAL, "context is resident in a batch");
     if (nv < 3 || ne < 1 || !vxy || !tri) return fail(c, SWE_EINVAL, "empty mesh");
     {
         // element arrays are addressed with 32-bit byte offsets (buffer resources)
@@ -642,6 +645,7 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t nv, const double *vxy, int64_t ne, c
 swe_status swe_set_bathymetry(swe_ctx *c, const double *hb)
 {
     if (!c || !hb) return SWE_EINVAL;
+    if (c->batch) return fail(c, SWE_EINVAL, "context is resident in a batch");
     if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
     for (int64_t i = 0; i < c->nv; ++i) {
         const double v = hb[c->v_perm[i]];
@@ -660,6 +664,7 @@ swe_status swe_set_bathymetry(swe_ctx *c, const double *hb)
 swe_status swe_set_order(swe_ctx *c, const int8_t *p)
 {
     if (!c || !p) return SWE_EINVAL;
+    if (c->batch) return fail(c, SWE_EINVAL, "context is resident in a batch");
     if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
     for (int64_t e = 0; e < c->ne; ++e)
         if (p[e] < c->cfg.p_base || p[e] > c->cfg.p_max)
@@ -707,6 +712,7 @@ swe_status swe_set_open_boundary(swe_ctx *c, int ncon, const double *amp, const 
 swe_status swe_set_state(swe_ctx *c, double t0, const double *coef)
 {
     if (!c || !coef) return SWE_EINVAL;
+    if (c->batch) return fail(c, SWE_EINVAL, "context is resident in a batch");
     if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
     HIP_TRY(c, hipStreamSynchronize(c->s_base));
     HIP_TRY(c, hipStreamSynchronize(c->s_corr));
@@ -763,6 +769,7 @@ swe_status swe_set_state_points(swe_ctx *c, double t0, const double *vals)
 swe_status swe_set_source(swe_ctx *c, const double *coef)
 {
     if (!c) return SWE_EINVAL;
+    if (c->batch) return fail(c, SWE_EINVAL, "context is resident in a batch");
     if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
     HIP_TRY(c, hipStreamSynchronize(c->s_base));
     if (!coef) {
@@ -778,6 +785,7 @@ swe_status swe_set_source(swe_ctx *c, const double *coef)
 swe_status swe_step(swe_ctx *c, int64_t nsteps, double dt)
 {
     if (!c) return SWE_EINVAL;
+    if (c->batch) return fail(c, SWE_EINVAL, "context is resident in a batch");
     if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
     if (c->failed) return fail(c, SWE_ESTATE, "context is in a failed state; call swe_set_state");
     if (nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return fail(c, SWE_EINVAL, "bad step count or dt");
@@ -827,10 +835,18 @@ swe_status swe_sync(swe_ctx *c)
     return SWE_OK;
 }
 
+swe_status swe_batch_sync(swe_batch *b);
+double batch_member_time(swe_batch *b, int slot);
+
 swe_status swe_get_state(swe_ctx *c, double *coef, double *t_out)
 {
     if (!c || !coef) return SWE_EINVAL;
     if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    if (c->batch) {
+        swe_status st = swe_batch_sync(c->batch);
+        if (st != SWE_OK && st != SWE_ESTATE) return fail(c, st, "batch sync failed");
+        c->t = batch_member_time(c->batch, c->slot);
+    }
     HIP_TRY(c, hipStreamSynchronize(c->s_base));
     HIP_TRY(c, hipStreamSynchronize(c->s_corr));
     swe_status st = download(c, c->d_C[0], 3, coef, false);
@@ -842,6 +858,11 @@ swe_status swe_mass(swe_ctx *c, double *out)
 {
     if (!c || !out) return SWE_EINVAL;
     if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    if (c->batch) {
+        swe_status st = swe_batch_sync(c->batch);
+        if (st != SWE_OK && st != SWE_ESTATE) return fail(c, st, "batch sync failed");
+        c->t = batch_member_time(c->batch, c->slot);   // also brings the state over from the pool
+    }
     HIP_TRY(c, launch_mass(view(c), c->fp32, c->d_C[0], c->d_part, c->d_mass, c->s_base));
     HIP_TRY(c, hipMemcpyAsync(out, c->d_mass, sizeof(double), hipMemcpyDeviceToHost, c->s_base));
     HIP_TRY(c, hipStreamSynchronize(c->s_base));
@@ -851,6 +872,7 @@ swe_status swe_mass(swe_ctx *c, double *out)
 swe_status swe_rhs(swe_ctx *c, double t, const double *coef, double *rhs)
 {
     if (!c || !coef || !rhs) return SWE_EINVAL;
+    if (c->batch) return fail(c, SWE_EINVAL, "context is resident in a batch");
     if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
     HIP_TRY(c, hipStreamSynchronize(c->s_base));
     swe_status st = upload_state(c, coef, c->d_C[1]);
@@ -866,6 +888,7 @@ swe_status swe_rhs(swe_ctx *c, double t, const double *coef, double *rhs)
 swe_status swe_usolve(swe_ctx *c, const double *coef, double *u_out)
 {
     if (!c || !coef || !u_out) return SWE_EINVAL;
+    if (c->batch) return fail(c, SWE_EINVAL, "context is resident in a batch");
     if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
     HIP_TRY(c, hipStreamSynchronize(c->s_base));
     swe_status st = upload_state(c, coef, c->d_C[1]);
@@ -922,6 +945,601 @@ swe_status swe_indicator(swe_ctx *c, double t, const double *coef, double *I_out
     HIP_TRY(c, hipMemcpy(h.data(), c->d_I, sizeof(double) * c->ne, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < c->ne; ++i) I_out[c->e_perm[i]] = h[i];
     return SWE_OK;
+}
+
+
+// ----------------------------------------------------------------------------
+// Batches
+// ----------------------------------------------------------------------------
+}  // extern "C"
+
+// A range allocator over [0, cap): first fit, coalescing frees.
+struct RangeAlloc {
+    std::vector<std::pair<int64_t, int64_t>> free;   // (start, length), sorted by start
+    int64_t cap = 0;
+    int64_t take(int64_t n)
+    {
+        for (size_t k = 0; k < free.size(); ++k)
+            if (free[k].second >= n) {
+                const int64_t at = free[k].first;
+                free[k].first += n;
+                free[k].second -= n;
+                if (free[k].second == 0) free.erase(free.begin() + k);
+                return at;
+            }
+        return -1;
+    }
+    void give(int64_t at, int64_t n)
+    {
+        free.push_back({at, n});
+        std::sort(free.begin(), free.end());
+        std::vector<std::pair<int64_t, int64_t>> out;
+        for (auto &r : free) {
+            if (!out.empty() && out.back().first + out.back().second == r.first) out.back().second += r.second;
+            else out.push_back(r);
+        }
+        free.swap(out);
+    }
+    void grow(int64_t newcap)
+    {
+        give(cap, newcap - cap);
+        cap = newcap;
+    }
+};
+
+struct swe_batch {
+    swe_config cfg{};
+    bool fp32 = false;
+    size_t w = 8;
+    int64_t budget = 0, used = 0;
+    int cap = 0;
+    hipStream_t s = nullptr;
+    bool own_s = false;
+    struct Member { swe_ctx *ctx = nullptr; int64_t bytes = 0; int order = 0; int64_t first = 0, span = 0, vbase = 0, nv = 0; };
+    std::vector<Member> mem;
+    std::vector<InstDesc> h_inst;
+    InstDesc *d_inst = nullptr;
+    int *d_flags = nullptr;
+    struct Pool { PoolView v{}; RangeAlloc ra; };
+    Pool pool[4];
+    double4 *d_vtx = nullptr;
+    RangeAlloc vra;
+    int2 *d_tiles[4] = {nullptr, nullptr, nullptr, nullptr};
+    int tile_cap[4] = {0, 0, 0, 0};
+    int *d_ntiles = nullptr;
+    int tile[4] = {256, 256, 256, 256};
+    int grid[4] = {0, 0, 0, 0};
+    int ntiles[4] = {0, 0, 0, 0};
+    int ncu = 256;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int captured_orders = -1;             // bit p set: order p launched by the captured step
+    std::string err;
+};
+
+namespace {
+
+constexpr int POOL_ALIGN = 256;           // element ranges start on tile boundaries of every size
+
+swe_status bfail(swe_batch *b, swe_status s, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return s;
+}
+
+#define BHIP_TRY(bb, expr)                                                                        \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return bfail((bb), e_ == hipErrorOutOfMemory ? SWE_ENOMEM : SWE_EDEVICE,              \
+                         std::string(#expr) + ": " + hipGetErrorString(e_));                     \
+    } while (0)
+
+void drop_graph(swe_batch *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->captured_orders = -1;
+}
+
+// Grow the pool of order p to hold at least need elements (capacity doubles).
+swe_status grow_pool(swe_batch *b, int p, int64_t need)
+{
+    swe_batch::Pool &P = b->pool[p];
+    int64_t nc = std::max<int64_t>(P.ra.cap ? P.ra.cap : 65536, 65536);
+    while (nc < need) nc *= 2;
+    if (nc == P.ra.cap) return SWE_OK;
+    const int64_t K = K_OF[p];
+    if ((int64_t)3 * K * nc * (int64_t)b->w > (int64_t)INT32_MAX)
+        return bfail(b, SWE_EUNSUPPORTED, "pool of one order would exceed 2 GiB per array");
+    PoolView v{};
+    v.cap = (int)nc;
+    BHIP_TRY(b, hipMalloc(&v.C0, b->w * 3 * K * nc));
+    BHIP_TRY(b, hipMalloc(&v.C1, b->w * 3 * K * nc));
+    BHIP_TRY(b, hipMalloc(&v.U0, b->w * 2 * K * nc));
+    BHIP_TRY(b, hipMalloc(&v.U1, b->w * 2 * K * nc));
+    BHIP_TRY(b, hipMalloc(&v.ev, sizeof(int) * 3 * nc));
+    BHIP_TRY(b, hipMalloc(&v.nb, sizeof(int) * 3 * nc));
+    BHIP_TRY(b, hipMalloc(&v.nbk, nc));
+    BHIP_TRY(b, hipMemsetAsync(v.C1, 0, b->w * 3 * K * nc, b->s));
+    BHIP_TRY(b, hipMemsetAsync(v.U1, 0, b->w * 2 * K * nc, b->s));
+    const int64_t oc = P.ra.cap;
+    if (oc > 0) {
+        BHIP_TRY(b, hipMemcpy2DAsync(v.C0, b->w * nc, P.v.C0, b->w * oc, b->w * oc, 3 * K, hipMemcpyDeviceToDevice, b->s));
+        BHIP_TRY(b, hipMemcpy2DAsync(v.U0, b->w * nc, P.v.U0, b->w * oc, b->w * oc, 2 * K, hipMemcpyDeviceToDevice, b->s));
+        BHIP_TRY(b, hipMemcpy2DAsync(v.ev, 4 * nc, P.v.ev, 4 * oc, 4 * oc, 3, hipMemcpyDeviceToDevice, b->s));
+        BHIP_TRY(b, hipMemcpy2DAsync(v.nb, 4 * nc, P.v.nb, 4 * oc, 4 * oc, 3, hipMemcpyDeviceToDevice, b->s));
+        BHIP_TRY(b, hipMemcpyAsync(v.nbk, P.v.nbk, oc, hipMemcpyDeviceToDevice, b->s));
+        BHIP_TRY(b, hipStreamSynchronize(b->s));
+        void *old[] = {P.v.C0, P.v.C1, P.v.U0, P.v.U1, P.v.ev, P.v.nb, P.v.nbk};
+        for (void *q : old) (void)hipFree(q);
+    }
+    P.v = v;
+    P.ra.grow(nc);
+    // tile list capacity follows the pool: at most one tile per 64 elements
+    const int tc = (int)(nc / 64 + 1);
+    int2 *nt = nullptr;
+    BHIP_TRY(b, hipMalloc(&nt, sizeof(int2) * tc));
+    if (b->d_tiles[p]) (void)hipFree(b->d_tiles[p]);
+    b->d_tiles[p] = nt;
+    b->tile_cap[p] = tc;
+    drop_graph(b);
+    return SWE_OK;
+}
+
+swe_status grow_vertices(swe_batch *b, int64_t need)
+{
+    int64_t nc = std::max<int64_t>(b->vra.cap ? b->vra.cap : 65536, 65536);
+    while (nc < need) nc *= 2;
+    if (nc == b->vra.cap) return SWE_OK;
+    double4 *v = nullptr;
+    BHIP_TRY(b, hipMalloc(&v, sizeof(double4) * nc));
+    if (b->vra.cap) {
+        BHIP_TRY(b, hipMemcpyAsync(v, b->d_vtx, sizeof(double4) * b->vra.cap, hipMemcpyDeviceToDevice, b->s));
+        BHIP_TRY(b, hipStreamSynchronize(b->s));
+        (void)hipFree(b->d_vtx);
+    }
+    b->d_vtx = v;
+    b->vra.grow(nc);
+    drop_graph(b);
+    return SWE_OK;
+}
+
+// Tile lists of the resident set: order p gets tiles of b->tile[p] elements.
+swe_status upload_tiles(swe_batch *b)
+{
+    for (int p = 0; p < 4; ++p) {
+        std::vector<int2> t;
+        for (int i = 0; i < b->cap; ++i) {
+            const swe_batch::Member &m = b->mem[i];
+            if (!m.ctx || m.order != p) continue;
+            for (int64_t f = 0; f < m.ctx->ne; f += b->tile[p]) t.push_back(make_int2(i, (int)(m.first + f)));
+        }
+        if ((int)t.size() > b->tile_cap[p]) return bfail(b, SWE_ENOMEM, "tile list capacity exceeded");
+        b->ntiles[p] = (int)t.size();
+        if (!t.empty())
+            BHIP_TRY(b, hipMemcpyAsync(b->d_tiles[p], t.data(), sizeof(int2) * t.size(), hipMemcpyHostToDevice, b->s));
+        if (b->grid[p] <= 0) b->grid[p] = 2 * b->ncu;
+    }
+    BHIP_TRY(b, hipMemcpyAsync(b->d_ntiles, b->ntiles, sizeof(int) * 4, hipMemcpyHostToDevice, b->s));
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
+    int present = 0;
+    for (int p = 0; p < 4; ++p) present |= b->ntiles[p] ? 1 << p : 0;
+    if (present != b->captured_orders) drop_graph(b);   // the captured step launches other orders
+    return SWE_OK;
+}
+
+BatchArgs batch_args(const swe_batch *b, int p)
+{
+    BatchArgs a;
+    a.pool = b->pool[p].v;
+    a.vtx = b->d_vtx;
+    a.inst = b->d_inst;
+    a.tiles = b->d_tiles[p];
+    a.ntiles = b->d_ntiles + p;
+    a.flags = b->d_flags;
+    return a;
+}
+
+// FP64 order-3 instances are launched one by one (the single-instance stage
+// kernel, clock and element offset read from the device); every other class
+// runs in the persistent multi-instance kernel.
+bool per_instance(const swe_batch *b, int p) { return p == 3 && !b->fp32; }
+
+hipError_t enqueue_instance_stage(swe_batch *b, int i, int mode)
+{
+    const swe_batch::Member &m = b->mem[i];
+    const PoolView &v = b->pool[m.order].v;
+    StageArgs<double> a;
+    std::memset(&a, 0, sizeof(a));
+    a.m.ne = (int)m.ctx->ne;
+    a.m.stride = v.cap;
+    a.m.KS = K_OF[m.order];
+    a.m.vtx = b->d_vtx;
+    a.m.ev = v.ev;
+    a.m.enb = v.nb;
+    a.m.enbk = v.nbk;
+    a.Cin = static_cast<const double *>(mode == MODE_STAGE1 ? v.C0 : v.C1);
+    a.Uin = static_cast<const double *>(mode == MODE_STAGE1 ? v.U0 : v.U1);
+    a.Cn = static_cast<const double *>(v.C0);
+    a.Cout = static_cast<double *>(mode == MODE_STAGE1 ? v.C1 : v.C0);
+    a.Uout = static_cast<double *>(mode == MODE_STAGE1 ? v.U1 : v.U0);
+    a.ph = b->h_inst[i].ph;
+    a.flag = b->d_flags + i;
+    a.inst = b->d_inst + i;
+    a.e_off = (int)m.first;
+    return launch_stage(m.order, false, mode, false, &a, b->s);
+}
+
+hipError_t enqueue_batch_step(swe_batch *b)
+{
+    hipError_t e = launch_batch_clock(b->d_inst, b->cap, b->s);
+    for (int mode = MODE_STAGE1; mode <= MODE_STAGE2 && e == hipSuccess; ++mode)
+        for (int p = 0; p < 4 && e == hipSuccess; ++p) {
+            if (b->ntiles[p] == 0) continue;
+            if (per_instance(b, p)) {
+                for (int i = 0; i < b->cap && e == hipSuccess; ++i)
+                    if (b->mem[i].ctx && b->mem[i].order == p) e = enqueue_instance_stage(b, i, mode);
+                continue;
+            }
+            // the kernels read the tile counts from device memory, so the grid
+            // need not match the current resident set
+            e = launch_batch_stage(p, b->fp32, mode, b->tile[p], batch_args(b, p), b->grid[p], b->s);
+        }
+    return e;
+}
+
+// Capture one step as a graph; the kernels read everything that changes
+// (times, budgets, tile counts) from device memory.
+swe_status capture_step(swe_batch *b)
+{
+    drop_graph(b);
+    BHIP_TRY(b, hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_batch_step(b);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->s, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return bfail(b, SWE_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    BHIP_TRY(b, hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+    b->captured_orders = 0;
+    for (int p = 0; p < 4; ++p) b->captured_orders |= b->ntiles[p] ? 1 << p : 0;
+    return SWE_OK;
+}
+
+swe_status put_desc(swe_batch *b, int i)
+{
+    BHIP_TRY(b, hipMemcpyAsync(b->d_inst + i, &b->h_inst[i], sizeof(InstDesc), hipMemcpyHostToDevice, b->s));
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
+    return SWE_OK;
+}
+
+swe_status get_desc(swe_batch *b, int i)
+{
+    BHIP_TRY(b, hipMemcpyAsync(&b->h_inst[i], b->d_inst + i, sizeof(InstDesc), hipMemcpyDeviceToHost, b->s));
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
+    return SWE_OK;
+}
+
+// copy a resident instance's state and velocity from the pool into its context
+swe_status pull_state(swe_batch *b, int i)
+{
+    const swe_batch::Member &m = b->mem[i];
+    swe_ctx *c = m.ctx;
+    const swe_batch::Pool &P = b->pool[m.order];
+    const size_t w = b->w, K = c->K;
+    BHIP_TRY(b, hipMemcpy2DAsync(c->d_C[0], w * c->stride, static_cast<char *>(P.v.C0) + w * m.first, w * P.v.cap,
+                                 w * c->ne, 3 * K, hipMemcpyDeviceToDevice, b->s));
+    BHIP_TRY(b, hipMemcpy2DAsync(c->d_U[0], w * c->stride, static_cast<char *>(P.v.U0) + w * m.first, w * P.v.cap,
+                                 w * c->ne, 2 * K, hipMemcpyDeviceToDevice, b->s));
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
+    return SWE_OK;
+}
+
+}  // namespace
+
+double batch_member_time(swe_batch *b, int slot)
+{
+    if (!b || slot < 0 || slot >= b->cap) return 0.0;
+    if (get_desc(b, slot) != SWE_OK) return 0.0;
+    if (pull_state(b, slot) != SWE_OK) return b->h_inst[slot].t;
+    return b->h_inst[slot].t;
+}
+
+extern "C" {
+
+swe_status swe_batch_create(const swe_config *cfg, int64_t budget, int max_instances, swe_batch **out)
+{
+    if (!cfg || !out || budget <= 0 || max_instances <= 0 || max_instances > 65536) return SWE_EINVAL;
+    if (cfg->precision != SWE_FP64 && cfg->precision != SWE_FP32_WB) return SWE_EINVAL;
+    *out = nullptr;
+    swe_batch *b = new (std::nothrow) swe_batch();
+    if (!b) return SWE_ENOMEM;
+    b->cfg = *cfg;
+    b->fp32 = cfg->precision == SWE_FP32_WB;
+    b->w = b->fp32 ? 4 : 8;
+    b->budget = budget;
+    b->cap = max_instances;
+    b->mem.assign(max_instances, swe_batch::Member());
+    b->h_inst.assign(max_instances, InstDesc());
+    std::memset(b->h_inst.data(), 0, sizeof(InstDesc) * max_instances);
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        b->ncu = prop.multiProcessorCount;
+    if (cfg->stream_base) {
+        b->s = static_cast<hipStream_t>(cfg->stream_base);
+    } else if (hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return SWE_EDEVICE;
+    } else {
+        b->own_s = true;
+    }
+    if (hipMalloc(&b->d_inst, sizeof(InstDesc) * max_instances) != hipSuccess ||
+        hipMalloc(&b->d_flags, sizeof(int) * max_instances) != hipSuccess ||
+        hipMalloc(&b->d_ntiles, sizeof(int) * 4) != hipSuccess) {
+        swe_batch_destroy(b);
+        return SWE_ENOMEM;
+    }
+    if (hipMemcpy(b->d_inst, b->h_inst.data(), sizeof(InstDesc) * max_instances, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(b->d_flags, 0, sizeof(int) * max_instances) != hipSuccess ||
+        hipMemset(b->d_ntiles, 0, sizeof(int) * 4) != hipSuccess) {
+        swe_batch_destroy(b);
+        return SWE_EDEVICE;
+    }
+    *out = b;
+    return SWE_OK;
+}
+
+void swe_batch_destroy(swe_batch *b)
+{
+    if (!b) return;
+    if (b->s) (void)hipStreamSynchronize(b->s);
+    for (int i = 0; i < b->cap; ++i)
+        if (b->mem[i].ctx) {
+            (void)pull_state(b, i);
+            (void)get_desc(b, i);
+            b->mem[i].ctx->t = b->h_inst[i].t;
+            b->mem[i].ctx->batch = nullptr;
+            b->mem[i].ctx->slot = -1;
+        }
+    drop_graph(b);
+    std::vector<void *> ptrs = {b->d_inst, b->d_flags, b->d_ntiles, b->d_vtx};
+    for (int p = 0; p < 4; ++p) {
+        const PoolView &v = b->pool[p].v;
+        for (void *q : {v.C0, v.C1, v.U0, v.U1, (void *)v.ev, (void *)v.nb, (void *)v.nbk, (void *)b->d_tiles[p]})
+            ptrs.push_back(q);
+    }
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    if (b->own_s) (void)hipStreamDestroy(b->s);
+    delete b;
+}
+
+const char *swe_batch_last_error(const swe_batch *b) { return b ? b->err.c_str() : "null batch"; }
+int64_t swe_batch_free_bytes(const swe_batch *b) { return b ? b->budget - b->used : 0; }
+
+int swe_batch_resident(const swe_batch *b)
+{
+    if (!b) return 0;
+    int n = 0;
+    for (const auto &m : b->mem) n += m.ctx ? 1 : 0;
+    return n;
+}
+
+swe_status swe_batch_admit(swe_batch *b, swe_ctx *c, int64_t nsteps, double dt, int32_t *slot)
+{
+    if (!b || !c || !slot || nsteps < 0 || !(dt > 0.0)) return SWE_EINVAL;
+    if (!c->have_mesh) return bfail(b, SWE_EINVAL, "context has no mesh");
+    if (c->batch) return bfail(b, SWE_EINVAL, "context is already resident in a batch");
+    if (c->fp32 != b->fp32) return bfail(b, SWE_EINVAL, "context precision differs from the batch");
+    if (c->cfg.separate || c->cfg.adapt || !c->uniform || c->d_src || c->failed)
+        return bfail(b, SWE_EINVAL, "batch members need one uniform order, no separation, adaptivity or source");
+    if (c->ncon > 4) return bfail(b, SWE_EINVAL, "batch members support at most 4 forcing constituents");
+    const int64_t bytes = swe_footprint_bytes(c->ne, c->cfg.p_max, c->cfg.precision);
+    if (bytes > b->budget - b->used) return bfail(b, SWE_ENOMEM, "footprint exceeds the free budget");
+    int i = 0;
+    while (i < b->cap && b->mem[i].ctx) ++i;
+    if (i == b->cap) return bfail(b, SWE_ENOMEM, "no free slot");
+    BHIP_TRY(b, hipStreamSynchronize(c->s_base));
+    BHIP_TRY(b, hipStreamSynchronize(c->s_corr));
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
+    const int p = c->cfg.p_max;
+    swe_batch::Pool &P = b->pool[p];
+    const int64_t span = (c->ne + POOL_ALIGN - 1) / POOL_ALIGN * POOL_ALIGN;
+    int64_t first = P.ra.take(span);
+    if (first < 0) {
+        swe_status st = grow_pool(b, p, P.ra.cap + span);
+        if (st) return st;
+        first = P.ra.take(span);
+        if (first < 0) return bfail(b, SWE_ENOMEM, "pool allocation failed");
+    }
+    int64_t vbase = b->vra.take(c->nv);
+    if (vbase < 0) {
+        swe_status st = grow_vertices(b, b->vra.cap + c->nv);
+        if (st) { P.ra.give(first, span); return st; }
+        vbase = b->vra.take(c->nv);
+    }
+    const size_t w = b->w, K = c->K;
+    BHIP_TRY(b, hipMemcpy2DAsync(static_cast<char *>(P.v.C0) + w * first, w * P.v.cap, c->d_C[0], w * c->stride,
+                                 w * c->ne, 3 * K, hipMemcpyDeviceToDevice, b->s));
+    BHIP_TRY(b, hipMemcpy2DAsync(static_cast<char *>(P.v.U0) + w * first, w * P.v.cap, c->d_U[0], w * c->stride,
+                                 w * c->ne, 2 * K, hipMemcpyDeviceToDevice, b->s));
+    BHIP_TRY(b, hipMemcpyAsync(b->d_vtx + vbase, c->d_vtx, sizeof(double4) * c->nv, hipMemcpyDeviceToDevice, b->s));
+    BHIP_TRY(b, launch_relocate(c->d_ev, c->d_nb, c->d_nbk, (int)c->ne, c->stride, P.v, (int)first, (int)vbase, b->s));
+    InstDesc &d = b->h_inst[i];
+    std::memset(&d, 0, sizeof(d));
+    d.first = (int)first;
+    d.ne = (int)c->ne;
+    d.vbase = (int)vbase;
+    d.nv = (int)c->nv;
+    d.order = p;
+    d.ph.g = c->cfg.g;
+    d.ph.fc = c->cfg.f_coriolis;
+    d.ph.fric = c->cfg.friction_coef;
+    d.ph.friction = c->cfg.friction;
+    d.t0 = c->t;
+    d.t = c->t;
+    d.dt = dt;
+    d.steps_left = (int)std::min<int64_t>(nsteps, INT32_MAX);
+    d.active = 1;
+    d.ncon = c->ncon;
+    for (int k = 0; k < c->ncon; ++k) { d.amp[k] = c->amp[k]; d.omega[k] = c->omega[k]; d.phase[k] = c->phase[k]; }
+    BHIP_TRY(b, hipMemsetAsync(b->d_flags + i, 0, sizeof(int), b->s));
+    swe_status st = put_desc(b, i);
+    if (st) return st;
+    swe_batch::Member &m = b->mem[i];
+    m.ctx = c;
+    m.bytes = bytes;
+    m.order = p;
+    m.first = first;
+    m.span = span;
+    m.vbase = vbase;
+    m.nv = c->nv;
+    b->used += bytes;
+    c->batch = b;
+    c->slot = i;
+    if (per_instance(b, p)) drop_graph(b);   // the captured step launches each such instance
+    st = upload_tiles(b);
+    if (st) return st;
+    *slot = i;
+    return SWE_OK;
+}
+
+swe_status swe_batch_tick(swe_batch *b, int64_t nsteps)
+{
+    if (!b || nsteps < 0) return SWE_EINVAL;
+    if (nsteps == 0 || swe_batch_resident(b) == 0) return SWE_OK;
+    if (!b->gexec) {
+        swe_status st = capture_step(b);
+        if (st) return st;
+    }
+    for (int64_t k = 0; k < nsteps; ++k) BHIP_TRY(b, hipGraphLaunch(b->gexec, b->s));
+    return SWE_OK;
+}
+
+swe_status swe_batch_sync(swe_batch *b)
+{
+    if (!b) return SWE_EINVAL;
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
+    return SWE_OK;
+}
+
+swe_status swe_batch_query(swe_batch *b, int32_t slot, int64_t *steps_left, double *t, int *failed)
+{
+    if (!b || slot < 0 || slot >= b->cap || !b->mem[slot].ctx) return SWE_EINVAL;
+    swe_status st = get_desc(b, slot);
+    if (st) return st;
+    int f = 0;
+    BHIP_TRY(b, hipMemcpy(&f, b->d_flags + slot, sizeof(int), hipMemcpyDeviceToHost));
+    if (steps_left) *steps_left = b->h_inst[slot].steps_left;
+    if (t) *t = b->h_inst[slot].t;
+    if (failed) *failed = f;
+    return SWE_OK;
+}
+
+swe_status swe_batch_retire(swe_batch *b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= b->cap || !b->mem[slot].ctx) return SWE_EINVAL;
+    swe_batch::Member &m = b->mem[slot];
+    swe_ctx *c = m.ctx;
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
+    swe_status st = get_desc(b, slot);
+    if (st) return st;
+    st = pull_state(b, slot);
+    if (st) return st;
+    int f = 0;
+    BHIP_TRY(b, hipMemcpy(&f, b->d_flags + slot, sizeof(int), hipMemcpyDeviceToHost));
+    c->t = b->h_inst[slot].t;
+    if (f) c->failed = true;
+    b->h_inst[slot].active = 0;
+    b->h_inst[slot].run = 0;
+    st = put_desc(b, slot);
+    if (st) return st;
+    if (per_instance(b, m.order)) drop_graph(b);
+    b->pool[m.order].ra.give(m.first, m.span);
+    b->vra.give(m.vbase, m.nv);
+    b->used -= m.bytes;
+    m = swe_batch::Member();
+    c->batch = nullptr;
+    c->slot = -1;
+    return upload_tiles(b);
+}
+
+swe_status swe_batch_tile_config(const swe_batch *b, int p, int *tile, int *grid)
+{
+    if (!b || p < 0 || p > 3) return SWE_EINVAL;
+    if (tile) *tile = b->tile[p];
+    if (grid) *grid = b->grid[p];
+    return SWE_OK;
+}
+
+swe_status swe_batch_tune(swe_batch *b, int reps)
+{
+    if (!b || reps <= 0) return SWE_EINVAL;
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
+    // every resident instance takes part without advancing: stage 1 reads
+    // buffer 0 and writes buffer 1 only, so the timing launches leave the
+    // state untouched; the clock fields are restored afterwards
+    std::vector<InstDesc> saved(b->h_inst);
+    for (int i = 0; i < b->cap; ++i) {
+        if (!b->mem[i].ctx) continue;
+        swe_status st = get_desc(b, i);
+        if (st) return st;
+        saved[i] = b->h_inst[i];
+        b->h_inst[i].run = 1;
+        st = put_desc(b, i);
+        if (st) return st;
+    }
+    hipEvent_t e0, e1;
+    BHIP_TRY(b, hipEventCreate(&e0));
+    BHIP_TRY(b, hipEventCreate(&e1));
+    const int tiles[3] = {64, 128, 256};
+    const int mult[4] = {1, 2, 4, 8};
+    swe_status st = SWE_OK;
+    for (int p = 0; p < 4 && st == SWE_OK; ++p) {
+        bool any = false;
+        for (int i = 0; i < b->cap; ++i) any = any || (b->mem[i].ctx && b->mem[i].order == p);
+        if (!any || per_instance(b, p)) continue;
+        float best = 1e30f;
+        int bt = b->tile[p], bg = b->grid[p];
+        for (int ti = 0; ti < 3 && st == SWE_OK; ++ti) {
+            b->tile[p] = tiles[ti];
+            st = upload_tiles(b);
+            for (int mi = 0; mi < 4 && st == SWE_OK; ++mi) {
+                const int grid = std::max(1, std::min(b->ntiles[p], mult[mi] * b->ncu * 256 / tiles[ti]));
+                hipError_t e = launch_batch_stage(p, b->fp32, MODE_STAGE1, tiles[ti], batch_args(b, p), grid, b->s);
+                if (e == hipSuccess) e = hipEventRecord(e0, b->s);
+                for (int r = 0; r < reps && e == hipSuccess; ++r)
+                    e = launch_batch_stage(p, b->fp32, MODE_STAGE1, tiles[ti], batch_args(b, p), grid, b->s);
+                if (e == hipSuccess) e = hipEventRecord(e1, b->s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) { st = bfail(b, SWE_EDEVICE, std::string("tuning: ") + hipGetErrorString(e)); break; }
+                if (ms < best) { best = ms; bt = tiles[ti]; bg = grid; }
+            }
+        }
+        b->tile[p] = bt;
+        b->grid[p] = bg;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int i = 0; i < b->cap; ++i) {
+        if (!b->mem[i].ctx) continue;
+        b->h_inst[i] = saved[i];
+        swe_status s2 = put_desc(b, i);
+        if (st == SWE_OK) st = s2;
+    }
+    // stage 1 also checked depths: start the flags of the real run clean
+    BHIP_TRY(b, hipMemsetAsync(b->d_flags, 0, sizeof(int) * b->cap, b->s));
+    if (st == SWE_OK) st = upload_tiles(b);
+    drop_graph(b);
+    return st;
 }
 
 }  // extern "C"

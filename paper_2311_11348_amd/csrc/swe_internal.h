@@ -64,6 +64,44 @@ struct StageArgs {
     int *listw;          // [4][lcap] lists being rebuilt by the order update
     int *cntw;           // [4] their lengths
     Real *Calt, *Ualt;   // the other state/velocity buffer (order update clears dropped modes)
+    // batched instance launched on its own: element indices start at e_off in
+    // the pooled arrays; step, open-sea elevation and run flag come from inst
+    const struct InstDesc *inst;
+    int e_off;
+};
+
+struct InstDesc;
+
+// One resident instance of a batch.  Its elements occupy [first, first + ne)
+// of the pool of its order and its vertices [vbase, vbase + nv) of the vertex
+// pool; neighbour and vertex ids in the pools are already offset.
+struct InstDesc {
+    int first, ne, vbase, nv;
+    int order;
+    int active, run;             // resident / advancing in the current step
+    int steps_done, steps_left;
+    int ncon;
+    Physics ph;
+    double t0, t, dt;            // start time, current time, step
+    double xh[2];                // open-sea elevation at the two stage times of this step
+    double amp[4], omega[4], phase[4];
+};
+
+// Pooled arrays of one order class (structure of arrays, stride cap).
+struct PoolView {
+    void *C0, *C1, *U0, *U1;     // state and velocity ping-pong buffers [slot][cap]
+    int *ev, *nb;                // [3][cap]
+    unsigned char *nbk;          // [cap]
+    int cap;
+};
+
+struct BatchArgs {
+    PoolView pool;               // pool of the launched order
+    const double4 *vtx;          // vertex pool
+    const InstDesc *inst;
+    const int2 *tiles;           // [tile_cap] (instance, first element) of the launched order
+    const int *ntiles;           // device-side tile count of the launched order
+    int *flags;                  // [instances]
 };
 
 // Launchers (defined in swe_kernels.hip).  Return hipSuccess or the launch error.
@@ -78,5 +116,10 @@ hipError_t launch_apply_order(int pm, bool fp32, const void *args, const signed 
 hipError_t launch_mass(const MeshView &m, bool fp32, const void *C, double *partial,
                        double *out, hipStream_t s);
 int mass_partials(int ne);
+hipError_t launch_batch_stage(int p, bool fp32, int mode, int tile, const BatchArgs &b, int grid, hipStream_t s);
+hipError_t launch_batch_clock(InstDesc *inst, int n, hipStream_t s);
+// copy an instance's mesh arrays into a pool, offsetting vertex and element ids
+hipError_t launch_relocate(const int *ev, const int *nb, const unsigned char *nbk, int ne, int stride,
+                           const PoolView &pool, int first, int vbase, hipStream_t s);
 
 }  // namespace swe

@@ -623,7 +623,7 @@ __device__ __forceinline__ void hb_modes(const Geo &G, double (&hbh)[3])
 template <int KN, int NX, typename Real>
 __device__ __forceinline__ void load_trace_table(Real (*sR)[KN][NX])
 {
-    for (int i = threadIdx.x; i < 3 * KN * NX; i += BLOCK) {
+    for (int i = threadIdx.x; i < 3 * KN * NX; i += blockDim.x) {
         const int k = i / (KN * NX), r = i % (KN * NX);
         sR[k][r / NX][r % NX] = (r % NX) < 4 ? Real(TR[k][r / NX][r % NX]) : Real(0);
     }
@@ -647,12 +647,12 @@ __device__ __forceinline__ void element_rhs(const StageArgs<Real> &a, unsigned e
                                             const Buf<Real> &bU, const Buf<int> &bNb,
                                             const Fields<P, Real> &s, const Geo &G, const double (&hbh)[3],
                                             double dt, const Real (*sR)[Ord<PN>::K][(P > PN ? P : PN) + 1],
-                                            Acc<P, Real> &A)
+                                            Acc<P, Real> &A, double xihat)
 {
     constexpr int K = Ord<P>::K;
     volume_term<P, Real>(s, hbh, G, a.ph.g, dt, A);
     source_term<P, Real>(s, G, a.ph, dt, A);
-    edge_terms<P, PN, Real>(a.m, e, bC, bU, bNb, s, G, a.ph.g, a.xihat, dt, sR, A);
+    edge_terms<P, PN, Real>(a.m, e, bC, bU, bNb, s, G, a.ph.g, xihat, dt, sR, A);
     if constexpr (Acc<P, Real>::SPLIT) {
 #pragma unroll
         for (int q = 0; q < K; ++q) {
@@ -674,7 +674,8 @@ __device__ __forceinline__ void element_rhs(const StageArgs<Real> &a, unsigned e
 // SSP-RK2 combine of acc = c + dt L, u-solve of the new state, store, depth check
 template <int P, typename Real, int MODE>
 __device__ __forceinline__ void finish_stage(const StageArgs<Real> &a, unsigned e, const Geo &G,
-                                             const double (&hbh)[3], int Ke, const Real (&L)[3][Ord<P>::K])
+                                             const double (&hbh)[3], int Ke, const Real (&L)[3][Ord<P>::K],
+                                             int *flag)
 {
     constexpr int K = Ord<P>::K;
     const int KS = a.m.KS, stride = a.m.stride;
@@ -705,7 +706,7 @@ __device__ __forceinline__ void finish_stage(const StageArgs<Real> &a, unsigned 
         chk += xn[q] + Un[q] + Vn[q] + un[q] + vn[q];
     }
     const double Hmean = SQRT2 * double(xn[0]) + (G.h[0] + G.h[1] + G.h[2]) * (1.0 / 3.0);
-    if (!(Hmean > 0.0) || !isfinite(chk)) a.flag[0] = 1;
+    if (!(Hmean > 0.0) || !isfinite(chk)) flag[0] = 1;
 }
 
 // ------------------------------------------------------------ kernels
@@ -714,16 +715,12 @@ __device__ __forceinline__ void finish_stage(const StageArgs<Real> &a, unsigned 
 // with its first K(P) modes (P = p_base); elements whose right-hand side also
 // has a correction store their partial stage value in Lb for the epilogue.
 template <int P, typename Real, int MODE, bool SEP>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_target<P, Real>(), 8)))
-k_stage(StageArgs<Real> a)
+__device__ __forceinline__ void stage_element(const StageArgs<Real> &a, unsigned e,
+                                              const Real (*sR)[Ord<P>::K][Ord<P>::NT], double xihat,
+                                              double dt_stage, int *flag)
 {
-    constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
-    __shared__ Real sR[3][K][NT];
-    load_trace_table<K, NT, Real>(sR);
-    __syncthreads();
-    const unsigned e = (unsigned)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    constexpr int K = Ord<P>::K;
     const MeshView &m = a.m;
-    if (e >= (unsigned)m.ne) return;
     const int KS = m.KS, stride = m.stride;
     const unsigned off = e * (unsigned)sizeof(Real);
     const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
@@ -736,10 +733,10 @@ k_stage(StageArgs<Real> a)
     load_state<P, Real>(bC, bU, KS, off, s);
     const int Ke = (!SEP && a.mixed) ? KOFP[m.ep[e]] : K;
 
-    const double dt = MODE == MODE_RHS ? 1.0 : a.dt;
+    const double dt = MODE == MODE_RHS ? 1.0 : dt_stage;
     Acc<P, Real> A;
     acc_init<P, Real>(A, s, MODE != MODE_RHS);
-    element_rhs<P, P, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A);
+    element_rhs<P, P, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A, xihat);
     if (!SEP && a.mixed) {
         // modes above the element's order stay zero
 #pragma unroll
@@ -764,8 +761,112 @@ k_stage(StageArgs<Real> a)
                 return;
             }
         }
-        finish_stage<P, Real, MODE>(a, e, G, hbh, Ke, A.L);
+        finish_stage<P, Real, MODE>(a, e, G, hbh, Ke, A.L, flag);
     }
+}
+
+template <int P, typename Real, int MODE, bool SEP>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_target<P, Real>(), 8)))
+k_stage(StageArgs<Real> a)
+{
+    constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
+    __shared__ Real sR[3][K][NT];
+    load_trace_table<K, NT, Real>(sR);
+    __syncthreads();
+    const unsigned le = (unsigned)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (le >= (unsigned)a.m.ne) return;
+    double xihat = a.xihat, dt = a.dt;
+    if (a.inst) {
+        // one instance of a batch: its clock lives on the device
+        if (!a.inst->run) return;
+        xihat = MODE == MODE_STAGE2 ? a.inst->xh[1] : a.inst->xh[0];
+        dt = a.inst->dt;
+    }
+    stage_element<P, Real, MODE, SEP>(a, le + (unsigned)a.e_off, sR, xihat, dt, a.flag);
+}
+
+// ------------------------------------------------------------ batched instances
+// One persistent launch per order class and stage covers the tiles of every
+// resident instance of that order.  All instances of an order share pooled
+// arrays passed as kernel arguments; a tile (TILE consecutive elements of one
+// instance) only reads its instance's scalars (step, open-sea elevation,
+// physics, clock).  Block b walks a contiguous chunk of the tile list, so the
+// tiles of one instance stay on one XCD.  Instances whose clock says they are
+// done are skipped: one captured step serves any resident set.
+template <int P, typename Real, int MODE, int TILE>
+__global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(waves_target<P, Real>(), 8)))
+k_batch_stage(BatchArgs b)
+{
+    constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
+    __shared__ Real sR[3][K][NT];
+    load_trace_table<K, NT, Real>(sR);
+    __syncthreads();
+    const int ntiles = b.ntiles[0];
+    const int per = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int t0 = (int)blockIdx.x * per, t1 = t0 + per < ntiles ? t0 + per : ntiles;
+    StageArgs<Real> a;
+    a.m.ne = 0;
+    a.m.stride = b.pool.cap;
+    a.m.KS = K;
+    a.m.vtx = b.vtx;
+    a.m.ev = b.pool.ev;
+    a.m.enb = b.pool.nb;
+    a.m.enbk = b.pool.nbk;
+    a.m.ep = nullptr;
+    a.Cin = static_cast<const Real *>(MODE == MODE_STAGE1 ? b.pool.C0 : b.pool.C1);
+    a.Uin = static_cast<const Real *>(MODE == MODE_STAGE1 ? b.pool.U0 : b.pool.U1);
+    a.Cn = static_cast<const Real *>(b.pool.C0);
+    a.Cout = static_cast<Real *>(MODE == MODE_STAGE1 ? b.pool.C1 : b.pool.C0);
+    a.Uout = static_cast<Real *>(MODE == MODE_STAGE1 ? b.pool.U1 : b.pool.U0);
+    a.Lout = nullptr;
+    a.src = nullptr;
+    a.mixed = 0;
+    for (int t = t0; t < t1; ++t) {
+        const int2 tile = b.tiles[t];
+        const InstDesc &I = b.inst[tile.x];
+        if (!I.run) continue;
+        a.ph = I.ph;
+        const unsigned e = (unsigned)tile.y + threadIdx.x;
+        if (e < (unsigned)(I.first + I.ne))
+            stage_element<P, Real, MODE, false>(a, e, sR, MODE == MODE_STAGE1 ? I.xh[0] : I.xh[1], I.dt,
+                                                b.flags + tile.x);
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_relocate(const int *ev, const int *nb, const unsigned char *nbk, int ne,
+                                                    int stride, PoolView pool, int first, int vbase)
+{
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= ne) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        pool.ev[k * pool.cap + first + e] = ev[k * stride + e] + vbase;
+        const int n = nb[k * stride + e];
+        pool.nb[k * pool.cap + first + e] = n >= 0 ? n + first : n;
+    }
+    pool.nbk[first + e] = nbk[e];
+}
+
+// Per-step clock of every resident instance: open-sea elevation at the two
+// stage times, then advance its time and step budget.
+__global__ void __launch_bounds__(BLOCK) k_batch_clock(InstDesc *inst, int n)
+{
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    InstDesc &I = inst[i];
+    const int run = I.active && I.steps_left > 0;
+    I.run = run;
+    if (!run) return;
+    double x1 = 0.0, x2 = 0.0;
+    for (int c = 0; c < I.ncon; ++c) {
+        x1 += I.amp[c] * sin(I.omega[c] * I.t + I.phase[c]);
+        x2 += I.amp[c] * sin(I.omega[c] * (I.t + I.dt) + I.phase[c]);
+    }
+    I.xh[0] = x1;
+    I.xh[1] = x2;
+    I.t = I.t0 + (double)(I.steps_done + 1) * I.dt;
+    I.steps_done += 1;
+    I.steps_left -= 1;
 }
 
 // Correction of the order-separated scheme for the listed elements of order P
@@ -807,7 +908,7 @@ k_corr(StageArgs<Real> a, double dt)
             }
             Acc<B, Real> Ab;
             acc_init<B, Real>(Ab, sb, false);
-            element_rhs<B, B, Real>(a, e, bC, bU, bNb, sb, G, hbh, dt, sRb, Ab);
+            element_rhs<B, B, Real>(a, e, bC, bU, bNb, sb, G, hbh, dt, sRb, Ab, a.xihat);
             // ... then the full part accumulates on top of its negation
 #pragma unroll
             for (int q = 0; q < K; ++q) {
@@ -821,7 +922,7 @@ k_corr(StageArgs<Real> a, double dt)
                 for (int j = 0; j < 3; ++j) A.L[j][q] = -Ab.L[j][q];
             }
         }
-        element_rhs<P, PN, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A);
+        element_rhs<P, PN, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A, a.xihat);
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
@@ -855,7 +956,7 @@ k_epi(StageArgs<Real> a, int KB)
 #pragma unroll
             for (int q = 0; q < K; ++q)
                 L[j][q] = (q < KB ? bB.ld(j * KB + q, off) : bC.ld(j * KS + q, off)) + bL.ld(j * KS + q, off);
-        finish_stage<P, Real, MODE>(a, e, G, hbh, K, L);
+        finish_stage<P, Real, MODE>(a, e, G, hbh, K, L, a.flag);
     }
 }
 
@@ -1178,6 +1279,62 @@ hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s)
 }
 
 int mass_partials(int ne) { return (ne + BLOCK - 1) / BLOCK; }
+
+namespace {
+template <int P, typename Real, int TILE>
+hipError_t batch_pt(int mode, const BatchArgs &b, int grid, hipStream_t s)
+{
+    if (mode == MODE_STAGE1) hipLaunchKernelGGL((k_batch_stage<P, Real, MODE_STAGE1, TILE>), dim3(grid), dim3(TILE), 0, s, b);
+    else hipLaunchKernelGGL((k_batch_stage<P, Real, MODE_STAGE2, TILE>), dim3(grid), dim3(TILE), 0, s, b);
+    return hipGetLastError();
+}
+
+template <typename Real, int TILE>
+hipError_t batch_t(int p, int mode, const BatchArgs &b, int grid, hipStream_t s)
+{
+    switch (p) {
+    case 0: return batch_pt<0, Real, TILE>(mode, b, grid, s);
+    case 1: return batch_pt<1, Real, TILE>(mode, b, grid, s);
+    case 2: return batch_pt<2, Real, TILE>(mode, b, grid, s);
+    case 3: return batch_pt<3, Real, TILE>(mode, b, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename Real>
+hipError_t batch_r(int p, int mode, int tile, const BatchArgs &b, int grid, hipStream_t s)
+{
+    switch (tile) {
+    case 64: return batch_t<Real, 64>(p, mode, b, grid, s);
+    case 128: return batch_t<Real, 128>(p, mode, b, grid, s);
+    case 256: return batch_t<Real, 256>(p, mode, b, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_batch_stage(int p, bool fp32, int mode, int tile, const BatchArgs &b, int grid, hipStream_t s)
+{
+    if (grid <= 0) return hipSuccess;
+    return fp32 ? batch_r<float>(p, mode, tile, b, grid, s) : batch_r<double>(p, mode, tile, b, grid, s);
+}
+
+hipError_t launch_batch_clock(InstDesc *inst, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_clock, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, inst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_relocate(const int *ev, const int *nb, const unsigned char *nbk, int ne, int stride,
+                           const PoolView &pool, int first, int vbase, hipStream_t s)
+{
+    if (ne <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_relocate, dim3((ne + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, ev, nb, nbk, ne, stride, pool,
+                       first, vbase);
+    return hipGetLastError();
+}
 
 hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, int p_hi, double *I_out,
                             signed char *p_new, hipStream_t s)

@@ -75,6 +75,18 @@ def lib() -> C.CDLL:
         "swe_destroy": (None, [vp]),
         "swe_num_elements": (C.c_int64, [vp]),
         "swe_num_modes": (C.c_int, [vp]),
+        "swe_batch_create": (C.c_int, [C.POINTER(swe_config), i64, C.c_int, pp]),
+        "swe_batch_admit": (C.c_int, [vp, vp, i64, C.c_double, C.POINTER(C.c_int32)]),
+        "swe_batch_tick": (C.c_int, [vp, i64]),
+        "swe_batch_sync": (C.c_int, [vp]),
+        "swe_batch_query": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int64), dp, C.POINTER(C.c_int)]),
+        "swe_batch_retire": (C.c_int, [vp, C.c_int32]),
+        "swe_batch_tune": (C.c_int, [vp, C.c_int]),
+        "swe_batch_tile_config": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "swe_batch_free_bytes": (C.c_int64, [vp]),
+        "swe_batch_resident": (C.c_int, [vp]),
+        "swe_batch_last_error": (C.c_char_p, [vp]),
+        "swe_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -268,3 +280,74 @@ def context_for(problem, precision=SWE_FP64, separate=0, stream_base=None, strea
     if separate or np.any(problem.p != problem.p_max):
         ctx.set_order(problem.p)
     return ctx
+
+
+class Batch:
+    """Many independent instances advanced together (see swe_batch_* in the header)."""
+
+    def __init__(self, precision=SWE_FP64, budget_bytes=64 << 30, max_instances=1024, stream=None):
+        self.L = lib()
+        cfg = Config(precision=precision, stream_base=stream)
+        self._c = cfg.to_c()
+        h = C.c_void_p()
+        st = self.L.swe_batch_create(C.byref(self._c), int(budget_bytes), int(max_instances), C.byref(h))
+        if st != SWE_OK:
+            raise SweError(st, "swe_batch_create failed")
+        self.h = h
+        self.members = {}
+
+    def _check(self, st):
+        if st != SWE_OK:
+            raise SweError(st, self.L.swe_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.L.swe_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def admit(self, ctx: Context, nsteps: int, dt: float) -> int:
+        slot = C.c_int32()
+        self._check(self.L.swe_batch_admit(self.h, ctx.h, int(nsteps), float(dt), C.byref(slot)))
+        self.members[slot.value] = ctx
+        return slot.value
+
+    def tick(self, nsteps: int):
+        self._check(self.L.swe_batch_tick(self.h, int(nsteps)))
+
+    def sync(self):
+        self._check(self.L.swe_batch_sync(self.h))
+
+    def query(self, slot: int):
+        left, t, failed = C.c_int64(), C.c_double(), C.c_int()
+        self._check(self.L.swe_batch_query(self.h, int(slot), C.byref(left), C.byref(t), C.byref(failed)))
+        return left.value, t.value, bool(failed.value)
+
+    def retire(self, slot: int) -> Context:
+        self._check(self.L.swe_batch_retire(self.h, int(slot)))
+        return self.members.pop(slot)
+
+    def tune(self, reps: int = 3):
+        self._check(self.L.swe_batch_tune(self.h, int(reps)))
+
+    def tile_config(self, p: int):
+        t, g = C.c_int(), C.c_int()
+        self._check(self.L.swe_batch_tile_config(self.h, int(p), C.byref(t), C.byref(g)))
+        return t.value, g.value
+
+    def free_bytes(self) -> int:
+        return int(self.L.swe_batch_free_bytes(self.h))
+
+    def resident(self) -> int:
+        return int(self.L.swe_batch_resident(self.h))

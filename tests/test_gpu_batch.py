@@ -1,0 +1,89 @@
+"""Batched instances: each instance's result inside a batch (persistent
+launches over all resident instances, captured step replayed, membership
+changing between ticks, autotuned tiles) is bitwise the result of the same
+instance run on its own; admission respects the footprint budget."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2311_11348_amd import inputs as I
+from paper_2311_11348_amd import swe
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make_instances(count, seed, n_lo=200, n_hi=6000):
+    probs = []
+    for i in range(count):
+        prob = I.config_instance(seed * 100 + i, n_lo=n_lo, n_hi=n_hi)
+        probs.append(prob)
+    return probs
+
+
+def ctx_for(prob, precision):
+    ctx = swe.context_for(prob, precision=precision)
+    ctx.set_state_fn(prob.ic)
+    return ctx
+
+
+@pytest.mark.parametrize("precision", [swe.SWE_FP64, swe.SWE_FP32_WB])
+def test_batch_equals_alone(precision):
+    probs = make_instances(6, seed=7)
+    steps = [30, 17, 25, 40, 9, 33]
+    dts = [p.dt() for p in probs]
+    alone = []
+    for prob, n, dt in zip(probs, steps, dts):
+        ctx = ctx_for(prob, precision)
+        ctx.step(n, dt)
+        ctx.sync()
+        alone.append(ctx.state())
+        ctx.close()
+    ctxs = [ctx_for(p, precision) for p in probs]
+    with swe.Batch(precision=precision, budget_bytes=8 << 30, max_instances=16) as b:
+        slots = [b.admit(c, n, dt) for c, n, dt in zip(ctxs[:4], steps[:4], dts[:4])]
+        b.tick(5)
+        slots += [b.admit(c, n, dt) for c, n, dt in zip(ctxs[4:], steps[4:], dts[4:])]   # join mid-run
+        b.tick(10)
+        b.tune(reps=2)
+        b.tick(50)
+        b.sync()
+        for s, n in zip(slots, steps):
+            left, t, failed = b.query(s)
+            assert left == 0 and not failed
+        for s in slots:
+            b.retire(s)
+        assert b.resident() == 0
+    for i, (ctx, (ref, tref)) in enumerate(zip(ctxs, alone)):
+        got, t = ctx.state()
+        say(f"instance {i}: ne={ctx.ne} p={probs[i].p_max} equal={np.array_equal(got, ref)} t={t:.3f}/{tref:.3f}")
+        assert np.array_equal(got, ref), i
+        assert t == tref
+        ctx.close()
+
+
+def test_batch_admission_budget():
+    probs = make_instances(3, seed=9)
+    ctxs = [ctx_for(p, swe.SWE_FP32_WB) for p in probs]
+    need = [swe.swe_footprint_bytes(c.ne, p.p_max, swe.SWE_FP32_WB) for c, p in zip(ctxs, probs)]
+    budget = need[0] + need[1] // 2
+    with swe.Batch(precision=swe.SWE_FP32_WB, budget_bytes=budget, max_instances=4) as b:
+        s0 = b.admit(ctxs[0], 3, probs[0].dt())
+        with pytest.raises(swe.SweError) as ei:
+            b.admit(ctxs[1], 3, probs[1].dt())
+        assert ei.value.status == swe.SWE_ENOMEM
+        with pytest.raises(swe.SweError):
+            ctxs[0].step(1, 1.0)       # resident contexts refuse their own stepping
+        b.tick(3)
+        b.retire(s0)
+        assert b.free_bytes() == budget
+        with pytest.raises(swe.SweError):      # precision mismatch
+            fp64 = ctx_for(probs[2], swe.SWE_FP64)
+            b.admit(fp64, 1, 1.0)
+    for c in ctxs:
+        c.close()
