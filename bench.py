@@ -1,6 +1,7 @@
 """Throughput of the DG shallow-water hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tidal|tsunami|static32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload tidal|tsunami|static32|batched|served]
 
 tidal (default): 512x512x2 triangulation of a 100 km square, nodes jittered
   by U(-0.2h, 0.2h) (seed 2), uniform order p = 2, bathymetry
@@ -14,6 +15,15 @@ tsunami: 256x256x2 jittered (seed 3), linear shelf 4000 m -> 50 m, 2 m hump,
   base order 1 and corrections on a second stream, FP32 path.
 static32: the tidal mesh with base order 1 and every 32nd element at order 2,
   order-separated on two streams, FP32 path.
+batched: 64 independent instances (seeds 4000+i), log-uniform 16k-500k
+  elements, p in {1,2,3}, tidal or hump, random smooth bathymetry, 300 steps
+  each; FP32 and FP64 batched against the plain FP64 solver run one instance
+  at a time; reports DOF-updates/s and solves/s.
+served: Poisson arrivals (20 req/s for 120 s, seed 5), 8k-260k elements,
+  p in {1,2,3}, 200-2000 steps; continuous batching with admission by
+  footprint; reports solves/s with p50/p99 latency, then the capacity of
+  the batched FP32 server and of the plain FP64 solver on the first 100
+  requests offered at once.
 
 A step is one SSP-RK2 step (two stages) of the whole hot path: volume +
 source + edge fluxes + stage update + u H = q (+ order update when adaptive).
@@ -23,6 +33,7 @@ are resident in HBM before the timed region.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -143,12 +154,161 @@ def run_separated(prob, precision, steps, warmup, chunk=50):
             "order_fractions": {f"p{i}": float(frac[i]) for i in range(4) if frac[i] > 0}}
 
 
+def run_batched(count, steps, warmup):
+    """Many independent instances: FP32 and FP64 batched (persistent tile
+    kernels, captured step, autotuned tiles) and the plain FP64 solver (one
+    instance at a time, one ordinary launch per stage).  Every instance runs
+    warmup + steps steps; the timed region holds the last ``steps`` of all of
+    them.  Inputs are resident before timing."""
+    import numpy as np
+    import torch
+    from paper_2311_11348_amd import inputs as I
+    from paper_2311_11348_amd import swe
+    t_prep = time.perf_counter()
+    probs = I.config_c4(count)
+    print(f"bench: {count} instances generated in {time.perf_counter() - t_prep:.1f} s, "
+          f"{sum(p.mesh.ne for p in probs)} elements", file=sys.stderr, flush=True)
+    stream = torch.cuda.Stream()
+    dofs = np.array([3 * K_OF_P[p.p_max] * p.mesh.ne for p in probs], dtype=np.float64)
+    dts = [p.dt() for p in probs]
+
+    def elapsed(fn):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1)
+
+    def batched(prec):
+        t0 = time.perf_counter()
+        ctxs = []
+        for p in probs:
+            c = swe.context_for(p, precision=prec)
+            c.set_state_fn(p.ic)
+            ctxs.append(c)
+        budget = sum(swe.swe_footprint_bytes(c.ne, p.p_max, prec) for c, p in zip(ctxs, probs)) + (1 << 30)
+        b = swe.Batch(precision=prec, budget_bytes=budget, max_instances=count, stream=stream.cuda_stream)
+        slots = [b.admit(c, steps + warmup, dt) for c, dt in zip(ctxs, dts)]
+        b.tune(reps=3)
+        tiles = {p: b.tile_config(p) for p in range(4)}
+        b.tick(warmup)
+        b.sync()
+        print(f"bench: batched precision {prec} ready after {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+
+        def run():
+            b.tick(steps)
+        ms = elapsed(run)
+        done = b.poll()
+        assert len(done) == count and not any(f for _, f in done), done
+        out = []
+        for s, c in zip(slots, ctxs):
+            b.retire(s)
+            out.append(c.state()[0][:, 0].copy())
+            c.close()
+        b.close()
+        return ms, out, tiles
+
+    def plain_fp64():
+        ms, out = 0.0, []
+        for p, dt in zip(probs, dts):
+            c = swe.context_for(p, precision=swe.SWE_FP64, stream_base=stream.cuda_stream)
+            c.set_state_fn(p.ic)
+            c.step(warmup, dt)
+            c.sync()
+            torch.cuda.synchronize()
+
+            def run():
+                c.step(steps, dt)
+            ms += elapsed(run)
+            c.sync()
+            out.append(c.state()[0][:, 0].copy())
+            c.close()
+        return ms, out
+
+    ms32, xi32, tiles = batched(swe.SWE_FP32_WB)
+    ms64, xi64, _ = batched(swe.SWE_FP64)
+    msp, xip = plain_fp64()
+    d64 = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(xi64, xip))
+    err = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(xi32, xi64))
+    upd = dofs.sum() * 2 * steps
+    word_bytes = {4: 0.0, 8: 0.0}
+    for w in word_bytes:
+        word_bytes[w] = sum(p.mesh.ne * stage_bytes_per_element(p.p_max, w, p.mesh.nv, p.mesh.ne)
+                            for p in probs) * 2 * steps
+    ach = word_bytes[4] / (ms32 * 1e-3) / 1e9
+
+    def leg(ms, word):
+        return {"solves_per_s": count / (ms * 1e-3), "value": upd / (ms * 1e-3), "ms_total": ms,
+                "hbm_gbs": word_bytes[word] / (ms * 1e-3) / 1e9}
+    k = np.bincount([p.p_max for p in probs], minlength=4)
+    return {"value": upd / (ms32 * 1e-3), "ms_per_step": ms32 / steps,
+            "solves_per_s": count / (ms32 * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_batch_stage<P,float> over all orders + k_batch_clock (whole step)"},
+            "fp64_batched": leg(ms64, 8), "plain_fp64": leg(msp, 8),
+            "speedup_solves_vs_plain_fp64": msp / ms32,
+            "fp32_xi_rel_l2_vs_fp64_max": err, "fp64_batched_vs_plain_xi_rel_l2_max": d64,
+            "tiles": {f"p{p}": {"tile": t[0], "grid": t[1]} for p, t in tiles.items() if k[p] > 0},
+            "elements": int(sum(p.mesh.ne for p in probs)),
+            "orders": {f"p{p}": int(k[p]) for p in range(4) if k[p] > 0}}
+
+
+def run_served(duration, rate, capacity_requests, tick_steps):
+    """Continuous batching over a Poisson request trace (FP32 with FP64
+    well-balancing), then the capacity of the batched FP32 server and of the
+    plain FP64 solver on the same first requests, all offered at once."""
+    import torch
+    from paper_2311_11348_amd import inputs as I
+    from paper_2311_11348_amd import swe
+    from paper_2311_11348_amd.serve import GpuExecutor, PlainExecutor, requests_from_trace, serve
+    stream = torch.cuda.Stream()
+    trace = I.request_trace(rate=rate, duration=duration)
+    reqs = requests_from_trace(trace)
+    budget = 64 << 30
+    print(f"bench: served trace {len(reqs)} requests over {duration} s", file=sys.stderr, flush=True)
+    last = [0.0]
+
+    def progress(t, n):
+        if t - last[0] > 10.0:
+            last[0] = t
+            print(f"bench: t={t:.0f} s, {n} resident", file=sys.stderr, flush=True)
+    ex = GpuExecutor(swe.SWE_FP32_WB, budget, max_instances=1024, stream=stream.cuda_stream, keep_state=False)
+    st = serve(reqs, ex, tick_steps=tick_steps, on_tick=progress)
+    ex.close()
+    main = st.summary()
+    print(f"bench: served {main}", file=sys.stderr, flush=True)
+    cap = []
+    for mk in ("batched_fp32", "plain_fp64"):
+        sub = requests_from_trace([dataclasses.replace(t, arrival=0.0) for t in trace[:capacity_requests]])
+        if mk == "batched_fp32":
+            e = GpuExecutor(swe.SWE_FP32_WB, budget, max_instances=1024, stream=stream.cuda_stream,
+                            keep_state=False)
+            s2 = serve(sub, e, tick_steps=tick_steps, on_tick=progress)
+            e.close()
+        else:
+            e = PlainExecutor(swe.SWE_FP64, stream=stream.cuda_stream, keep_state=False)
+            s2 = serve(sub, e, tick_steps=1 << 30, on_tick=progress)
+        sm = s2.summary()
+        print(f"bench: capacity {mk} {sm}", file=sys.stderr, flush=True)
+        cap.append((mk, sm))
+    return main, dict(cap)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", choices=["tidal", "tsunami", "static32"], default="tidal")
+    ap.add_argument("--workload", choices=["tidal", "tsunami", "static32", "batched", "served"], default="tidal")
+    ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--duration", type=float, default=120.0)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--capacity-requests", type=int, default=100)
+    ap.add_argument("--tick-steps", type=int, default=50)
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--p", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -195,6 +355,28 @@ def main() -> int:
                    config={"workload": f"tsunami: {n}x{n}x2 jittered, shelf 4000-50 m, 2 m hump, "
                                        "p in {1,2,3} by indicator (1e-3 m), base p=1 + corrections on 2 streams",
                            "elements": prob.mesh.ne, "order_fractions": r["order_fractions"]})
+    elif args.workload == "batched":
+        steps = args.steps if args.steps != 500 else 300
+        r = run_batched(args.instances, steps, args.warmup)
+        out.update(steps=steps, value=r.pop("value"), ms_per_step=r.pop("ms_per_step"),
+                   dtype="f32 (f64 bathymetry terms)", roofline=r.pop("roofline"),
+                   config={"workload": f"batched: {args.instances} independent instances, log-uniform "
+                                       "16k-500k elements, p in {1,2,3}, tidal or hump, random smooth "
+                                       f"bathymetry 50-4000 m, {steps} steps each, persistent tile kernels",
+                           **{k: r.pop(k) for k in ("elements", "orders", "tiles")}}, **r)
+    elif args.workload == "served":
+        main_s, cap = run_served(args.duration, args.rate, args.capacity_requests, args.tick_steps)
+        out.update(metric="served solves/s", unit="solves/s", value=main_s["solves_per_s"],
+                   ms_per_step=None, steps=None, warmup=None, dtype="f32 (f64 bathymetry terms)",
+                   p50_latency_s=main_s["p50_latency_s"], p99_latency_s=main_s["p99_latency_s"],
+                   served=main_s, capacity=cap,
+                   speedup_solves_vs_plain_fp64=cap["batched_fp32"]["solves_per_s"]
+                   / max(cap["plain_fp64"]["solves_per_s"], 1e-30),
+                   config={"workload": f"served: Poisson {args.rate:g} req/s for {args.duration:g} s, "
+                                       "8k-260k elements log-uniform, p in {1,2,3}, 200-2000 steps, "
+                                       "tidal or hump; admission by resident footprint (64 GiB); "
+                                       f"{args.tick_steps} steps per tick; capacity legs: first "
+                                       f"{args.capacity_requests} requests offered at once"})
     else:
         n = args.n or 512
         prob = I.config_c2(n=n, p=2)

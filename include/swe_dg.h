@@ -170,7 +170,9 @@ void swe_destroy(swe_ctx *ctx);
  * Batches: many independent instances advanced together.  Every resident
  * instance of one order is covered by one persistent launch per RK stage;
  * each instance keeps its own time, step size, forcing and step budget on
- * the device, so one captured step (a HIP graph) serves any resident set.
+ * the device, so one step graph (built from kernel nodes, no stream capture,
+ * and replayed) serves any resident set.  Other host threads may create and
+ * fill contexts while a batch runs.
  * Members are ordinary contexts (precision equal to the batch's, one uniform
  * order p_max, not separated, not adaptive, no extra source) prepared with
  * swe_set_mesh / swe_set_bathymetry / swe_set_open_boundary (at most 4
@@ -202,6 +204,11 @@ swe_status swe_batch_sync(swe_batch *b);
 /* Steps left, current time and failure flag (non-finite value or
  * non-positive mean depth) of the instance in slot; synchronises. */
 swe_status swe_batch_query(swe_batch *b, int32_t slot, int64_t *steps_left, double *t, int *failed);
+
+/* Resident slots that are done (step budget used up) or failed, in slot
+ * order: slots[0 .. *n-1] (at most max entries), failed[k] = 1 if slots[k]
+ * was flagged.  One synchronising read for the whole batch. */
+swe_status swe_batch_poll(swe_batch *b, int32_t *slots, int32_t *failed, int max, int *n);
 
 /* Release the slot; the member context keeps its state and gets back its
  * time (and the failed state if flagged) and can be used on its own again. */

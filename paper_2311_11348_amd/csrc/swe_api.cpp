@@ -1013,7 +1013,7 @@ struct swe_batch {
     int ncu = 256;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
-    int captured_orders = -1;             // bit p set: order p launched by the captured step
+    int graph_orders = -1;             // bit p set: order p launched by the step graph
     std::string err;
 };
 
@@ -1041,7 +1041,7 @@ void drop_graph(swe_batch *b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->gexec = nullptr;
     b->graph = nullptr;
-    b->captured_orders = -1;
+    b->graph_orders = -1;
 }
 
 // Grow the pool of order p to hold at least need elements (capacity doubles).
@@ -1127,7 +1127,7 @@ swe_status upload_tiles(swe_batch *b)
     BHIP_TRY(b, hipStreamSynchronize(b->s));
     int present = 0;
     for (int p = 0; p < 4; ++p) present |= b->ntiles[p] ? 1 << p : 0;
-    if (present != b->captured_orders) drop_graph(b);   // the captured step launches other orders
+    if (present != b->graph_orders) drop_graph(b);   // the step graph launches other orders
     return SWE_OK;
 }
 
@@ -1148,7 +1148,7 @@ BatchArgs batch_args(const swe_batch *b, int p)
 // runs in the persistent multi-instance kernel.
 bool per_instance(const swe_batch *b, int p) { return p == 3 && !b->fp32; }
 
-hipError_t enqueue_instance_stage(swe_batch *b, int i, int mode)
+hipError_t enqueue_instance_stage(swe_batch *b, int i, int mode, Sink &k)
 {
     const swe_batch::Member &m = b->mem[i];
     const PoolView &v = b->pool[m.order].v;
@@ -1170,44 +1170,46 @@ hipError_t enqueue_instance_stage(swe_batch *b, int i, int mode)
     a.flag = b->d_flags + i;
     a.inst = b->d_inst + i;
     a.e_off = (int)m.first;
-    return launch_stage(m.order, false, mode, false, &a, b->s);
+    return launch_stage(m.order, false, mode, false, &a, k);
 }
 
-hipError_t enqueue_batch_step(swe_batch *b)
+hipError_t enqueue_batch_step(swe_batch *b, Sink &k)
 {
-    hipError_t e = launch_batch_clock(b->d_inst, b->cap, b->s);
+    hipError_t e = launch_batch_clock(b->d_inst, b->d_flags, b->cap, k);
     for (int mode = MODE_STAGE1; mode <= MODE_STAGE2 && e == hipSuccess; ++mode)
         for (int p = 0; p < 4 && e == hipSuccess; ++p) {
             if (b->ntiles[p] == 0) continue;
             if (per_instance(b, p)) {
                 for (int i = 0; i < b->cap && e == hipSuccess; ++i)
-                    if (b->mem[i].ctx && b->mem[i].order == p) e = enqueue_instance_stage(b, i, mode);
+                    if (b->mem[i].ctx && b->mem[i].order == p) e = enqueue_instance_stage(b, i, mode, k);
                 continue;
             }
             // the kernels read the tile counts from device memory, so the grid
             // need not match the current resident set
-            e = launch_batch_stage(p, b->fp32, mode, b->tile[p], batch_args(b, p), b->grid[p], b->s);
+            e = launch_batch_stage(p, b->fp32, mode, b->tile[p], batch_args(b, p), b->grid[p], k);
         }
     return e;
 }
 
-// Capture one step as a graph; the kernels read everything that changes
-// (times, budgets, tile counts) from device memory.
-swe_status capture_step(swe_batch *b)
+// Build one step as a graph of kernel nodes in launch order (no stream
+// capture); the kernels read everything that changes (times, budgets, tile
+// counts) from device memory.
+swe_status build_step_graph(swe_batch *b)
 {
     drop_graph(b);
-    BHIP_TRY(b, hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue_batch_step(b);
     hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(b->s, &g);
-    if (e != hipSuccess || e2 != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return bfail(b, SWE_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    BHIP_TRY(b, hipGraphCreate(&g, 0));
+    Sink k;
+    k.g = g;
+    const hipError_t e = enqueue_batch_step(b, k);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return bfail(b, SWE_EDEVICE, std::string("step graph: ") + hipGetErrorString(e));
     }
     b->graph = g;
     BHIP_TRY(b, hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
-    b->captured_orders = 0;
-    for (int p = 0; p < 4; ++p) b->captured_orders |= b->ntiles[p] ? 1 << p : 0;
+    b->graph_orders = 0;
+    for (int p = 0; p < 4; ++p) b->graph_orders |= b->ntiles[p] ? 1 << p : 0;
     return SWE_OK;
 }
 
@@ -1403,7 +1405,7 @@ swe_status swe_batch_admit(swe_batch *b, swe_ctx *c, int64_t nsteps, double dt, 
     b->used += bytes;
     c->batch = b;
     c->slot = i;
-    if (per_instance(b, p)) drop_graph(b);   // the captured step launches each such instance
+    if (per_instance(b, p)) drop_graph(b);   // the step graph launches each such instance
     st = upload_tiles(b);
     if (st) return st;
     *slot = i;
@@ -1415,7 +1417,7 @@ swe_status swe_batch_tick(swe_batch *b, int64_t nsteps)
     if (!b || nsteps < 0) return SWE_EINVAL;
     if (nsteps == 0 || swe_batch_resident(b) == 0) return SWE_OK;
     if (!b->gexec) {
-        swe_status st = capture_step(b);
+        swe_status st = build_step_graph(b);
         if (st) return st;
     }
     for (int64_t k = 0; k < nsteps; ++k) BHIP_TRY(b, hipGraphLaunch(b->gexec, b->s));
@@ -1439,6 +1441,26 @@ swe_status swe_batch_query(swe_batch *b, int32_t slot, int64_t *steps_left, doub
     if (steps_left) *steps_left = b->h_inst[slot].steps_left;
     if (t) *t = b->h_inst[slot].t;
     if (failed) *failed = f;
+    return SWE_OK;
+}
+
+swe_status swe_batch_poll(swe_batch *b, int32_t *slots, int32_t *failed, int max, int *n)
+{
+    if (!b || !slots || !failed || !n || max < 0) return SWE_EINVAL;
+    std::vector<int> flags(b->cap);
+    BHIP_TRY(b, hipMemcpyAsync(b->h_inst.data(), b->d_inst, sizeof(InstDesc) * b->cap, hipMemcpyDeviceToHost, b->s));
+    BHIP_TRY(b, hipMemcpyAsync(flags.data(), b->d_flags, sizeof(int) * b->cap, hipMemcpyDeviceToHost, b->s));
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
+    int k = 0;
+    for (int i = 0; i < b->cap && k < max; ++i) {
+        if (!b->mem[i].ctx) continue;
+        if (b->h_inst[i].steps_left <= 0 || flags[i]) {
+            slots[k] = i;
+            failed[k] = flags[i] ? 1 : 0;
+            ++k;
+        }
+    }
+    *n = k;
     return SWE_OK;
 }
 
@@ -1486,6 +1508,8 @@ swe_status swe_batch_tune(swe_batch *b, int reps)
     // buffer 0 and writes buffer 1 only, so the timing launches leave the
     // state untouched; the clock fields are restored afterwards
     std::vector<InstDesc> saved(b->h_inst);
+    std::vector<int> flags(b->cap);
+    BHIP_TRY(b, hipMemcpy(flags.data(), b->d_flags, sizeof(int) * b->cap, hipMemcpyDeviceToHost));
     for (int i = 0; i < b->cap; ++i) {
         if (!b->mem[i].ctx) continue;
         swe_status st = get_desc(b, i);
@@ -1499,7 +1523,7 @@ swe_status swe_batch_tune(swe_batch *b, int reps)
     BHIP_TRY(b, hipEventCreate(&e0));
     BHIP_TRY(b, hipEventCreate(&e1));
     const int tiles[3] = {64, 128, 256};
-    const int mult[4] = {1, 2, 4, 8};
+    const int mult[5] = {1, 2, 4, 8, 0};    // 0: one block per tile of the pool's capacity
     swe_status st = SWE_OK;
     for (int p = 0; p < 4 && st == SWE_OK; ++p) {
         bool any = false;
@@ -1510,12 +1534,15 @@ swe_status swe_batch_tune(swe_batch *b, int reps)
         for (int ti = 0; ti < 3 && st == SWE_OK; ++ti) {
             b->tile[p] = tiles[ti];
             st = upload_tiles(b);
-            for (int mi = 0; mi < 4 && st == SWE_OK; ++mi) {
-                const int grid = std::max(1, std::min(b->ntiles[p], mult[mi] * b->ncu * 256 / tiles[ti]));
-                hipError_t e = launch_batch_stage(p, b->fp32, MODE_STAGE1, tiles[ti], batch_args(b, p), grid, b->s);
+            for (int mi = 0; mi < 5 && st == SWE_OK; ++mi) {
+                const int grid = mult[mi] ? std::max(1, std::min(b->ntiles[p], mult[mi] * b->ncu * 256 / tiles[ti]))
+                                          : (int)(b->pool[p].v.cap / tiles[ti] + 1);
+                Sink k;
+                k.s = b->s;
+                hipError_t e = launch_batch_stage(p, b->fp32, MODE_STAGE1, tiles[ti], batch_args(b, p), grid, k);
                 if (e == hipSuccess) e = hipEventRecord(e0, b->s);
                 for (int r = 0; r < reps && e == hipSuccess; ++r)
-                    e = launch_batch_stage(p, b->fp32, MODE_STAGE1, tiles[ti], batch_args(b, p), grid, b->s);
+                    e = launch_batch_stage(p, b->fp32, MODE_STAGE1, tiles[ti], batch_args(b, p), grid, k);
                 if (e == hipSuccess) e = hipEventRecord(e1, b->s);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float ms = 0.f;
@@ -1535,8 +1562,9 @@ swe_status swe_batch_tune(swe_batch *b, int reps)
         swe_status s2 = put_desc(b, i);
         if (st == SWE_OK) st = s2;
     }
-    // stage 1 also checked depths: start the flags of the real run clean
-    BHIP_TRY(b, hipMemsetAsync(b->d_flags, 0, sizeof(int) * b->cap, b->s));
+    // stage 1 also checked depths: the flags go back to what the real run had
+    BHIP_TRY(b, hipMemcpyAsync(b->d_flags, flags.data(), sizeof(int) * b->cap, hipMemcpyHostToDevice, b->s));
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
     if (st == SWE_OK) st = upload_tiles(b);
     drop_graph(b);
     return st;

@@ -105,7 +105,19 @@ struct BatchArgs {
 };
 
 // Launchers (defined in swe_kernels.hip).  Return hipSuccess or the launch error.
+// Where a launch goes: a stream, or (g set) a kernel node appended to a graph
+// under construction, after the node appended before it.  Graphs built this
+// way need no stream capture, so other host threads may keep calling HIP
+// (allocations, copies) while a step graph is being built.
+struct Sink {
+    hipStream_t s = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphNode_t last = nullptr;
+};
+hipError_t emit(Sink &k, const void *fn, dim3 grid, dim3 block, void **args);
+
 hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, hipStream_t s);
+hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, Sink &k);
 hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, hipStream_t s);
 hipError_t launch_epi(int p, int b, bool fp32, int mode, const void *args, int grid, hipStream_t s);
 hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s);
@@ -116,8 +128,8 @@ hipError_t launch_apply_order(int pm, bool fp32, const void *args, const signed 
 hipError_t launch_mass(const MeshView &m, bool fp32, const void *C, double *partial,
                        double *out, hipStream_t s);
 int mass_partials(int ne);
-hipError_t launch_batch_stage(int p, bool fp32, int mode, int tile, const BatchArgs &b, int grid, hipStream_t s);
-hipError_t launch_batch_clock(InstDesc *inst, int n, hipStream_t s);
+hipError_t launch_batch_stage(int p, bool fp32, int mode, int tile, const BatchArgs &b, int grid, Sink &k);
+hipError_t launch_batch_clock(InstDesc *inst, const int *flags, int n, Sink &k);
 // copy an instance's mesh arrays into a pool, offsetting vertex and element ids
 hipError_t launch_relocate(const int *ev, const int *nb, const unsigned char *nbk, int ne, int stride,
                            const PoolView &pool, int first, int vbase, hipStream_t s);

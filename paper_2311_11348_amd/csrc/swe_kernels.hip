@@ -790,8 +790,8 @@ k_stage(StageArgs<Real> a)
 // resident instance of that order.  All instances of an order share pooled
 // arrays passed as kernel arguments; a tile (TILE consecutive elements of one
 // instance) only reads its instance's scalars (step, open-sea elevation,
-// physics, clock).  Block b walks a contiguous chunk of the tile list, so the
-// tiles of one instance stay on one XCD.  Instances whose clock says they are
+// physics, clock).  Each XCD walks a contiguous eighth of the tile list, so
+// the neighbour gathers of an instance's elements stay in one L2.  Instances whose clock says they are
 // done are skipped: one captured step serves any resident set.
 template <int P, typename Real, int MODE, int TILE>
 __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(waves_target<P, Real>(), 8)))
@@ -801,9 +801,17 @@ k_batch_stage(BatchArgs b)
     __shared__ Real sR[3][K][NT];
     load_trace_table<K, NT, Real>(sR);
     __syncthreads();
+    // XCD x (blocks x, x+8, ...) owns the contiguous eighth [lo, hi) of the
+    // tile list and splits it into contiguous chunks, one per block; with one
+    // block per tile or more, each block takes a single tile.  Grids of fewer
+    // than 8 blocks split the list among the blocks there are.
     const int ntiles = b.ntiles[0];
-    const int per = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int t0 = (int)blockIdx.x * per, t1 = t0 + per < ntiles ? t0 + per : ntiles;
+    const int nx = gridDim.x < 8u ? (int)gridDim.x : 8;
+    const int x = (int)blockIdx.x % nx, i = (int)blockIdx.x / nx;
+    const int bx = ((int)gridDim.x - x + nx - 1) / nx;
+    const int lo = (int)((long long)ntiles * x / nx), hi = (int)((long long)ntiles * (x + 1) / nx);
+    const int per = (hi - lo + bx - 1) / bx;
+    const int t0 = lo + i * per, t1 = t0 + per < hi ? t0 + per : hi;
     StageArgs<Real> a;
     a.m.ne = 0;
     a.m.stride = b.pool.cap;
@@ -849,12 +857,13 @@ __global__ void __launch_bounds__(BLOCK) k_relocate(const int *ev, const int *nb
 
 // Per-step clock of every resident instance: open-sea elevation at the two
 // stage times, then advance its time and step budget.
-__global__ void __launch_bounds__(BLOCK) k_batch_clock(InstDesc *inst, int n)
+__global__ void __launch_bounds__(BLOCK) k_batch_clock(InstDesc *inst, const int *flags, int n)
 {
     const int i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     InstDesc &I = inst[i];
-    const int run = I.active && I.steps_left > 0;
+    // a failed instance (non-positive depth or a non-finite value) stops where it failed
+    const int run = I.active && I.steps_left > 0 && flags[i] == 0;
     I.run = run;
     if (!run) return;
     double x1 = 0.0, x2 = 0.0;
@@ -1151,19 +1160,20 @@ __global__ void __launch_bounds__(BLOCK) k_mass_final(const double *partial, int
 }
 
 template <int P, typename Real, bool SEP>
-hipError_t stage_p(int mode, const void *args, hipStream_t s)
+hipError_t stage_p(int mode, const void *args, Sink &s)
 {
-    const StageArgs<Real> &a = *static_cast<const StageArgs<Real> *>(args);
+    StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
     if (a.m.ne <= 0) return hipSuccess;
     const dim3 grid((a.m.ne + BLOCK - 1) / BLOCK), block(BLOCK);
-    if (mode == MODE_RHS) hipLaunchKernelGGL((k_stage<P, Real, MODE_RHS, false>), grid, block, 0, s, a);
-    else if (mode == MODE_STAGE1) hipLaunchKernelGGL((k_stage<P, Real, MODE_STAGE1, SEP>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_stage<P, Real, MODE_STAGE2, SEP>), grid, block, 0, s, a);
-    return hipGetLastError();
+    void *kargs[] = {&a};
+    const void *fn = mode == MODE_RHS      ? reinterpret_cast<const void *>(&k_stage<P, Real, MODE_RHS, false>)
+                     : mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_stage<P, Real, MODE_STAGE1, SEP>)
+                                           : reinterpret_cast<const void *>(&k_stage<P, Real, MODE_STAGE2, SEP>);
+    return emit(s, fn, grid, block, kargs);
 }
 
 template <typename Real>
-hipError_t stage_r(int p, int mode, bool sep, const void *args, hipStream_t s)
+hipError_t stage_r(int p, int mode, bool sep, const void *args, Sink &s)
 {
     if (sep) {
         switch (p) {
@@ -1255,9 +1265,32 @@ hipError_t usolve_r(int p, const void *args, hipStream_t s)
 
 }  // namespace
 
+hipError_t emit(Sink &k, const void *fn, dim3 grid, dim3 block, void **args)
+{
+    if (!k.g) return hipLaunchKernel(fn, grid, block, args, 0, k.s);
+    hipKernelNodeParams prm{};
+    prm.func = const_cast<void *>(fn);
+    prm.gridDim = grid;
+    prm.blockDim = block;
+    prm.sharedMemBytes = 0;
+    prm.kernelParams = args;      // copied into the node
+    prm.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    const hipError_t e = hipGraphAddKernelNode(&node, k.g, k.last ? &k.last : nullptr, k.last ? 1 : 0, &prm);
+    if (e == hipSuccess) k.last = node;
+    return e;
+}
+
+hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, Sink &k)
+{
+    return fp32 ? stage_r<float>(p, mode, sep, args, k) : stage_r<double>(p, mode, sep, args, k);
+}
+
 hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, hipStream_t s)
 {
-    return fp32 ? stage_r<float>(p, mode, sep, args, s) : stage_r<double>(p, mode, sep, args, s);
+    Sink k;
+    k.s = s;
+    return launch_stage(p, fp32, mode, sep, args, k);
 }
 
 hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, hipStream_t s)
@@ -1282,15 +1315,17 @@ int mass_partials(int ne) { return (ne + BLOCK - 1) / BLOCK; }
 
 namespace {
 template <int P, typename Real, int TILE>
-hipError_t batch_pt(int mode, const BatchArgs &b, int grid, hipStream_t s)
+hipError_t batch_pt(int mode, const BatchArgs &b, int grid, Sink &s)
 {
-    if (mode == MODE_STAGE1) hipLaunchKernelGGL((k_batch_stage<P, Real, MODE_STAGE1, TILE>), dim3(grid), dim3(TILE), 0, s, b);
-    else hipLaunchKernelGGL((k_batch_stage<P, Real, MODE_STAGE2, TILE>), dim3(grid), dim3(TILE), 0, s, b);
-    return hipGetLastError();
+    BatchArgs a = b;
+    void *kargs[] = {&a};
+    const void *fn = mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_batch_stage<P, Real, MODE_STAGE1, TILE>)
+                                         : reinterpret_cast<const void *>(&k_batch_stage<P, Real, MODE_STAGE2, TILE>);
+    return emit(s, fn, dim3(grid), dim3(TILE), kargs);
 }
 
 template <typename Real, int TILE>
-hipError_t batch_t(int p, int mode, const BatchArgs &b, int grid, hipStream_t s)
+hipError_t batch_t(int p, int mode, const BatchArgs &b, int grid, Sink &s)
 {
     switch (p) {
     case 0: return batch_pt<0, Real, TILE>(mode, b, grid, s);
@@ -1302,7 +1337,7 @@ hipError_t batch_t(int p, int mode, const BatchArgs &b, int grid, hipStream_t s)
 }
 
 template <typename Real>
-hipError_t batch_r(int p, int mode, int tile, const BatchArgs &b, int grid, hipStream_t s)
+hipError_t batch_r(int p, int mode, int tile, const BatchArgs &b, int grid, Sink &s)
 {
     switch (tile) {
     case 64: return batch_t<Real, 64>(p, mode, b, grid, s);
@@ -1314,17 +1349,17 @@ hipError_t batch_r(int p, int mode, int tile, const BatchArgs &b, int grid, hipS
 
 }  // namespace
 
-hipError_t launch_batch_stage(int p, bool fp32, int mode, int tile, const BatchArgs &b, int grid, hipStream_t s)
+hipError_t launch_batch_stage(int p, bool fp32, int mode, int tile, const BatchArgs &b, int grid, Sink &k)
 {
     if (grid <= 0) return hipSuccess;
-    return fp32 ? batch_r<float>(p, mode, tile, b, grid, s) : batch_r<double>(p, mode, tile, b, grid, s);
+    return fp32 ? batch_r<float>(p, mode, tile, b, grid, k) : batch_r<double>(p, mode, tile, b, grid, k);
 }
 
-hipError_t launch_batch_clock(InstDesc *inst, int n, hipStream_t s)
+hipError_t launch_batch_clock(InstDesc *inst, const int *flags, int n, Sink &k)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_clock, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, inst, n);
-    return hipGetLastError();
+    void *kargs[] = {&inst, &flags, &n};
+    return emit(k, reinterpret_cast<const void *>(&k_batch_clock), dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), kargs);
 }
 
 hipError_t launch_relocate(const int *ev, const int *nb, const unsigned char *nbk, int ne, int stride,

@@ -286,22 +286,37 @@ def config_c3(n: int = 256, seed: int = 3) -> Problem:
                     friction_coef=CF_BAHAMAS, steps=1000, adapt=1, adapt_tau=1e-3)
 
 
-def config_instance(seed: int, n_lo: float = 16e3, n_hi: float = 500e3) -> Problem:
-    """One batched/served instance: log-uniform size, p in {1,2,3}, tidal or hump."""
-    rng = np.random.default_rng(seed)
-    N = math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))
-    n = max(2, int(round(math.sqrt(N / 2.0))))
-    p = int(rng.integers(1, 4))
-    tidal = bool(rng.integers(0, 2) == 0)
+def instance_mesh_n(n_elements: float) -> int:
+    """Side count n of the n x n x 2 mesh closest to ``n_elements`` triangles."""
+    return max(2, int(round(math.sqrt(n_elements / 2.0))))
+
+
+def instance_problem(rng: np.random.Generator, n_elements: float, p: int, tidal: bool, steps: int,
+                     name: str) -> Problem:
+    """A batched/served instance: ~n_elements jittered triangles of the 100 km
+    square, uniform order p, smooth random bathymetry 50-4000 m, Coriolis and
+    quadratic friction; tidal (lake at rest, west edge open, 0.5 m tide) or a
+    2 m Gaussian hump in a closed basin.  The mesh seed and the bathymetry are
+    drawn from ``rng``."""
+    n = instance_mesh_n(n_elements)
     mesh = structured_mesh(n, jitter=0.2, seed=int(rng.integers(0, 2**31 - 1)), open_west=tidal)
     bathy = bathy_random_smooth(rng)
     if tidal:
         ic, forcing = ic_rest(0.0), tide_forcing()
     else:
         ic, forcing = ic_gaussian(2.0, 2.0e4, L_DOMAIN / 4, L_DOMAIN / 2), Forcing()
-    return _problem(f"inst{seed}", mesh, bathy, ic, p, p, p, f_coriolis=CORIOLIS_BAHAMAS,
+    return _problem(name, mesh, bathy, ic, p, p, p, f_coriolis=CORIOLIS_BAHAMAS,
                     friction=FRICTION_QUADRATIC, friction_coef=CF_BAHAMAS, forcing=forcing,
-                    steps=300)
+                    steps=steps)
+
+
+def config_instance(seed: int, n_lo: float = 16e3, n_hi: float = 500e3) -> Problem:
+    """One batched instance: log-uniform size, p in {1,2,3}, tidal or hump, 300 steps."""
+    rng = np.random.default_rng(seed)
+    N = math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))
+    p = int(rng.integers(1, 4))
+    tidal = bool(rng.integers(0, 2) == 0)
+    return instance_problem(rng, N, p, tidal, 300, f"inst{seed}")
 
 
 def config_c4(count: int = 64, seed: int = 4) -> list:
@@ -334,6 +349,23 @@ def request_trace(rate: float = 20.0, duration: float = 120.0, seed: int = 5,
                            tidal=bool(r.integers(0, 2) == 0)))
         i += 1
     return out
+
+
+def request_problem(req: Request) -> Problem:
+    """The solve a served request describes: ~n_elements jittered triangles
+    (mesh seed from the request's seed), uniform order p; tidal requests take
+    the tidal workload's bathymetry, forcing and open west edge, hump requests
+    the tsunami workload's shelf and 2 m hump in a closed basin."""
+    rng = np.random.default_rng([req.seed, 1])
+    mesh = structured_mesh(instance_mesh_n(req.n_elements_target), jitter=0.2,
+                           seed=int(rng.integers(0, 2**31 - 1)), open_west=req.tidal)
+    if req.tidal:
+        bathy, ic, forcing = bathy_sincos(), ic_rest(0.0), tide_forcing()
+    else:
+        bathy, ic, forcing = bathy_shelf(), ic_gaussian(2.0, 2.0e4, L_DOMAIN / 4, L_DOMAIN / 2), Forcing()
+    return _problem(f"req{req.seed}", mesh, bathy, ic, req.p, req.p, req.p, f_coriolis=CORIOLIS_BAHAMAS,
+                    friction=FRICTION_QUADRATIC, friction_coef=CF_BAHAMAS, forcing=forcing,
+                    steps=req.steps)
 
 
 # ------------------------------------------------------------- random states

@@ -87,6 +87,7 @@ def lib() -> C.CDLL:
         "swe_batch_resident": (C.c_int, [vp]),
         "swe_batch_last_error": (C.c_char_p, [vp]),
         "swe_batch_destroy": (None, [vp]),
+        "swe_batch_poll": (C.c_int, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -333,6 +334,14 @@ class Batch:
         left, t, failed = C.c_int64(), C.c_double(), C.c_int()
         self._check(self.L.swe_batch_query(self.h, int(slot), C.byref(left), C.byref(t), C.byref(failed)))
         return left.value, t.value, bool(failed.value)
+
+    def poll(self, max_slots: int = 4096):
+        """Slots that are done or failed: list of (slot, failed)."""
+        slots = (C.c_int32 * max_slots)()
+        failed = (C.c_int32 * max_slots)()
+        n = C.c_int()
+        self._check(self.L.swe_batch_poll(self.h, slots, failed, max_slots, C.byref(n)))
+        return [(slots[i], bool(failed[i])) for i in range(n.value)]
 
     def retire(self, slot: int) -> Context:
         self._check(self.L.swe_batch_retire(self.h, int(slot)))
