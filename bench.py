@@ -59,6 +59,59 @@ def stage_bytes_per_element(p: int, word: int, nv: int, ne: int) -> float:
     return state + geo
 
 
+KERNEL_SOURCES = ("paper_2311_11348_amd/csrc/swe_kernels.hip", "paper_2311_11348_amd/csrc/swe_internal.h",
+                  "paper_2311_11348_amd/csrc/swe_tables.h", "paper_2311_11348_amd/build.py")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_p2_tidal512_traffic.txt")
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 over the sources and build flags that determine the kernels' code."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernels):
+    """HBM bytes per launch of the given kernels from the committed PMC summary
+    (FETCH_SIZE and WRITE_SIZE runs, each scaled by what the same counter reads
+    for a copy kernel of known size), averaged over the kernels; None when the
+    summary is missing or the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    fs = float(kv["copy_bytes"]) / (float(kv["copy_fetch_kib"]) * 1024.0)
+    ws = float(kv["copy_bytes"]) / (float(kv["copy_write_kib"]) * 1024.0)
+    vals = []
+    for k in kernels:
+        f, w = kv.get(f"fetch_kib[{k}]"), kv.get(f"write_kib[{k}]")
+        if f is None or w is None:
+            return None
+        vals.append(float(f) * 1024.0 * fs + float(w) * 1024.0 * ws)
+    return sum(vals) / len(vals)
+
+
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 3) -> None:
+    """An elementwise copy of nbytes (read nbytes, write nbytes), for scaling
+    the HBM byte counters of a profiled run."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def cpu_baseline(p: int, budget_s: float = 15.0):
     """The FP64 oracle (single thread) on a bounded sample of the same workload:
     the same problem family on a 64x64x2 mesh, timed over whole SSP-RK2 steps."""
@@ -114,10 +167,14 @@ def run_uniform(prob, precision, steps, warmup):
     launch_s = ms * 1e-3 / (2 * steps)
     bpe = stage_bytes_per_element(p, word, nv, ne)
     achieved = bpe * ne / launch_s / 1e9
+    real = "double" if word == 8 else "float"
+    traffic = measured_traffic([f"k_stage<{p}, {real}, {m}, false>" for m in (1, 2)]) if p == 2 and ne == 524288 else None
     return {"value": dof / launch_s, "ms_per_step": ms / steps,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": f"k_stage<{p},{'double' if word == 8 else 'float'}>",
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": traffic / 1e9 / launch_s if traffic is not None else None,
+                         "traffic_bytes_per_launch": traffic,
+                         "kernel": f"k_stage<{p},{real}>",
                          "bytes_per_launch": bpe * ne, "avg_launch_us": launch_s * 1e6}}
 
 
@@ -312,6 +369,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--p", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB elementwise copy first (scales PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (instances and "
@@ -330,6 +389,8 @@ def main() -> int:
     out = {"metric": "DOF-updates/s per RK stage", "unit": "DOF-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic"}
+    if args.copy_calibration:
+        copy_calibration()
     if args.workload == "tidal":
         n = args.n or 512
         prob = I.config_c2(n=n, p=args.p)
