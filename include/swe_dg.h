@@ -71,9 +71,17 @@ typedef struct {
     int adapt;              /* 0: static order map; 1: orders re-chosen every step by the indicator */
     double adapt_tau;       /* indicator threshold (m) when adapt = 1 */
     int separate;           /* 0: one full-order kernel per stage; 1: base and correction
-                               kernels on two streams (required for mixed orders) */
+                               kernels on two streams (the order separation of the
+                               paper); 2: order-partitioned: elements of order p_base
+                               with neighbours of order p_base in the base kernel, every
+                               other element's full stage in a kernel of its order, on
+                               parallel branches (same results, fewer dependent kernels) */
     void *stream_base;      /* hipStream_t for the base work, or NULL for a library-owned stream */
     void *stream_corr;      /* hipStream_t for the correction work, or NULL */
+    int step_graph;         /* how swe_step enqueues a step: 1 (default) one replayed HIP
+                               graph per step (forcing clock on the device) for separated and
+                               partitioned steps, plain launches for a fused step; 2 always
+                               the graph; 0 always kernel-by-kernel launches */
 } swe_config;
 
 /* Fill *cfg with defaults: FP64, p_base = p_max = 1, g = 9.81, no Coriolis,
@@ -126,7 +134,11 @@ swe_status swe_set_state_points(swe_ctx *ctx, double t0, const double *vals);
 swe_status swe_set_source(swe_ctx *ctx, const double *coef);
 
 /* Advance nsteps SSP-RK2 steps of size dt (s).  Work is enqueued on the
- * context's streams; errors detected on the device surface at swe_sync. */
+ * context's streams; errors detected on the device surface at swe_sync.
+ * With a step graph (see step_graph; at most 4 forcing constituents), one
+ * step is a graph of kernel nodes (base and correction branches joined
+ * where the scheme joins them) replayed nsteps times; stage times and the
+ * open-sea elevation are computed on the device from t0 + k dt. */
 swe_status swe_step(swe_ctx *ctx, int64_t nsteps, double dt);
 
 /* Wait for queued work; returns SWE_ESTATE if a stage produced a non-finite

@@ -73,6 +73,11 @@ struct swe_ctx {
     bool failed = false;
     int ncon = 0;
     double amp[NCON_MAX] = {0}, omega[NCON_MAX] = {0}, phase[NCON_MAX] = {0};
+    // replayed step: one graph per step, clock (time, forcing) on the device
+    InstDesc *d_inst = nullptr;
+    hipGraph_t step_graph = nullptr;
+    hipGraphExec_t step_exec = nullptr;
+    std::vector<long long> graph_key;     // what the step graph was built for
     std::string err;
 };
 
@@ -92,8 +97,20 @@ swe_status fail(swe_ctx *c, swe_status s, const std::string &msg)
                         std::string(#expr) + ": " + hipGetErrorString(e_));                      \
     } while (0)
 
+void drop_step_graph(swe_ctx *c)
+{
+    if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+    if (c->step_graph) (void)hipGraphDestroy(c->step_graph);
+    c->step_exec = nullptr;
+    c->step_graph = nullptr;
+    c->graph_key.clear();
+}
+
 void free_mesh(swe_ctx *c)
 {
+    drop_step_graph(c);
+    if (c->d_inst) (void)hipFree(c->d_inst);
+    c->d_inst = nullptr;
     void *ptrs[] = {c->d_vtx, c->d_ev, c->d_nb, c->d_nbk, c->d_p, c->d_C[0], c->d_C[1],
                     c->d_U[0], c->d_U[1], c->d_L, c->d_src, c->d_flag, c->d_part, c->d_mass,
                     c->d_inlist, c->d_Lb, c->d_Lc, c->d_list, c->d_cnt, c->d_pnew, c->d_I};
@@ -155,11 +172,62 @@ StageArgs<Real> make_args(const swe_ctx *c)
     return a;
 }
 
+// Where the kernels of a step go: the context's two streams joined by
+// events, or two branches of a step graph under construction (graph set).
+struct Lanes {
+    swe_ctx *c;
+    Sink a, b;           // base work, correction work
+    bool graph = false;
+    explicit Lanes(swe_ctx *cc) : c(cc)
+    {
+        a.s = c->s_base;
+        b.s = c->s_corr;
+    }
+    Lanes(swe_ctx *cc, hipGraph_t g) : c(cc), graph(true)
+    {
+        a.g = g;
+        b.g = g;
+    }
+    // the correction branch starts after everything enqueued on the base branch so far
+    hipError_t fork()
+    {
+        if (graph) {
+            b.ndep = a.ndep;
+            b.dep[0] = a.dep[0];
+            b.dep[1] = a.dep[1];
+            return hipSuccess;
+        }
+        const hipError_t e = hipEventRecord(c->ev_ready, c->s_base);
+        return e == hipSuccess ? hipStreamWaitEvent(c->s_corr, c->ev_ready, 0) : e;
+    }
+    // base work enqueued next waits for the correction branch
+    hipError_t join()
+    {
+        if (graph) return a.join(b) ? hipSuccess : hipErrorInvalidValue;
+        const hipError_t e = hipEventRecord(c->ev_corr, c->s_corr);
+        return e == hipSuccess ? hipStreamWaitEvent(c->s_base, c->ev_corr, 0) : e;
+    }
+
+    // stage time: from the host, or (graph) from the device clock of the step
+    template <typename Real>
+    void time(StageArgs<Real> &args, int stage, double t, double dt) const
+    {
+        if (graph) {
+            args.inst = c->d_inst;
+            args.stage = stage;
+        } else {
+            args.xihat = xi_hat(c, t);
+            args.dt = dt;
+        }
+    }
+};
+
 // launch one stage; in/out buffer indices follow the Shu-Osher form
 template <typename Real>
-hipError_t enqueue_stage(swe_ctx *c, int mode, int in, int out, double tstage, double dt,
-                         const void *Cn, void *Lout)
+hipError_t enqueue_stage(Lanes &L, int mode, int in, int out, double tstage, double dt, const void *Cn,
+                         void *Lout)
 {
+    swe_ctx *c = L.c;
     StageArgs<Real> a = make_args<Real>(c);
     a.Cin = static_cast<const Real *>(c->d_C[in]);
     a.Uin = static_cast<const Real *>(c->d_U[in]);
@@ -167,9 +235,16 @@ hipError_t enqueue_stage(swe_ctx *c, int mode, int in, int out, double tstage, d
     a.Cout = out >= 0 ? static_cast<Real *>(c->d_C[out]) : nullptr;
     a.Uout = out >= 0 ? static_cast<Real *>(c->d_U[out]) : nullptr;
     a.Lout = static_cast<Real *>(Lout);
-    a.xihat = xi_hat(c, tstage);
-    a.dt = dt;
-    return launch_stage(c->cfg.p_max, c->fp32, mode, false, &a, c->s_base);
+    L.time(a, mode == MODE_STAGE2 ? 1 : 0, tstage, dt);
+    return launch_stage(c->cfg.p_max, c->fp32, mode, false, &a, L.a);
+}
+
+template <typename Real>
+hipError_t enqueue_stage(swe_ctx *c, int mode, int in, int out, double tstage, double dt, const void *Cn,
+                         void *Lout)
+{
+    Lanes L(c);
+    return enqueue_stage<Real>(L, mode, in, out, tstage, dt, Cn, Lout);
 }
 
 bool separated(const swe_ctx *c) { return c->cfg.separate && c->cfg.p_base < c->cfg.p_max; }
@@ -184,14 +259,15 @@ int list_grid(const swe_ctx *c, int p)
 
 // Order adaptation at the start of a step, from the state in buffer 0.
 template <typename Real>
-hipError_t enqueue_adapt(swe_ctx *c, double tn)
+hipError_t enqueue_adapt(Lanes &L, double tn)
 {
+    swe_ctx *c = L.c;
     StageArgs<Real> a = make_args<Real>(c);
     a.Cin = static_cast<const Real *>(c->d_C[0]);
-    a.xihat = xi_hat(c, tn);
+    L.time(a, 0, tn, 0.0);
     a.cntw = c->d_cnt;
     hipError_t e = launch_indicator(c->fp32, &a, c->cfg.adapt_tau, c->cfg.p_base, c->cfg.p_max, nullptr,
-                                    c->d_pnew, c->s_base);
+                                    c->d_pnew, L.a);
     if (e != hipSuccess) return e;
     a.Cout = static_cast<Real *>(c->d_C[0]);
     a.Calt = static_cast<Real *>(c->d_C[1]);
@@ -199,16 +275,16 @@ hipError_t enqueue_adapt(swe_ctx *c, double tn)
     a.Ualt = static_cast<Real *>(c->d_U[1]);
     a.inlist = c->d_inlist;
     a.listw = c->d_list;
-    return launch_apply_order(c->cfg.p_max, c->fp32, &a, c->d_pnew, c->d_p, c->cfg.p_base, (int)c->ne,
-                              c->s_base);
+    return launch_apply_order(c->cfg.p_max, c->fp32, &a, c->d_pnew, c->d_p, c->cfg.p_base, (int)c->ne, L.a);
 }
 
-// Order-separated stage: base kernel over all elements (stream A) while the
-// corrections of the listed elements run on stream B; the epilogue of the
-// listed elements joins both on stream A.
+// Order-separated stage: base kernel over all elements (branch A) while the
+// corrections of the listed elements run on branch B; the epilogue of the
+// listed elements joins both on branch A.
 template <typename Real>
-hipError_t enqueue_separated(swe_ctx *c, int mode, int in, int out, double tstage, double dt)
+hipError_t enqueue_separated(Lanes &L, int mode, int in, int out, double tstage, double dt)
 {
+    swe_ctx *c = L.c;
     const int b = c->cfg.p_base, pm = c->cfg.p_max;
     StageArgs<Real> a = make_args<Real>(c);
     a.mixed = 0;
@@ -217,36 +293,130 @@ hipError_t enqueue_separated(swe_ctx *c, int mode, int in, int out, double tstag
     a.Cn = static_cast<const Real *>(c->d_C[0]);
     a.Cout = static_cast<Real *>(c->d_C[out]);
     a.Uout = static_cast<Real *>(c->d_U[out]);
-    a.xihat = xi_hat(c, tstage);
-    a.dt = dt;
+    L.time(a, mode == MODE_STAGE2 ? 1 : 0, tstage, dt);
     a.inlist = c->d_inlist;
     a.Lb = static_cast<Real *>(c->d_Lb);
     a.Lc = static_cast<Real *>(c->d_Lc);
-    hipError_t e = hipEventRecord(c->ev_ready, c->s_base);
+    hipError_t e = L.fork();
     if (e != hipSuccess) return e;
-    e = launch_stage(b, c->fp32, mode, true, &a, c->s_base);
-    if (e != hipSuccess) return e;
-    e = hipStreamWaitEvent(c->s_corr, c->ev_ready, 0);
+    e = launch_stage(b, c->fp32, mode, true, &a, L.a);
     if (e != hipSuccess) return e;
     for (int p = b; p <= pm; ++p) {
         if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
         a.list = c->d_list + c->list_off[p];
         a.count = c->d_cnt + p;
-        e = launch_corr(p, b, pm, c->fp32, &a, dt, list_grid(c, p), c->s_corr);
+        e = launch_corr(p, b, pm, c->fp32, &a, dt, list_grid(c, p), L.b);
         if (e != hipSuccess) return e;
     }
-    e = hipEventRecord(c->ev_corr, c->s_corr);
-    if (e != hipSuccess) return e;
-    e = hipStreamWaitEvent(c->s_base, c->ev_corr, 0);
+    e = L.join();
     if (e != hipSuccess) return e;
     for (int p = b; p <= pm; ++p) {
         if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
         a.list = c->d_list + c->list_off[p];
         a.count = c->d_cnt + p;
-        e = launch_epi(p, b, c->fp32, mode, &a, list_grid(c, p), c->s_base);
+        e = launch_epi(p, b, c->fp32, mode, &a, list_grid(c, p), L.a);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// Order-partitioned stage: the base kernel does every element of order
+// p_base whose neighbours are all of order p_base (branch A); each order's
+// listed elements get their full stage from a kernel of that order, all on
+// parallel branches; nothing needs joining afterwards but the next stage.
+template <typename Real>
+hipError_t enqueue_partitioned(Lanes &L, int mode, int in, int out, double tstage, double dt)
+{
+    swe_ctx *c = L.c;
+    const int b = c->cfg.p_base, pm = c->cfg.p_max;
+    StageArgs<Real> a = make_args<Real>(c);
+    a.mixed = 0;
+    a.Cin = static_cast<const Real *>(c->d_C[in]);
+    a.Uin = static_cast<const Real *>(c->d_U[in]);
+    a.Cn = static_cast<const Real *>(c->d_C[0]);
+    a.Cout = static_cast<Real *>(c->d_C[out]);
+    a.Uout = static_cast<Real *>(c->d_U[out]);
+    L.time(a, mode == MODE_STAGE2 ? 1 : 0, tstage, dt);
+    a.inlist = c->d_inlist;
+    a.skip_listed = 1;
+    hipError_t e = L.fork();
+    if (e != hipSuccess) return e;
+    const Sink origin = L.b;   // graph: what the stage starts after
+    e = launch_stage(b, c->fp32, mode, true, &a, L.a);
+    if (e != hipSuccess) return e;
+    a.skip_listed = 0;
+    Sink ends[4];
+    int nends = 0;
+    for (int p = b; p <= pm; ++p) {
+        if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
+        a.list = c->d_list + c->list_off[p];
+        a.count = c->d_cnt + p;
+        if (L.graph) {
+            // each order on a branch of its own
+            ends[nends] = origin;
+            e = launch_full(p, pm, c->fp32, mode, &a, list_grid(c, p), ends[nends]);
+            ++nends;
+        } else {
+            e = launch_full(p, pm, c->fp32, mode, &a, list_grid(c, p), L.b);
+        }
+        if (e != hipSuccess) return e;
+    }
+    if (!L.graph) return L.join();
+    for (int i = 0; i < nends; ++i)
+        if (!L.a.join(ends[i])) return hipErrorInvalidValue;
+    return hipSuccess;
+}
+
+// One SSP-RK2 step (order update first when adaptive).
+template <typename Real>
+hipError_t enqueue_step(Lanes &L, double tn, double dt)
+{
+    swe_ctx *c = L.c;
+    hipError_t e = hipSuccess;
+    if (c->cfg.adapt) {
+        e = enqueue_adapt<Real>(L, tn);
+        if (e != hipSuccess) return e;
+    }
+    if (separated(c) && c->cfg.separate == 2) {
+        e = enqueue_partitioned<Real>(L, MODE_STAGE1, 0, 1, tn, dt);
+        if (e == hipSuccess) e = enqueue_partitioned<Real>(L, MODE_STAGE2, 1, 0, tn + dt, dt);
+    } else if (separated(c)) {
+        e = enqueue_separated<Real>(L, MODE_STAGE1, 0, 1, tn, dt);
+        if (e == hipSuccess) e = enqueue_separated<Real>(L, MODE_STAGE2, 1, 0, tn + dt, dt);
+    } else {
+        e = enqueue_stage<Real>(L, MODE_STAGE1, 0, 1, tn, dt, nullptr, nullptr);
+        if (e == hipSuccess) e = enqueue_stage<Real>(L, MODE_STAGE2, 1, 0, tn + dt, dt, c->d_C[0], nullptr);
+    }
+    return e;
+}
+
+// The step graph: the device clock (stage times, open-sea elevation, depth
+// check stop), then one step as above.  Rebuilt when what it launches changes.
+std::vector<long long> step_graph_key(const swe_ctx *c)
+{
+    return {(long long)(intptr_t)c->d_C[0], (long long)(intptr_t)c->d_src, c->uniform ? 1 : 0,
+            c->list_cnt[0], c->list_cnt[1], c->list_cnt[2], c->list_cnt[3]};
+}
+
+swe_status ensure_step_graph(swe_ctx *c)
+{
+    const std::vector<long long> key = step_graph_key(c);
+    if (c->step_exec && key == c->graph_key) return SWE_OK;
+    drop_step_graph(c);
+    hipGraph_t g = nullptr;
+    HIP_TRY(c, hipGraphCreate(&g, 0));
+    Lanes L(c, g);
+    hipError_t e = launch_batch_clock(c->d_inst, c->d_flag, 1, L.a);
+    if (e == hipSuccess) e = c->fp32 ? enqueue_step<float>(L, 0.0, 0.0) : enqueue_step<double>(L, 0.0, 0.0);
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->step_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        c->step_exec = nullptr;
+        return fail(c, SWE_EDEVICE, std::string("step graph: ") + hipGetErrorString(e));
+    }
+    c->step_graph = g;
+    c->graph_key = key;
+    return SWE_OK;
 }
 
 // Elements whose right-hand side has a correction: order above p_base, or a
@@ -398,6 +568,7 @@ void swe_config_default(swe_config *cfg)
     cfg->g = 9.81;
     cfg->friction = SWE_FRICTION_NONE;
     cfg->adapt_tau = 1e-3;
+    cfg->step_graph = 1;
 }
 
 swe_status swe_create(const swe_config *cfg, swe_ctx **out)
@@ -408,6 +579,7 @@ swe_status swe_create(const swe_config *cfg, swe_ctx **out)
     if (cfg->p_max < 0 || cfg->p_max > 3 || cfg->p_base < 0 || cfg->p_base > cfg->p_max) return SWE_EINVAL;
     if (!(cfg->g > 0.0) || cfg->friction < 0 || cfg->friction > 2) return SWE_EINVAL;
     if (cfg->adapt && !(cfg->adapt_tau > 0.0)) return SWE_EINVAL;
+    if (cfg->separate < 0 || cfg->separate > 2) return SWE_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SWE_EDEVICE;
     swe_ctx *c = new (std::nothrow) swe_ctx();
@@ -610,6 +782,7 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t nv, const double *vxy, int64_t ne, c
     }
     HIP_TRY(c, hipMalloc(&c->d_L, w * 3 * K * S));
     HIP_TRY(c, hipMalloc(&c->d_flag, sizeof(int)));
+    HIP_TRY(c, hipMalloc(&c->d_inst, sizeof(InstDesc)));
     HIP_TRY(c, hipMemset(c->d_flag, 0, sizeof(int)));
     HIP_TRY(c, hipMalloc(&c->d_part, sizeof(double) * (mass_partials((int)ne) + 1)));
     HIP_TRY(c, hipMalloc(&c->d_mass, sizeof(double)));
@@ -790,29 +963,41 @@ swe_status swe_step(swe_ctx *c, int64_t nsteps, double dt)
     if (c->failed) return fail(c, SWE_ESTATE, "context is in a failed state; call swe_set_state");
     if (nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return fail(c, SWE_EINVAL, "bad step count or dt");
     const double t0 = c->t;
+    if (nsteps == 0) return SWE_OK;
+    if (nsteps > INT_MAX) return fail(c, SWE_EINVAL, "too many steps in one call");
+    if (c->cfg.adapt) c->uniform = false;   // orders may differ from the first order update on
+    // graphs pay off where a step has many dependent kernels (order-separated
+    // and order-partitioned steps); a fused step is two plain launches
+    const bool graph = c->ncon <= 4 && (c->cfg.step_graph == 2 || (c->cfg.step_graph == 1 && separated(c)));
+    if (graph) {
+        swe_status st = ensure_step_graph(c);
+        if (st != SWE_OK) return st;
+        InstDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.ne = (int)c->ne;
+        d.nv = (int)c->nv;
+        d.order = c->cfg.p_max;
+        d.active = 1;
+        d.steps_left = (int)nsteps;
+        d.ncon = c->ncon;
+        for (int i = 0; i < c->ncon; ++i) {
+            d.amp[i] = c->amp[i];
+            d.omega[i] = c->omega[i];
+            d.phase[i] = c->phase[i];
+        }
+        d.t0 = t0;
+        d.t = t0;
+        d.dt = dt;
+        hipError_t e = launch_inst_set(c->d_inst, d, c->s_base);
+        for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) e = hipGraphLaunch(c->step_exec, c->s_base);
+        if (e != hipSuccess) return fail(c, SWE_EDEVICE, std::string("step graph launch: ") + hipGetErrorString(e));
+        c->t = t0 + (double)nsteps * dt;
+        return SWE_OK;
+    }
+    Lanes L(c);
     for (int64_t s = 0; s < nsteps; ++s) {
         const double tn = t0 + (double)s * dt;
-        hipError_t e = hipSuccess;
-        if (c->cfg.adapt) {
-            e = c->fp32 ? enqueue_adapt<float>(c, tn) : enqueue_adapt<double>(c, tn);
-            if (e != hipSuccess) return fail(c, SWE_EDEVICE, std::string("adapt launch: ") + hipGetErrorString(e));
-            c->uniform = false;
-        }
-        if (separated(c)) {
-            if (c->fp32) {
-                e = enqueue_separated<float>(c, MODE_STAGE1, 0, 1, tn, dt);
-                if (e == hipSuccess) e = enqueue_separated<float>(c, MODE_STAGE2, 1, 0, tn + dt, dt);
-            } else {
-                e = enqueue_separated<double>(c, MODE_STAGE1, 0, 1, tn, dt);
-                if (e == hipSuccess) e = enqueue_separated<double>(c, MODE_STAGE2, 1, 0, tn + dt, dt);
-            }
-        } else if (c->fp32) {
-            e = enqueue_stage<float>(c, MODE_STAGE1, 0, 1, tn, dt, nullptr, nullptr);
-            if (e == hipSuccess) e = enqueue_stage<float>(c, MODE_STAGE2, 1, 0, tn + dt, dt, c->d_C[0], nullptr);
-        } else {
-            e = enqueue_stage<double>(c, MODE_STAGE1, 0, 1, tn, dt, nullptr, nullptr);
-            if (e == hipSuccess) e = enqueue_stage<double>(c, MODE_STAGE2, 1, 0, tn + dt, dt, c->d_C[0], nullptr);
-        }
+        const hipError_t e = c->fp32 ? enqueue_step<float>(L, tn, dt) : enqueue_step<double>(L, tn, dt);
         if (e != hipSuccess) return fail(c, SWE_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
         c->t = t0 + (double)(s + 1) * dt;
     }

@@ -68,6 +68,8 @@ struct StageArgs {
     // the pooled arrays; step, open-sea elevation and run flag come from inst
     const struct InstDesc *inst;
     int e_off;
+    int stage;           // with inst: which stage time of the step (0 or 1) a kernel without MODE uses
+    int skip_listed;     // base kernel of the order-partitioned scheme: listed elements are not its work
 };
 
 struct InstDesc;
@@ -112,24 +114,46 @@ struct BatchArgs {
 struct Sink {
     hipStream_t s = nullptr;
     hipGraph_t g = nullptr;
-    hipGraphNode_t last = nullptr;
+    static constexpr int MAXDEP = 6;
+    hipGraphNode_t dep[MAXDEP] = {};   // what the next node waits for
+    int ndep = 0;
+    // the next node also waits for what another branch ended with (a join)
+    bool join(const Sink &o)
+    {
+        for (int i = 0; i < o.ndep; ++i) {
+            bool have = false;
+            for (int j = 0; j < ndep; ++j) have = have || dep[j] == o.dep[i];
+            if (have) continue;
+            if (ndep == MAXDEP) return false;
+            dep[ndep++] = o.dep[i];
+        }
+        return true;
+    }
 };
 hipError_t emit(Sink &k, const void *fn, dim3 grid, dim3 block, void **args);
 
 hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, hipStream_t s);
 hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, Sink &k);
 hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, hipStream_t s);
+hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, Sink &k);
 hipError_t launch_epi(int p, int b, bool fp32, int mode, const void *args, int grid, hipStream_t s);
+// full stage of the listed elements of order p (neighbours of order <= pn)
+hipError_t launch_full(int p, int pn, bool fp32, int mode, const void *args, int grid, Sink &k);
+hipError_t launch_epi(int p, int b, bool fp32, int mode, const void *args, int grid, Sink &k);
 hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s);
 hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, int p_hi, double *I_out,
-                            signed char *p_new, hipStream_t s);
+                            signed char *p_new, Sink &k);
 hipError_t launch_apply_order(int pm, bool fp32, const void *args, const signed char *p_new, signed char *p_cur,
-                              int p_base, int lcap, hipStream_t s);
+                              int p_base, int lcap, Sink &k);
+hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, int p_hi, double *I_out,
+                            signed char *p_new, hipStream_t s);
 hipError_t launch_mass(const MeshView &m, bool fp32, const void *C, double *partial,
                        double *out, hipStream_t s);
 int mass_partials(int ne);
 hipError_t launch_batch_stage(int p, bool fp32, int mode, int tile, const BatchArgs &b, int grid, Sink &k);
 hipError_t launch_batch_clock(InstDesc *inst, const int *flags, int n, Sink &k);
+// write one instance descriptor in stream order (no host buffer outlives the call)
+hipError_t launch_inst_set(InstDesc *inst, const InstDesc &v, hipStream_t s);
 // copy an instance's mesh arrays into a pool, offsetting vertex and element ids
 hipError_t launch_relocate(const int *ev, const int *nb, const unsigned char *nbk, int ne, int stride,
                            const PoolView &pool, int first, int vbase, hipStream_t s);

@@ -720,6 +720,9 @@ __device__ __forceinline__ void stage_element(const StageArgs<Real> &a, unsigned
                                               double dt_stage, int *flag)
 {
     constexpr int K = Ord<P>::K;
+    if constexpr (SEP) {
+        if (a.skip_listed && a.inlist[e]) return;   // a full-order kernel owns this element
+    }
     const MeshView &m = a.m;
     const int KS = m.KS, stride = m.stride;
     const unsigned off = e * (unsigned)sizeof(Real);
@@ -898,6 +901,12 @@ k_corr(StageArgs<Real> a, double dt)
     const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
     const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
     const Buf<Real> bL(a.Lc, 3 * KS, stride);
+    double xihat = a.xihat;
+    if (a.inst) {
+        // the clock of a replayed step lives on the device
+        xihat = a.inst->xh[a.stage];
+        dt = a.inst->dt;
+    }
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
         const unsigned e = (unsigned)a.list[i];
         const unsigned off = e * (unsigned)sizeof(Real);
@@ -917,7 +926,7 @@ k_corr(StageArgs<Real> a, double dt)
             }
             Acc<B, Real> Ab;
             acc_init<B, Real>(Ab, sb, false);
-            element_rhs<B, B, Real>(a, e, bC, bU, bNb, sb, G, hbh, dt, sRb, Ab, a.xihat);
+            element_rhs<B, B, Real>(a, e, bC, bU, bNb, sb, G, hbh, dt, sRb, Ab, xihat);
             // ... then the full part accumulates on top of its negation
 #pragma unroll
             for (int q = 0; q < K; ++q) {
@@ -931,7 +940,7 @@ k_corr(StageArgs<Real> a, double dt)
                 for (int j = 0; j < 3; ++j) A.L[j][q] = -Ab.L[j][q];
             }
         }
-        element_rhs<P, PN, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A, a.xihat);
+        element_rhs<P, PN, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A, xihat);
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
@@ -969,6 +978,43 @@ k_epi(StageArgs<Real> a, int KB)
     }
 }
 
+// Order-partitioned scheme: the full stage of the listed elements of order P
+// (neighbours of order <= PN), one element per lane over the device-side list;
+// the base kernel skips these elements, so no epilogue joins the two.
+template <int P, int PN, typename Real, int MODE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
+k_full(StageArgs<Real> a)
+{
+    constexpr int NX = (P > PN ? P : PN) + 1, KN = Ord<PN>::K;
+    __shared__ Real sR[3][KN][NX];
+    load_trace_table<KN, NX, Real>(sR);
+    __syncthreads();
+    const MeshView &m = a.m;
+    const int KS = m.KS, stride = m.stride;
+    const int count = a.count[0];
+    const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
+    const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
+    double xihat = a.xihat, dt = a.dt;
+    if (a.inst) {
+        xihat = MODE == MODE_STAGE2 ? a.inst->xh[1] : a.inst->xh[0];
+        dt = a.inst->dt;
+    }
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
+        const unsigned e = (unsigned)a.list[i];
+        const unsigned off = e * (unsigned)sizeof(Real);
+        Geo G;
+        load_geo(m.vtx, bEv, e * 4u, G);
+        double hbh[3];
+        hb_modes(G, hbh);
+        Fields<P, Real> s;
+        load_state<P, Real>(bC, bU, KS, off, s);
+        Acc<P, Real> A;
+        acc_init<P, Real>(A, s, true);
+        element_rhs<P, PN, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A, xihat);
+        finish_stage<P, Real, MODE>(a, e, G, hbh, Ord<P>::K, A.L, a.flag);
+    }
+}
+
 // ------------------------------------------------------------ p-adaptivity
 // Indicator (stand-in for the paper's JRL indicator, which its text only
 // cites): the largest jump of the P1 part of xi at the edge midpoints; land
@@ -1000,7 +1046,7 @@ __global__ void __launch_bounds__(BLOCK) k_indicator(StageArgs<Real> a, double t
             const double y0 = bC.ld(0, on), y1 = bC.ld(1, on), y2 = bC.ld(2, on);
             other = TPMID[kk][0] * y0 + TPMID[kk][1] * y1 + TPMID[kk][2] * y2;
         } else if (nb == NB_OPEN) {
-            other = a.xihat;
+            other = a.inst ? a.inst->xh[0] : a.xihat;
         }
         const double j = fabs(own - other);
         I = j > I ? j : I;
@@ -1193,14 +1239,15 @@ hipError_t stage_r(int p, int mode, bool sep, const void *args, Sink &s)
 }
 
 template <int P, int B, int PN, typename Real>
-hipError_t corr_pbn(const StageArgs<Real> &a, double dt, int grid, hipStream_t s)
+hipError_t corr_pbn(const StageArgs<Real> &a, double dt, int grid, Sink &s)
 {
-    hipLaunchKernelGGL((k_corr<P, B, PN, Real>), dim3(grid), dim3(BLOCK), 0, s, a, dt);
-    return hipGetLastError();
+    StageArgs<Real> aa = a;
+    void *kargs[] = {&aa, &dt};
+    return emit(s, reinterpret_cast<const void *>(&k_corr<P, B, PN, Real>), dim3(grid), dim3(BLOCK), kargs);
 }
 
 template <int B, int PN, typename Real>
-hipError_t corr_bn(int p, const StageArgs<Real> &a, double dt, int grid, hipStream_t s)
+hipError_t corr_bn(int p, const StageArgs<Real> &a, double dt, int grid, Sink &s)
 {
     if (p < B || p > PN) return hipErrorInvalidValue;
     if constexpr (B <= 0 && 0 <= PN) if (p == 0) return corr_pbn<0, B, PN, Real>(a, dt, grid, s);
@@ -1211,7 +1258,7 @@ hipError_t corr_bn(int p, const StageArgs<Real> &a, double dt, int grid, hipStre
 }
 
 template <typename Real>
-hipError_t corr_r(int p, int b, int pn, const void *args, double dt, int grid, hipStream_t s)
+hipError_t corr_r(int p, int b, int pn, const void *args, double dt, int grid, Sink &s)
 {
     const StageArgs<Real> &a = *static_cast<const StageArgs<Real> *>(args);
     if (b == 0 && pn == 1) return corr_bn<0, 1, Real>(p, a, dt, grid, s);
@@ -1224,16 +1271,16 @@ hipError_t corr_r(int p, int b, int pn, const void *args, double dt, int grid, h
 }
 
 template <typename Real>
-hipError_t epi_r(int p, int mode, int KB, const void *args, int grid, hipStream_t s)
+hipError_t epi_r(int p, int mode, int KB, const void *args, int grid, Sink &s)
 {
-    const StageArgs<Real> &a = *static_cast<const StageArgs<Real> *>(args);
-    const dim3 g(grid), b(BLOCK);
-#define SWE_EPI(PP)                                                                                  \
-    if (p == PP) {                                                                                   \
-        if (mode == MODE_STAGE1) hipLaunchKernelGGL((k_epi<PP, Real, MODE_STAGE1>), g, b, 0, s, a, KB); \
-        else hipLaunchKernelGGL((k_epi<PP, Real, MODE_STAGE2>), g, b, 0, s, a, KB);                 \
-        return hipGetLastError();                                                                    \
-    }
+    StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
+    void *kargs[] = {&a, &KB};
+#define SWE_EPI(PP)                                                                                     \
+    if (p == PP)                                                                                        \
+        return emit(s,                                                                                  \
+                    mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_epi<PP, Real, MODE_STAGE1>)    \
+                                        : reinterpret_cast<const void *>(&k_epi<PP, Real, MODE_STAGE2>),   \
+                    dim3(grid), dim3(BLOCK), kargs);
     SWE_EPI(0)
     SWE_EPI(1)
     SWE_EPI(2)
@@ -1276,8 +1323,11 @@ hipError_t emit(Sink &k, const void *fn, dim3 grid, dim3 block, void **args)
     prm.kernelParams = args;      // copied into the node
     prm.extra = nullptr;
     hipGraphNode_t node = nullptr;
-    const hipError_t e = hipGraphAddKernelNode(&node, k.g, k.last ? &k.last : nullptr, k.last ? 1 : 0, &prm);
-    if (e == hipSuccess) k.last = node;
+    const hipError_t e = hipGraphAddKernelNode(&node, k.g, k.ndep ? k.dep : nullptr, (size_t)k.ndep, &prm);
+    if (e == hipSuccess) {
+        k.dep[0] = node;
+        k.ndep = 1;
+    }
     return e;
 }
 
@@ -1293,17 +1343,70 @@ hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, 
     return launch_stage(p, fp32, mode, sep, args, k);
 }
 
-hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, hipStream_t s)
+hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, Sink &k)
 {
     if (grid <= 0) return hipSuccess;
-    return fp32 ? corr_r<float>(p, b, pn, args, dt, grid, s) : corr_r<double>(p, b, pn, args, dt, grid, s);
+    return fp32 ? corr_r<float>(p, b, pn, args, dt, grid, k) : corr_r<double>(p, b, pn, args, dt, grid, k);
+}
+
+hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, hipStream_t s)
+{
+    Sink k;
+    k.s = s;
+    return launch_corr(p, b, pn, fp32, args, dt, grid, k);
+}
+
+template <int P, int PN, typename Real>
+hipError_t full_ppn(int mode, const void *args, int grid, Sink &s)
+{
+    StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
+    void *kargs[] = {&a};
+    return emit(s,
+                mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_full<P, PN, Real, MODE_STAGE1>)
+                                    : reinterpret_cast<const void *>(&k_full<P, PN, Real, MODE_STAGE2>),
+                dim3(grid), dim3(BLOCK), kargs);
+}
+
+template <int PN, typename Real>
+hipError_t full_pn(int p, int mode, const void *args, int grid, Sink &s)
+{
+    if (p > PN) return hipErrorInvalidValue;
+    if constexpr (0 <= PN) if (p == 0) return full_ppn<0, PN, Real>(mode, args, grid, s);
+    if constexpr (1 <= PN) if (p == 1) return full_ppn<1, PN, Real>(mode, args, grid, s);
+    if constexpr (2 <= PN) if (p == 2) return full_ppn<2, PN, Real>(mode, args, grid, s);
+    if constexpr (3 <= PN) if (p == 3) return full_ppn<3, PN, Real>(mode, args, grid, s);
+    return hipErrorInvalidValue;
+}
+
+template <typename Real>
+hipError_t full_r(int p, int pn, int mode, const void *args, int grid, Sink &s)
+{
+    switch (pn) {
+    case 1: return full_pn<1, Real>(p, mode, args, grid, s);
+    case 2: return full_pn<2, Real>(p, mode, args, grid, s);
+    case 3: return full_pn<3, Real>(p, mode, args, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_full(int p, int pn, bool fp32, int mode, const void *args, int grid, Sink &k)
+{
+    if (grid <= 0) return hipSuccess;
+    return fp32 ? full_r<float>(p, pn, mode, args, grid, k) : full_r<double>(p, pn, mode, args, grid, k);
+}
+
+hipError_t launch_epi(int p, int b, bool fp32, int mode, const void *args, int grid, Sink &k)
+{
+    if (grid <= 0) return hipSuccess;
+    const int KB = (b + 1) * (b + 2) / 2;
+    return fp32 ? epi_r<float>(p, mode, KB, args, grid, k) : epi_r<double>(p, mode, KB, args, grid, k);
 }
 
 hipError_t launch_epi(int p, int b, bool fp32, int mode, const void *args, int grid, hipStream_t s)
 {
-    if (grid <= 0) return hipSuccess;
-    const int KB = (b + 1) * (b + 2) / 2;
-    return fp32 ? epi_r<float>(p, mode, KB, args, grid, s) : epi_r<double>(p, mode, KB, args, grid, s);
+    Sink k;
+    k.s = s;
+    return launch_epi(p, b, fp32, mode, args, grid, k);
 }
 
 hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s)
@@ -1371,41 +1474,63 @@ hipError_t launch_relocate(const int *ev, const int *nb, const unsigned char *nb
     return hipGetLastError();
 }
 
+template <typename Real>
+hipError_t indicator_r(const void *args, double tau, int p_lo, int p_hi, double *I_out, signed char *p_new,
+                       Sink &s)
+{
+    StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
+    void *kargs[] = {&a, &tau, &p_lo, &p_hi, &I_out, &p_new};
+    return emit(s, reinterpret_cast<const void *>(&k_indicator<Real>), dim3((a.m.ne + BLOCK - 1) / BLOCK),
+                dim3(BLOCK), kargs);
+}
+
+hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, int p_hi, double *I_out,
+                            signed char *p_new, Sink &k)
+{
+    return fp32 ? indicator_r<float>(args, tau, p_lo, p_hi, I_out, p_new, k)
+                : indicator_r<double>(args, tau, p_lo, p_hi, I_out, p_new, k);
+}
+
 hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, int p_hi, double *I_out,
                             signed char *p_new, hipStream_t s)
 {
-    const int ne = static_cast<const StageArgs<double> *>(args)->m.ne;
-    const dim3 g((ne + BLOCK - 1) / BLOCK), b(BLOCK);
-    if (fp32)
-        hipLaunchKernelGGL(k_indicator<float>, g, b, 0, s, *static_cast<const StageArgs<float> *>(args), tau,
-                           p_lo, p_hi, I_out, p_new);
-    else
-        hipLaunchKernelGGL(k_indicator<double>, g, b, 0, s, *static_cast<const StageArgs<double> *>(args), tau,
-                           p_lo, p_hi, I_out, p_new);
-    return hipGetLastError();
+    Sink k;
+    k.s = s;
+    return launch_indicator(fp32, args, tau, p_lo, p_hi, I_out, p_new, k);
 }
 
 template <typename Real>
 hipError_t apply_r(int pm, const void *args, const signed char *p_new, signed char *p_cur, int p_base, int lcap,
-                   hipStream_t s)
+                   Sink &s)
 {
-    const StageArgs<Real> &a = *static_cast<const StageArgs<Real> *>(args);
+    StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
+    void *kargs[] = {&a, &p_new, &p_cur, &p_base, &lcap};
     const dim3 g((a.m.ne + BLOCK - 1) / BLOCK), b(BLOCK);
     switch (pm) {
-    case 0: hipLaunchKernelGGL((k_apply_order<0, Real>), g, b, 0, s, a, p_new, p_cur, p_base, lcap); break;
-    case 1: hipLaunchKernelGGL((k_apply_order<1, Real>), g, b, 0, s, a, p_new, p_cur, p_base, lcap); break;
-    case 2: hipLaunchKernelGGL((k_apply_order<2, Real>), g, b, 0, s, a, p_new, p_cur, p_base, lcap); break;
-    case 3: hipLaunchKernelGGL((k_apply_order<3, Real>), g, b, 0, s, a, p_new, p_cur, p_base, lcap); break;
-    default: return hipErrorInvalidValue;
+    case 0: return emit(s, reinterpret_cast<const void *>(&k_apply_order<0, Real>), g, b, kargs);
+    case 1: return emit(s, reinterpret_cast<const void *>(&k_apply_order<1, Real>), g, b, kargs);
+    case 2: return emit(s, reinterpret_cast<const void *>(&k_apply_order<2, Real>), g, b, kargs);
+    case 3: return emit(s, reinterpret_cast<const void *>(&k_apply_order<3, Real>), g, b, kargs);
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_apply_order(int pm, bool fp32, const void *args, const signed char *p_new, signed char *p_cur,
-                              int p_base, int lcap, hipStream_t s)
+                              int p_base, int lcap, Sink &k)
 {
-    return fp32 ? apply_r<float>(pm, args, p_new, p_cur, p_base, lcap, s)
-                : apply_r<double>(pm, args, p_new, p_cur, p_base, lcap, s);
+    return fp32 ? apply_r<float>(pm, args, p_new, p_cur, p_base, lcap, k)
+                : apply_r<double>(pm, args, p_new, p_cur, p_base, lcap, k);
+}
+
+__global__ void k_inst_set(InstDesc *inst, InstDesc v)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *inst = v;
+}
+
+hipError_t launch_inst_set(InstDesc *inst, const InstDesc &v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_inst_set, dim3(1), dim3(64), 0, s, inst, v);
+    return hipGetLastError();
 }
 
 hipError_t launch_mass(const MeshView &m, bool fp32, const void *C, double *partial, double *out,

@@ -33,7 +33,8 @@ class swe_config(C.Structure):
     _fields_ = [("precision", C.c_int), ("p_base", C.c_int), ("p_max", C.c_int),
                 ("g", C.c_double), ("f_coriolis", C.c_double), ("friction", C.c_int),
                 ("friction_coef", C.c_double), ("adapt", C.c_int), ("adapt_tau", C.c_double),
-                ("separate", C.c_int), ("stream_base", C.c_void_p), ("stream_corr", C.c_void_p)]
+                ("separate", C.c_int), ("stream_base", C.c_void_p), ("stream_corr", C.c_void_p),
+                ("step_graph", C.c_int)]
 
 
 _lib = None
@@ -119,12 +120,13 @@ class Config:
     separate: int = 0
     stream_base: Optional[int] = None
     stream_corr: Optional[int] = None
+    step_graph: int = 1          # 1: graph for separated steps, 2: always, 0: never
 
     def to_c(self) -> swe_config:
         c = swe_config()
         lib().swe_config_default(C.byref(c))
         for k in ("precision", "p_base", "p_max", "g", "f_coriolis", "friction", "friction_coef",
-                  "adapt", "adapt_tau", "separate"):
+                  "adapt", "adapt_tau", "separate", "step_graph"):
             setattr(c, k, getattr(self, k))
         c.stream_base = self.stream_base
         c.stream_corr = self.stream_corr
@@ -265,13 +267,14 @@ class Context:
         return I
 
 
-def context_for(problem, precision=SWE_FP64, separate=0, stream_base=None, stream_corr=None) -> Context:
+def context_for(problem, precision=SWE_FP64, separate=0, stream_base=None, stream_corr=None,
+                step_graph=1) -> Context:
     """Build a context from an ``inputs.Problem`` (mesh, bathymetry, forcing, orders)."""
     cfg = Config(precision=precision, p_base=problem.p_base, p_max=problem.p_max, g=problem.g,
                  f_coriolis=problem.f_coriolis, friction=problem.friction,
                  friction_coef=problem.friction_coef, adapt=problem.adapt,
                  adapt_tau=problem.adapt_tau, separate=separate, stream_base=stream_base,
-                 stream_corr=stream_corr)
+                 stream_corr=stream_corr, step_graph=step_graph)
     ctx = Context(cfg)
     ctx.set_mesh(problem.mesh.vxy, problem.mesh.tri, problem.mesh.tag)
     ctx.set_bathymetry(problem.hb_vertex)
