@@ -97,6 +97,25 @@ swe_status fail(swe_ctx *c, swe_status s, const std::string &msg)
                         std::string(#expr) + ": " + hipGetErrorString(e_));                      \
     } while (0)
 
+// Every transfer of a context is ordered on its base stream (the library's
+// kernels run on non-blocking streams, which the null stream does not order
+// against); host-to-device copies wait until the data has left the host
+// buffer, device-to-host copies first wait for the context's queued work.
+hipError_t h2d(swe_ctx *c, void *dst, const void *src, size_t bytes)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->s_base);
+    return e == hipSuccess ? hipStreamSynchronize(c->s_base) : e;
+}
+
+hipError_t d2h(swe_ctx *c, void *dst, const void *src, size_t bytes)
+{
+    hipError_t e = hipStreamSynchronize(c->s_corr);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->s_base);
+    return e == hipSuccess ? hipStreamSynchronize(c->s_base) : e;
+}
+
+hipError_t dzero(swe_ctx *c, void *dst, size_t bytes) { return hipMemsetAsync(dst, 0, bytes, c->s_base); }
+
 void drop_step_graph(swe_ctx *c)
 {
     if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
@@ -193,8 +212,7 @@ struct Lanes {
     {
         if (graph) {
             b.ndep = a.ndep;
-            b.dep[0] = a.dep[0];
-            b.dep[1] = a.dep[1];
+            for (int i = 0; i < Sink::MAXDEP; ++i) b.dep[i] = a.dep[i];
             return hipSuccess;
         }
         const hipError_t e = hipEventRecord(c->ev_ready, c->s_base);
@@ -249,12 +267,22 @@ hipError_t enqueue_stage(swe_ctx *c, int mode, int in, int out, double tstage, d
 
 bool separated(const swe_ctx *c) { return c->cfg.separate && c->cfg.p_base < c->cfg.p_max; }
 
-// Grid of a correction/epilogue launch: exact for static lists; with
-// adaptivity the list lengths live on the device and the kernels loop over them.
+// Grid of a correction/epilogue launch (one listed element per thread): exact
+// for static lists; with adaptivity the lengths live on the device and the
+// grid covers every element.
 int list_grid(const swe_ctx *c, int p)
 {
-    if (c->cfg.adapt) return std::min<int>((int)((c->ne + BLOCK - 1) / BLOCK), 1024);
+    if (c->cfg.adapt) return (int)((c->ne + BLOCK - 1) / BLOCK);
     return (c->list_cnt[p] + BLOCK - 1) / BLOCK;
+}
+
+// Grid of the correction's base pass over the lists of every order.
+int base_pass_grid(const swe_ctx *c)
+{
+    if (c->cfg.adapt) return (int)((c->ne + BLOCK - 1) / BLOCK);   // the lists hold each element at most once
+    int sum = 0;
+    for (int p = 0; p < 4; ++p) sum += c->list_cnt[p];
+    return (sum + BLOCK - 1) / BLOCK;
 }
 
 // Order adaptation at the start of a step, from the state in buffer 0.
@@ -300,6 +328,10 @@ hipError_t enqueue_separated(Lanes &L, int mode, int in, int out, double tstage,
     hipError_t e = L.fork();
     if (e != hipSuccess) return e;
     e = launch_stage(b, c->fp32, mode, true, &a, L.a);
+    if (e != hipSuccess) return e;
+    a.list = c->d_list;
+    a.count = c->d_cnt;
+    e = launch_corr_base(b, c->fp32, &a, dt, base_pass_grid(c), L.b);
     if (e != hipSuccess) return e;
     for (int p = b; p <= pm; ++p) {
         if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
@@ -439,14 +471,13 @@ swe_status build_lists(swe_ctx *c)
         }
     }
     for (int p = 0; p < 4; ++p) c->list_cnt[p] = (int)L[p].size();
-    HIP_TRY(c, hipMemcpy(c->d_inlist, in.data(), S, hipMemcpyHostToDevice));
+    HIP_TRY(c, h2d(c, c->d_inlist, in.data(), S));
     for (int p = 0; p < 4; ++p) {
         c->list_off[p] = p * (int)c->ne;
         if (!L[p].empty())
-            HIP_TRY(c, hipMemcpy(c->d_list + c->list_off[p], L[p].data(), sizeof(int) * L[p].size(),
-                                 hipMemcpyHostToDevice));
+            HIP_TRY(c, h2d(c, c->d_list + c->list_off[p], L[p].data(), sizeof(int) * L[p].size()));
     }
-    HIP_TRY(c, hipMemcpy(c->d_cnt, c->list_cnt, sizeof(int) * 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, h2d(c, c->d_cnt, c->list_cnt, sizeof(int) * 4));
     return SWE_OK;
 }
 
@@ -484,9 +515,9 @@ swe_status upload_state(swe_ctx *c, const double *coef, void *dst)
     if (c->fp32) {
         std::vector<float> f(n);
         for (size_t i = 0; i < n; ++i) f[i] = (float)h[i];
-        HIP_TRY(c, hipMemcpy(dst, f.data(), n * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(c, h2d(c, dst, f.data(), n * sizeof(float)));
     } else {
-        HIP_TRY(c, hipMemcpy(dst, h.data(), n * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(c, h2d(c, dst, h.data(), n * sizeof(double)));
     }
     return SWE_OK;
 }
@@ -498,10 +529,10 @@ swe_status download(swe_ctx *c, const void *src, int ncomp, double *out, bool is
     std::vector<double> h(n);
     if (c->fp32) {
         std::vector<float> f(n);
-        HIP_TRY(c, hipMemcpy(f.data(), src, n * sizeof(float), hipMemcpyDeviceToHost));
+        HIP_TRY(c, d2h(c, f.data(), src, n * sizeof(float)));
         for (size_t i = 0; i < n; ++i) h[i] = f[i];
     } else {
-        HIP_TRY(c, hipMemcpy(h.data(), src, n * sizeof(double), hipMemcpyDeviceToHost));
+        HIP_TRY(c, d2h(c, h.data(), src, n * sizeof(double)));
     }
     (void)is_rhs;
     for (int64_t ie = 0; ie < c->ne; ++ie) {
@@ -517,7 +548,7 @@ swe_status upload_vertices(swe_ctx *c)
 {
     std::vector<double4> v(c->nv);
     for (int64_t i = 0; i < c->nv; ++i) v[i] = make_double4(c->vx[i], c->vy[i], c->hb[i], 0.0);
-    HIP_TRY(c, hipMemcpy(c->d_vtx, v.data(), sizeof(double4) * c->nv, hipMemcpyHostToDevice));
+    HIP_TRY(c, h2d(c, c->d_vtx, v.data(), sizeof(double4) * c->nv));
     return SWE_OK;
 }
 
@@ -528,7 +559,7 @@ swe_status upload_order(swe_ctx *c)
     c->uniform = true;
     for (int64_t i = 0; i < c->ne; ++i)
         if (c->p[i] != c->cfg.p_max) c->uniform = false;
-    HIP_TRY(c, hipMemcpy(c->d_p, h.data(), c->stride, hipMemcpyHostToDevice));
+    HIP_TRY(c, h2d(c, c->d_p, h.data(), c->stride));
     return SWE_OK;
 }
 
@@ -545,6 +576,9 @@ hipError_t enqueue_rhs_split(swe_ctx *c, double t)
     a.xihat = xi_hat(c, t);
     a.dt = 0.0;
     hipError_t e = launch_stage(b, c->fp32, MODE_RHS, false, &a, c->s_base);
+    a.list = c->d_list;
+    a.count = c->d_cnt;
+    if (e == hipSuccess) e = launch_corr_base(b, c->fp32, &a, 1.0, base_pass_grid(c), c->s_base);
     for (int p = b; p <= pm && e == hipSuccess; ++p) {
         if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
         a.list = c->d_list + c->list_off[p];
@@ -777,28 +811,28 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t nv, const double *vxy, int64_t ne, c
     for (int b = 0; b < 2; ++b) {
         HIP_TRY(c, hipMalloc(&c->d_C[b], w * 3 * K * S));
         HIP_TRY(c, hipMalloc(&c->d_U[b], w * 2 * K * S));
-        HIP_TRY(c, hipMemset(c->d_C[b], 0, w * 3 * K * S));
-        HIP_TRY(c, hipMemset(c->d_U[b], 0, w * 2 * K * S));
+        HIP_TRY(c, dzero(c, c->d_C[b], w * 3 * K * S));
+        HIP_TRY(c, dzero(c, c->d_U[b], w * 2 * K * S));
     }
     HIP_TRY(c, hipMalloc(&c->d_L, w * 3 * K * S));
     HIP_TRY(c, hipMalloc(&c->d_flag, sizeof(int)));
     HIP_TRY(c, hipMalloc(&c->d_inst, sizeof(InstDesc)));
-    HIP_TRY(c, hipMemset(c->d_flag, 0, sizeof(int)));
+    HIP_TRY(c, dzero(c, c->d_flag, sizeof(int)));
     HIP_TRY(c, hipMalloc(&c->d_part, sizeof(double) * (mass_partials((int)ne) + 1)));
     HIP_TRY(c, hipMalloc(&c->d_mass, sizeof(double)));
-    HIP_TRY(c, hipMemcpy(c->d_ev, c->ev.data(), sizeof(int) * 3 * S, hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->d_nb, nb.data(), sizeof(int) * 3 * S, hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->d_nbk, nbk.data(), S, hipMemcpyHostToDevice));
+    HIP_TRY(c, h2d(c, c->d_ev, c->ev.data(), sizeof(int) * 3 * S));
+    HIP_TRY(c, h2d(c, c->d_nb, nb.data(), sizeof(int) * 3 * S));
+    HIP_TRY(c, h2d(c, c->d_nbk, nbk.data(), S));
     c->nb_host = nb;
     if (separated(c) || c->cfg.adapt) {
         const int KB = K_OF[c->cfg.p_base];
         HIP_TRY(c, hipMalloc(&c->d_inlist, S));
-        HIP_TRY(c, hipMemset(c->d_inlist, 0, S));
+        HIP_TRY(c, dzero(c, c->d_inlist, S));
         HIP_TRY(c, hipMalloc(&c->d_Lb, w * 3 * KB * S));
         HIP_TRY(c, hipMalloc(&c->d_Lc, w * 3 * K * S));
         HIP_TRY(c, hipMalloc(&c->d_list, sizeof(int) * 4 * (size_t)ne));
         HIP_TRY(c, hipMalloc(&c->d_cnt, sizeof(int) * 4));
-        HIP_TRY(c, hipMemset(c->d_cnt, 0, sizeof(int) * 4));
+        HIP_TRY(c, dzero(c, c->d_cnt, sizeof(int) * 4));
         HIP_TRY(c, hipMalloc(&c->d_pnew, S));
         HIP_TRY(c, hipMalloc(&c->d_I, sizeof(double) * S));
     }
@@ -862,7 +896,7 @@ swe_status swe_get_order(swe_ctx *c, int8_t *p)
     if (c->cfg.adapt) {
         // orders change on the device every step
         HIP_TRY(c, hipStreamSynchronize(c->s_base));
-        HIP_TRY(c, hipMemcpy(c->p.data(), c->d_p, c->ne, hipMemcpyDeviceToHost));
+        HIP_TRY(c, d2h(c, c->p.data(), c->d_p, c->ne));
     }
     for (int64_t i = 0; i < c->ne; ++i) p[c->e_perm[i]] = c->p[i];
     return SWE_OK;
@@ -892,9 +926,9 @@ swe_status swe_set_state(swe_ctx *c, double t0, const double *coef)
     swe_status st = upload_state(c, coef, c->d_C[0]);
     if (st) return st;
     // modes above each element's order are zero in every state buffer
-    HIP_TRY(c, hipMemset(c->d_C[1], 0, c->rsz * 3 * c->K * c->stride));
-    HIP_TRY(c, hipMemset(c->d_U[1], 0, c->rsz * 2 * c->K * c->stride));
-    HIP_TRY(c, hipMemset(c->d_flag, 0, sizeof(int)));
+    HIP_TRY(c, dzero(c, c->d_C[1], c->rsz * 3 * c->K * c->stride));
+    HIP_TRY(c, dzero(c, c->d_U[1], c->rsz * 2 * c->K * c->stride));
+    HIP_TRY(c, dzero(c, c->d_flag, sizeof(int)));
     HIP_TRY(c, usolve_buf(c, 0));
     HIP_TRY(c, hipStreamSynchronize(c->s_base));
     c->t = t0;
@@ -1011,7 +1045,7 @@ swe_status swe_sync(swe_ctx *c)
     HIP_TRY(c, hipStreamSynchronize(c->s_corr));
     if (c->have_mesh) {
         int flag = 0;
-        HIP_TRY(c, hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+        HIP_TRY(c, d2h(c, &flag, c->d_flag, sizeof(int)));
         if (flag) {
             c->failed = true;
             return fail(c, SWE_ESTATE, "non-finite value or non-positive mean depth detected");
@@ -1127,7 +1161,7 @@ swe_status swe_indicator(swe_ctx *c, double t, const double *coef, double *I_out
     if (e != hipSuccess) return fail(c, SWE_EDEVICE, std::string("indicator launch: ") + hipGetErrorString(e));
     std::vector<double> h(c->ne);
     HIP_TRY(c, hipStreamSynchronize(c->s_base));
-    HIP_TRY(c, hipMemcpy(h.data(), c->d_I, sizeof(double) * c->ne, hipMemcpyDeviceToHost));
+    HIP_TRY(c, d2h(c, h.data(), c->d_I, sizeof(double) * c->ne));
     for (int64_t i = 0; i < c->ne; ++i) I_out[c->e_perm[i]] = h[i];
     return SWE_OK;
 }
@@ -1328,16 +1362,23 @@ BatchArgs batch_args(const swe_batch *b, int p)
     return a;
 }
 
-// FP64 order-3 instances are launched one by one (the single-instance stage
-// kernel, clock and element offset read from the device); every other class
-// runs in the persistent multi-instance kernel.
-bool per_instance(const swe_batch *b, int p) { return p == 3 && !b->fp32; }
+// Order-3 instances are launched one by one (the single-instance stage
+// kernel, one element per thread, clock and element offset read from the
+// device); every other class runs in the persistent multi-instance kernel.
+// The order-3 evaluation spills registers, and spilling code inside the
+// persistent kernel's tile loop gave wrong results.
+bool per_instance(const swe_batch *b, int p)
+{
+    (void)b;
+    return p == 3;
+}
 
-hipError_t enqueue_instance_stage(swe_batch *b, int i, int mode, Sink &k)
+template <typename Real>
+hipError_t instance_stage(swe_batch *b, int i, int mode, Sink &k)
 {
     const swe_batch::Member &m = b->mem[i];
     const PoolView &v = b->pool[m.order].v;
-    StageArgs<double> a;
+    StageArgs<Real> a;
     std::memset(&a, 0, sizeof(a));
     a.m.ne = (int)m.ctx->ne;
     a.m.stride = v.cap;
@@ -1346,16 +1387,21 @@ hipError_t enqueue_instance_stage(swe_batch *b, int i, int mode, Sink &k)
     a.m.ev = v.ev;
     a.m.enb = v.nb;
     a.m.enbk = v.nbk;
-    a.Cin = static_cast<const double *>(mode == MODE_STAGE1 ? v.C0 : v.C1);
-    a.Uin = static_cast<const double *>(mode == MODE_STAGE1 ? v.U0 : v.U1);
-    a.Cn = static_cast<const double *>(v.C0);
-    a.Cout = static_cast<double *>(mode == MODE_STAGE1 ? v.C1 : v.C0);
-    a.Uout = static_cast<double *>(mode == MODE_STAGE1 ? v.U1 : v.U0);
+    a.Cin = static_cast<const Real *>(mode == MODE_STAGE1 ? v.C0 : v.C1);
+    a.Uin = static_cast<const Real *>(mode == MODE_STAGE1 ? v.U0 : v.U1);
+    a.Cn = static_cast<const Real *>(v.C0);
+    a.Cout = static_cast<Real *>(mode == MODE_STAGE1 ? v.C1 : v.C0);
+    a.Uout = static_cast<Real *>(mode == MODE_STAGE1 ? v.U1 : v.U0);
     a.ph = b->h_inst[i].ph;
     a.flag = b->d_flags + i;
     a.inst = b->d_inst + i;
     a.e_off = (int)m.first;
-    return launch_stage(m.order, false, mode, false, &a, k);
+    return launch_stage(m.order, b->fp32, mode, false, &a, k);
+}
+
+hipError_t enqueue_instance_stage(swe_batch *b, int i, int mode, Sink &k)
+{
+    return b->fp32 ? instance_stage<float>(b, i, mode, k) : instance_stage<double>(b, i, mode, k);
 }
 
 hipError_t enqueue_batch_step(swe_batch *b, Sink &k)
@@ -1472,9 +1518,11 @@ swe_status swe_batch_create(const swe_config *cfg, int64_t budget, int max_insta
         swe_batch_destroy(b);
         return SWE_ENOMEM;
     }
-    if (hipMemcpy(b->d_inst, b->h_inst.data(), sizeof(InstDesc) * max_instances, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(b->d_flags, 0, sizeof(int) * max_instances) != hipSuccess ||
-        hipMemset(b->d_ntiles, 0, sizeof(int) * 4) != hipSuccess) {
+    if (hipMemcpyAsync(b->d_inst, b->h_inst.data(), sizeof(InstDesc) * max_instances, hipMemcpyHostToDevice,
+                       b->s) != hipSuccess ||
+        hipMemsetAsync(b->d_flags, 0, sizeof(int) * max_instances, b->s) != hipSuccess ||
+        hipMemsetAsync(b->d_ntiles, 0, sizeof(int) * 4, b->s) != hipSuccess ||
+        hipStreamSynchronize(b->s) != hipSuccess) {
         swe_batch_destroy(b);
         return SWE_EDEVICE;
     }
@@ -1622,7 +1670,8 @@ swe_status swe_batch_query(swe_batch *b, int32_t slot, int64_t *steps_left, doub
     swe_status st = get_desc(b, slot);
     if (st) return st;
     int f = 0;
-    BHIP_TRY(b, hipMemcpy(&f, b->d_flags + slot, sizeof(int), hipMemcpyDeviceToHost));
+    BHIP_TRY(b, hipMemcpyAsync(&f, b->d_flags + slot, sizeof(int), hipMemcpyDeviceToHost, b->s));
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
     if (steps_left) *steps_left = b->h_inst[slot].steps_left;
     if (t) *t = b->h_inst[slot].t;
     if (failed) *failed = f;
@@ -1660,7 +1709,8 @@ swe_status swe_batch_retire(swe_batch *b, int32_t slot)
     st = pull_state(b, slot);
     if (st) return st;
     int f = 0;
-    BHIP_TRY(b, hipMemcpy(&f, b->d_flags + slot, sizeof(int), hipMemcpyDeviceToHost));
+    BHIP_TRY(b, hipMemcpyAsync(&f, b->d_flags + slot, sizeof(int), hipMemcpyDeviceToHost, b->s));
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
     c->t = b->h_inst[slot].t;
     if (f) c->failed = true;
     b->h_inst[slot].active = 0;
@@ -1694,7 +1744,8 @@ swe_status swe_batch_tune(swe_batch *b, int reps)
     // state untouched; the clock fields are restored afterwards
     std::vector<InstDesc> saved(b->h_inst);
     std::vector<int> flags(b->cap);
-    BHIP_TRY(b, hipMemcpy(flags.data(), b->d_flags, sizeof(int) * b->cap, hipMemcpyDeviceToHost));
+    BHIP_TRY(b, hipMemcpyAsync(flags.data(), b->d_flags, sizeof(int) * b->cap, hipMemcpyDeviceToHost, b->s));
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
     for (int i = 0; i < b->cap; ++i) {
         if (!b->mem[i].ctx) continue;
         swe_status st = get_desc(b, i);

@@ -51,8 +51,18 @@ constexpr double INV_2SQRT3 = 0.28867513459481288225;  // 1 / (2 sqrt 3)
 template <int P, typename Real>
 constexpr int waves_target()
 {
-    // the order-3 kernels spill below 512 registers per lane: leave them at one wave
-    return P >= 3 ? 1 : P <= 1 ? 2 : (std::is_same<Real, double>::value ? SWE_WAVES_FP64 : SWE_WAVES_FP32);
+    // FP64 order 3 spills below 512 registers per lane: one wave.  FP32 order 3
+    // is held to 256 registers (two waves), so no accumulation registers serve
+    // as spill space (kernels doing so gave run-to-run differences).
+    return P >= 3 ? (std::is_same<Real, double>::value ? 1 : 2)
+                  : P <= 1 ? 2 : (std::is_same<Real, double>::value ? SWE_WAVES_FP64 : SWE_WAVES_FP32);
+}
+
+// Occupancy of the list kernels (corrections, full-order stages of listed elements)
+template <int P, typename Real>
+constexpr int list_waves()
+{
+    return (P >= 3 && !std::is_same<Real, double>::value) ? 2 : 1;
 }
 
 template <int P>
@@ -375,16 +385,15 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const 
     const unsigned nbk_all = m.enbk[e];
     const Real xbm = Real(SQRT2) * s.xi[0];
     const Real ubm = Real(SQRT2) * s.u[0], vbm = Real(SQRT2) * s.v[0];
+    // With the edge vector's normal nu = |E| n (no square root), every flux
+    // term carries |E| n or |E| lambda, and |E| / |det B| folds into dt / |det B|.
     const double dt_det = dt / G.det;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int ka = (k + 1) % 3, kb = (k + 2) % 3;
         const double dx = G.X[kb] - G.X[ka], dy = G.Y[kb] - G.Y[ka];
-        const double len = sqrt(dx * dx + dy * dy);
-        const double il = 1.0 / len;
-        const double nxd = dy * il, nyd = -dx * il;
-        const Real nx = Real(nxd), ny = Real(nyd);
-        const double scale = len * dt_det;                 // dt |E| / |det B|
+        const double len2 = dx * dx + dy * dy;
+        const Real nx = Real(dy), ny = Real(-dx);          // |E| n
         const double hmid = 0.5 * (G.h[ka] + G.h[kb]);
         const double hbt[2] = {hmid, (G.h[kb] - G.h[ka]) * INV_2SQRT3};
 
@@ -456,13 +465,14 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const 
             unbp = fabs(fma(Real(SQRT2) * u0, nx, Real(SQRT2) * v0 * ny));
         } else if (nb == NB_LAND) {
             // mirror: xi+ = xi-, normal parts of q and u change sign
+            const Real m2 = Real(-2.0 / len2);
 #pragma unroll
             for (int a = 0; a < NX; ++a) {
                 txp[a] = txm[a];
                 unp[a] = -unm[a];
                 qnp[a] = -qnm[a];
-                tUp[a] = fma(Real(-2) * qnm[a], nx, tUm[a]);
-                tVp[a] = fma(Real(-2) * qnm[a], ny, tVm[a]);
+                tUp[a] = fma(m2 * qnm[a], nx, tUm[a]);
+                tVp[a] = fma(m2 * qnm[a], ny, tVm[a]);
             }
             xbp = xbm;
             unbp = unbm;
@@ -479,13 +489,13 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const 
             xbp = Real(xihat);
             unbp = unbm;
         }
-        // penalty from constant parts at the edge midpoint (eq:lambda)
+        // penalty from constant parts at the edge midpoint (eq:lambda), times |E|
         Real lam;
         if constexpr (std::is_same<Real, double>::value)
-            lam = tmax(unbm, unbp) + sqrt(g * (tmax(xbm, xbp) + hmid));
+            lam = tmax(unbm, unbp) + sqrt(g * (tmax(xbm, xbp) + hmid) * len2);
         else
-            lam = tmax(unbm, unbp) + Real(sqrt(g * (double(tmax(xbm, xbp)) + hmid)));
-        const Real sc = Real(scale);
+            lam = tmax(unbm, unbp) + Real(sqrt(g * (double(tmax(xbm, xbp)) + hmid) * len2));
+        const Real sc = Real(dt_det);
         const Real hg = Real(0.5 * g);
         Real FX[NT], FU[NT], FV[NT];
         double FW[NT];
@@ -509,13 +519,13 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const 
 #pragma unroll
                 for (int b = 0; b < 2 && b < NX; ++b)
                     if (TG[c][a][b] != 0.0) w = fma(TG[c][a][b] * hbt[b], xs[a], w);
-            FW[c] = 0.5 * g * w * scale;
+            FW[c] = 0.5 * g * w * dt_det;
         }
         double FWx[NT], FWy[NT];
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
-            FWx[c] = FW[c] * nxd;
-            FWy[c] = FW[c] * nyd;
+            FWx[c] = FW[c] * dy;
+            FWy[c] = FW[c] * -dx;
         }
 #pragma unroll
         for (int q = 0; q < K; ++q) {
@@ -881,23 +891,24 @@ __global__ void __launch_bounds__(BLOCK) k_batch_clock(InstDesc *inst, const int
     I.steps_left -= 1;
 }
 
-// Correction of the order-separated scheme for the listed elements of order P
-// (base order B, neighbours of order <= PN): dt times the full right-hand
-// side minus its base part (rows below K(B)), and the full rows from K(B) on.
-template <int P, int B, int PN, typename Real>
+// Correction of the order-separated scheme, in two passes over the listed
+// elements (one element per lane):
+//  1. k_corr_base<B>: minus dt times the base part (rows below K(B), the
+//     element's and its neighbours' first K(B) modes), for the listed
+//     elements of every order;
+//  2. k_corr<P,B,PN>: for the listed elements of order P (neighbours of order
+//     <= PN), adds dt times the full right-hand side on top.
+// Each pass holds one right-hand side evaluation in registers.
+template <int B, typename Real>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
-k_corr(StageArgs<Real> a, double dt)
+k_corr_base(StageArgs<Real> a, double dt)
 {
-    constexpr int K = Ord<P>::K, KB = Ord<B>::K, NTB = Ord<B>::NT;
-    constexpr int KN = Ord<PN>::K, NX = (P > PN ? P : PN) + 1;
-    __shared__ Real sR[3][KN][NX];
+    constexpr int KB = Ord<B>::K, NTB = Ord<B>::NT;
     __shared__ Real sRb[3][KB][NTB];
-    load_trace_table<KN, NX, Real>(sR);
     load_trace_table<KB, NTB, Real>(sRb);
     __syncthreads();
     const MeshView &m = a.m;
     const int KS = m.KS, stride = m.stride;
-    const int count = a.count[0];
     const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
     const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
     const Buf<Real> bL(a.Lc, 3 * KS, stride);
@@ -907,45 +918,74 @@ k_corr(StageArgs<Real> a, double dt)
         xihat = a.inst->xh[a.stage];
         dt = a.inst->dt;
     }
-    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
-        const unsigned e = (unsigned)a.list[i];
-        const unsigned off = e * (unsigned)sizeof(Real);
-        Geo G;
-        load_geo(m.vtx, bEv, e * 4u, G);
-        double hbh[3];
-        hb_modes(G, hbh);
-        Fields<P, Real> s;
-        load_state<P, Real>(bC, bU, KS, off, s);
-        // base part first (first K(B) modes of the element and its neighbours) ...
-        Acc<P, Real> A;
-        {
-            Fields<B, Real> sb;
-#pragma unroll
-            for (int q = 0; q < KB; ++q) {
-                sb.xi[q] = s.xi[q]; sb.U[q] = s.U[q]; sb.V[q] = s.V[q]; sb.u[q] = s.u[q]; sb.v[q] = s.v[q];
-            }
-            Acc<B, Real> Ab;
-            acc_init<B, Real>(Ab, sb, false);
-            element_rhs<B, B, Real>(a, e, bC, bU, bNb, sb, G, hbh, dt, sRb, Ab, xihat);
-            // ... then the full part accumulates on top of its negation
-#pragma unroll
-            for (int q = 0; q < K; ++q) {
-#pragma unroll
-                for (int j = 0; j < 3; ++j) A.L[j][q] = Real(0);
-                if constexpr (Acc<P, Real>::SPLIT) { A.W[0][q] = 0.0; A.W[1][q] = 0.0; }
-            }
-#pragma unroll
-            for (int q = 0; q < KB; ++q) {
-#pragma unroll
-                for (int j = 0; j < 3; ++j) A.L[j][q] = -Ab.L[j][q];
-            }
-        }
-        element_rhs<P, PN, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A, xihat);
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int q = 0; q < K; ++q) bL.st(j * KS + q, off, A.L[j][q]);
+    // thread i takes entry i of the concatenated lists of orders B..3 (the
+    // grid covers their total length): one element per thread, no loop around
+    // the evaluation
+    int j = blockIdx.x * BLOCK + threadIdx.x, p = B;
+    while (p < 4 && j >= a.count[p]) {
+        j -= a.count[p];
+        ++p;
     }
+    if (p >= 4) return;
+    const unsigned e = (unsigned)a.list[(size_t)p * (size_t)m.ne + (size_t)j];
+    const unsigned off = e * (unsigned)sizeof(Real);
+    Geo G;
+    load_geo(m.vtx, bEv, e * 4u, G);
+    double hbh[3];
+    hb_modes(G, hbh);
+    Fields<B, Real> sb;
+    load_state<B, Real>(bC, bU, KS, off, sb);
+    Acc<B, Real> Ab;
+    acc_init<B, Real>(Ab, sb, false);
+    element_rhs<B, B, Real>(a, e, bC, bU, bNb, sb, G, hbh, dt, sRb, Ab, xihat);
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+        for (int q = 0; q < KB; ++q) bL.st(jj * KS + q, off, -Ab.L[jj][q]);
+}
+
+template <int P, int B, int PN, typename Real>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<(P > PN ? P : PN), Real>(), 8)))
+k_corr(StageArgs<Real> a, double dt)
+{
+    constexpr int K = Ord<P>::K, KB = Ord<B>::K;
+    constexpr int KN = Ord<PN>::K, NX = (P > PN ? P : PN) + 1;
+    __shared__ Real sR[3][KN][NX];
+    load_trace_table<KN, NX, Real>(sR);
+    __syncthreads();
+    const MeshView &m = a.m;
+    const int KS = m.KS, stride = m.stride;
+    const int count = a.count[0];
+    const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
+    const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
+    const Buf<Real> bL(a.Lc, 3 * KS, stride);
+    double xihat = a.xihat;
+    if (a.inst) {
+        xihat = a.inst->xh[a.stage];
+        dt = a.inst->dt;
+    }
+    // one listed element per thread (the grid covers the list), no loop
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= count) return;
+    const unsigned e = (unsigned)a.list[i];
+    const unsigned off = e * (unsigned)sizeof(Real);
+    Geo G;
+    load_geo(m.vtx, bEv, e * 4u, G);
+    double hbh[3];
+    hb_modes(G, hbh);
+    Fields<P, Real> s;
+    load_state<P, Real>(bC, bU, KS, off, s);
+    Acc<P, Real> A;
+    acc_init<P, Real>(A, s, false);
+    element_rhs<P, PN, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A, xihat);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            Real v = A.L[j][q];
+            if (q < KB) v += bL.ld(j * KS + q, off);   // minus the base part (pass 1)
+            bL.st(j * KS + q, off, v);
+        }
 }
 
 // Epilogue of the order-separated scheme for the listed elements of order P:
@@ -960,29 +1000,29 @@ k_epi(StageArgs<Real> a, int KB)
     const int count = a.count[0];
     const Buf<Real> bC(a.Cin, 3 * KS, stride), bL(a.Lc, 3 * KS, stride), bB(a.Lb, 3 * KB, stride);
     const Buf<int> bEv(m.ev, 3, stride);
-    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
-        const unsigned e = (unsigned)a.list[i];
-        const unsigned off = e * (unsigned)sizeof(Real);
-        Geo G;
+    const int i = blockIdx.x * BLOCK + threadIdx.x;   // one listed element per thread
+    if (i >= count) return;
+    const unsigned e = (unsigned)a.list[i];
+    const unsigned off = e * (unsigned)sizeof(Real);
+    Geo G;
 #pragma unroll
-        for (int v = 0; v < 3; ++v) G.h[v] = m.vtx[(unsigned)bEv.ld(v, e * 4u)].z;
-        double hbh[3];
-        hb_modes(G, hbh);
-        Real L[3][K];
+    for (int v = 0; v < 3; ++v) G.h[v] = m.vtx[(unsigned)bEv.ld(v, e * 4u)].z;
+    double hbh[3];
+    hb_modes(G, hbh);
+    Real L[3][K];
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int q = 0; q < K; ++q)
-                L[j][q] = (q < KB ? bB.ld(j * KB + q, off) : bC.ld(j * KS + q, off)) + bL.ld(j * KS + q, off);
-        finish_stage<P, Real, MODE>(a, e, G, hbh, K, L, a.flag);
-    }
+        for (int q = 0; q < K; ++q)
+            L[j][q] = (q < KB ? bB.ld(j * KB + q, off) : bC.ld(j * KS + q, off)) + bL.ld(j * KS + q, off);
+    finish_stage<P, Real, MODE>(a, e, G, hbh, K, L, a.flag);
 }
 
 // Order-partitioned scheme: the full stage of the listed elements of order P
 // (neighbours of order <= PN), one element per lane over the device-side list;
 // the base kernel skips these elements, so no epilogue joins the two.
 template <int P, int PN, typename Real, int MODE>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<(P > PN ? P : PN), Real>(), 8)))
 k_full(StageArgs<Real> a)
 {
     constexpr int NX = (P > PN ? P : PN) + 1, KN = Ord<PN>::K;
@@ -999,20 +1039,20 @@ k_full(StageArgs<Real> a)
         xihat = MODE == MODE_STAGE2 ? a.inst->xh[1] : a.inst->xh[0];
         dt = a.inst->dt;
     }
-    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
-        const unsigned e = (unsigned)a.list[i];
-        const unsigned off = e * (unsigned)sizeof(Real);
-        Geo G;
-        load_geo(m.vtx, bEv, e * 4u, G);
-        double hbh[3];
-        hb_modes(G, hbh);
-        Fields<P, Real> s;
-        load_state<P, Real>(bC, bU, KS, off, s);
-        Acc<P, Real> A;
-        acc_init<P, Real>(A, s, true);
-        element_rhs<P, PN, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A, xihat);
-        finish_stage<P, Real, MODE>(a, e, G, hbh, Ord<P>::K, A.L, a.flag);
-    }
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= count) return;
+    const unsigned e = (unsigned)a.list[i];
+    const unsigned off = e * (unsigned)sizeof(Real);
+    Geo G;
+    load_geo(m.vtx, bEv, e * 4u, G);
+    double hbh[3];
+    hb_modes(G, hbh);
+    Fields<P, Real> s;
+    load_state<P, Real>(bC, bU, KS, off, s);
+    Acc<P, Real> A;
+    acc_init<P, Real>(A, s, true);
+    element_rhs<P, PN, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A, xihat);
+    finish_stage<P, Real, MODE>(a, e, G, hbh, Ord<P>::K, A.L, a.flag);
 }
 
 // ------------------------------------------------------------ p-adaptivity
@@ -1341,6 +1381,33 @@ hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, 
     Sink k;
     k.s = s;
     return launch_stage(p, fp32, mode, sep, args, k);
+}
+
+template <typename Real>
+hipError_t corr_base_r(int b, const void *args, double dt, int grid, Sink &s)
+{
+    StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
+    void *kargs[] = {&a, &dt};
+    const dim3 g(grid), bl(BLOCK);
+    switch (b) {
+    case 0: return emit(s, reinterpret_cast<const void *>(&k_corr_base<0, Real>), g, bl, kargs);
+    case 1: return emit(s, reinterpret_cast<const void *>(&k_corr_base<1, Real>), g, bl, kargs);
+    case 2: return emit(s, reinterpret_cast<const void *>(&k_corr_base<2, Real>), g, bl, kargs);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_corr_base(int b, bool fp32, const void *args, double dt, int grid, Sink &k)
+{
+    if (grid <= 0) return hipSuccess;
+    return fp32 ? corr_base_r<float>(b, args, dt, grid, k) : corr_base_r<double>(b, args, dt, grid, k);
+}
+
+hipError_t launch_corr_base(int b, bool fp32, const void *args, double dt, int grid, hipStream_t s)
+{
+    Sink k;
+    k.s = s;
+    return launch_corr_base(b, fp32, args, dt, grid, k);
 }
 
 hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, Sink &k)

@@ -103,7 +103,7 @@ def test_split_repeatable(prec):
         c = I.random_state(prob.mesh, prob.p, pm, seed=500 + b + pm, hb_vertex=prob.hb_vertex,
                            xi_amp=1.0, q_amp=20.0)
         with swe.context_for(prob, precision=precision, separate=1) as ctx:
-            runs = [ctx.rhs_split(3.0, c) for _ in range(3)]
+            runs = [ctx.rhs_split(3.0, c) for _ in range(10)]
         for base, corr in runs:
             assert np.all(np.isfinite(base)) and np.all(np.isfinite(corr)), (b, pm)
             assert np.array_equal(base, runs[0][0]) and np.array_equal(corr, runs[0][1]), (b, pm)
