@@ -1350,6 +1350,14 @@ swe_status upload_tiles(swe_batch *b)
     return SWE_OK;
 }
 
+// Grid of a batch stage launch: one block per tile the pool of order p can
+// hold with tiles of `tile` elements, plus 8 (each XCD then has a block for
+// every tile of its eighth of the list; surplus blocks exit at once).
+int tile_grid(const swe_batch *b, int p, int tile)
+{
+    return (int)(b->pool[p].v.cap / tile) + 1 + 8;
+}
+
 BatchArgs batch_args(const swe_batch *b, int p)
 {
     BatchArgs a;
@@ -1362,15 +1370,16 @@ BatchArgs batch_args(const swe_batch *b, int p)
     return a;
 }
 
-// Order-3 instances are launched one by one (the single-instance stage
-// kernel, one element per thread, clock and element offset read from the
-// device); every other class runs in the persistent multi-instance kernel.
-// The order-3 evaluation spills registers, and spilling code inside the
-// persistent kernel's tile loop gave wrong results.
+// Every order class runs in the multi-instance kernel (one tile per block).
+// The single-instance path below (one launch per instance, clock and element
+// offset read from the device) stays available for a class that cannot; a
+// persistent kernel looping over tiles around the register-spilling order-3
+// evaluation gave wrong results, the one-tile-per-block kernel does not loop.
 bool per_instance(const swe_batch *b, int p)
 {
     (void)b;
-    return p == 3;
+    (void)p;
+    return false;
 }
 
 template <typename Real>
@@ -1417,7 +1426,7 @@ hipError_t enqueue_batch_step(swe_batch *b, Sink &k)
             }
             // the kernels read the tile counts from device memory, so the grid
             // need not match the current resident set
-            e = launch_batch_stage(p, b->fp32, mode, b->tile[p], batch_args(b, p), b->grid[p], k);
+            e = launch_batch_stage(p, b->fp32, mode, b->tile[p], batch_args(b, p), tile_grid(b, p, b->tile[p]), k);
         }
     return e;
 }
@@ -1731,7 +1740,7 @@ swe_status swe_batch_tile_config(const swe_batch *b, int p, int *tile, int *grid
 {
     if (!b || p < 0 || p > 3) return SWE_EINVAL;
     if (tile) *tile = b->tile[p];
-    if (grid) *grid = b->grid[p];
+    if (grid) *grid = b->pool[p].v.cap > 0 ? tile_grid(b, p, b->tile[p]) : 0;
     return SWE_OK;
 }
 
@@ -1759,7 +1768,6 @@ swe_status swe_batch_tune(swe_batch *b, int reps)
     BHIP_TRY(b, hipEventCreate(&e0));
     BHIP_TRY(b, hipEventCreate(&e1));
     const int tiles[3] = {64, 128, 256};
-    const int mult[5] = {1, 2, 4, 8, 0};    // 0: one block per tile of the pool's capacity
     swe_status st = SWE_OK;
     for (int p = 0; p < 4 && st == SWE_OK; ++p) {
         bool any = false;
@@ -1770,9 +1778,8 @@ swe_status swe_batch_tune(swe_batch *b, int reps)
         for (int ti = 0; ti < 3 && st == SWE_OK; ++ti) {
             b->tile[p] = tiles[ti];
             st = upload_tiles(b);
-            for (int mi = 0; mi < 5 && st == SWE_OK; ++mi) {
-                const int grid = mult[mi] ? std::max(1, std::min(b->ntiles[p], mult[mi] * b->ncu * 256 / tiles[ti]))
-                                          : (int)(b->pool[p].v.cap / tiles[ti] + 1);
+            {
+                const int grid = tile_grid(b, p, tiles[ti]);
                 Sink k;
                 k.s = b->s;
                 hipError_t e = launch_batch_stage(p, b->fp32, MODE_STAGE1, tiles[ti], batch_args(b, p), grid, k);
@@ -1783,7 +1790,10 @@ swe_status swe_batch_tune(swe_batch *b, int reps)
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float ms = 0.f;
                 if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                if (e != hipSuccess) { st = bfail(b, SWE_EDEVICE, std::string("tuning: ") + hipGetErrorString(e)); break; }
+                if (e != hipSuccess) {
+                    st = bfail(b, SWE_EDEVICE, std::string("tuning: ") + hipGetErrorString(e));
+                    break;
+                }
                 if (ms < best) { best = ms; bt = tiles[ti]; bg = grid; }
             }
         }

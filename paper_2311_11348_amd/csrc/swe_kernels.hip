@@ -48,13 +48,16 @@ constexpr double INV_2SQRT3 = 0.28867513459481288225;  // 1 / (2 sqrt 3)
 #ifndef SWE_WAVES_FP32
 #define SWE_WAVES_FP32 2
 #endif
+#ifndef SWE_WAVES_FP32_P3
+#define SWE_WAVES_FP32_P3 1
+#endif
 template <int P, typename Real>
 constexpr int waves_target()
 {
-    // FP64 order 3 spills below 512 registers per lane: one wave.  FP32 order 3
-    // is held to 256 registers (two waves), so no accumulation registers serve
-    // as spill space (kernels doing so gave run-to-run differences).
-    return P >= 3 ? (std::is_same<Real, double>::value ? 1 : 2)
+    // Order 3 needs more than 256 registers per lane: one wave (the
+    // accumulation registers then serve as spill space; no kernel loops
+    // around such an evaluation, which gave run-to-run differences).
+    return P >= 3 ? (std::is_same<Real, double>::value ? 1 : SWE_WAVES_FP32_P3)
                   : P <= 1 ? 2 : (std::is_same<Real, double>::value ? SWE_WAVES_FP64 : SWE_WAVES_FP32);
 }
 
@@ -62,7 +65,7 @@ constexpr int waves_target()
 template <int P, typename Real>
 constexpr int list_waves()
 {
-    return (P >= 3 && !std::is_same<Real, double>::value) ? 2 : 1;
+    return (P >= 3 && !std::is_same<Real, double>::value) ? SWE_WAVES_FP32_P3 : 1;
 }
 
 template <int P>
@@ -799,13 +802,14 @@ k_stage(StageArgs<Real> a)
 }
 
 // ------------------------------------------------------------ batched instances
-// One persistent launch per order class and stage covers the tiles of every
-// resident instance of that order.  All instances of an order share pooled
-// arrays passed as kernel arguments; a tile (TILE consecutive elements of one
-// instance) only reads its instance's scalars (step, open-sea elevation,
-// physics, clock).  Each XCD walks a contiguous eighth of the tile list, so
-// the neighbour gathers of an instance's elements stay in one L2.  Instances whose clock says they are
-// done are skipped: one captured step serves any resident set.
+// One launch per order class and stage covers the tiles of every resident
+// instance of that order (one tile per block, no loop around the element
+// evaluation).  All instances of an order share pooled arrays passed as
+// kernel arguments; a tile (TILE consecutive elements of one instance) only
+// reads its instance's scalars (step, open-sea elevation, physics, clock).
+// Each XCD takes a contiguous eighth of the tile list, so the neighbour
+// gathers of an instance's elements stay in one L2.  Instances whose clock
+// says they are done are skipped: one step graph serves any resident set.
 template <int P, typename Real, int MODE, int TILE>
 __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(waves_target<P, Real>(), 8)))
 k_batch_stage(BatchArgs b)
@@ -814,17 +818,15 @@ k_batch_stage(BatchArgs b)
     __shared__ Real sR[3][K][NT];
     load_trace_table<K, NT, Real>(sR);
     __syncthreads();
-    // XCD x (blocks x, x+8, ...) owns the contiguous eighth [lo, hi) of the
-    // tile list and splits it into contiguous chunks, one per block; with one
-    // block per tile or more, each block takes a single tile.  Grids of fewer
-    // than 8 blocks split the list among the blocks there are.
+    // One tile per block.  XCD x (blocks x, x+8, ...) owns the contiguous
+    // eighth [lo, hi) of the tile list; the grid is sized from the tile
+    // capacity (at least 8 blocks more than there can be tiles), so every
+    // XCD has a block for each of its tiles and the surplus blocks exit.
     const int ntiles = b.ntiles[0];
-    const int nx = gridDim.x < 8u ? (int)gridDim.x : 8;
-    const int x = (int)blockIdx.x % nx, i = (int)blockIdx.x / nx;
-    const int bx = ((int)gridDim.x - x + nx - 1) / nx;
-    const int lo = (int)((long long)ntiles * x / nx), hi = (int)((long long)ntiles * (x + 1) / nx);
-    const int per = (hi - lo + bx - 1) / bx;
-    const int t0 = lo + i * per, t1 = t0 + per < hi ? t0 + per : hi;
+    const int x = (int)(blockIdx.x & 7u), i = (int)(blockIdx.x >> 3);
+    const int lo = (int)(((long long)ntiles * x) >> 3), hi = (int)(((long long)ntiles * (x + 1)) >> 3);
+    const int t = lo + i;
+    if (t >= hi) return;
     StageArgs<Real> a;
     a.m.ne = 0;
     a.m.stride = b.pool.cap;
@@ -842,16 +844,14 @@ k_batch_stage(BatchArgs b)
     a.Lout = nullptr;
     a.src = nullptr;
     a.mixed = 0;
-    for (int t = t0; t < t1; ++t) {
-        const int2 tile = b.tiles[t];
-        const InstDesc &I = b.inst[tile.x];
-        if (!I.run) continue;
-        a.ph = I.ph;
-        const unsigned e = (unsigned)tile.y + threadIdx.x;
-        if (e < (unsigned)(I.first + I.ne))
-            stage_element<P, Real, MODE, false>(a, e, sR, MODE == MODE_STAGE1 ? I.xh[0] : I.xh[1], I.dt,
-                                                b.flags + tile.x);
-    }
+    const int2 tile = b.tiles[t];
+    const InstDesc &I = b.inst[tile.x];
+    if (!I.run) return;
+    a.ph = I.ph;
+    const unsigned e = (unsigned)tile.y + threadIdx.x;
+    if (e < (unsigned)(I.first + I.ne))
+        stage_element<P, Real, MODE, false>(a, e, sR, MODE == MODE_STAGE1 ? I.xh[0] : I.xh[1], I.dt,
+                                            b.flags + tile.x);
 }
 
 __global__ void __launch_bounds__(BLOCK) k_relocate(const int *ev, const int *nb, const unsigned char *nbk, int ne,
