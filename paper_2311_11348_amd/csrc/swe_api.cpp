@@ -75,8 +75,8 @@ struct swe_ctx {
     double amp[NCON_MAX] = {0}, omega[NCON_MAX] = {0}, phase[NCON_MAX] = {0};
     // replayed step: one graph per step, clock (time, forcing) on the device
     InstDesc *d_inst = nullptr;
-    hipGraph_t step_graph = nullptr;
-    hipGraphExec_t step_exec = nullptr;
+    hipGraph_t step_graph = nullptr, multi_graph = nullptr;   // one step; GRAPH_STEPS steps
+    hipGraphExec_t step_exec = nullptr, multi_exec = nullptr;
     std::vector<long long> graph_key;     // what the step graph was built for
     std::string err;
 };
@@ -120,8 +120,10 @@ void drop_step_graph(swe_ctx *c)
 {
     if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
     if (c->step_graph) (void)hipGraphDestroy(c->step_graph);
-    c->step_exec = nullptr;
-    c->step_graph = nullptr;
+    if (c->multi_exec) (void)hipGraphExecDestroy(c->multi_exec);
+    if (c->multi_graph) (void)hipGraphDestroy(c->multi_graph);
+    c->step_exec = c->multi_exec = nullptr;
+    c->step_graph = c->multi_graph = nullptr;
     c->graph_key.clear();
 }
 
@@ -333,21 +335,50 @@ hipError_t enqueue_separated(Lanes &L, int mode, int in, int out, double tstage,
     a.count = c->d_cnt;
     e = launch_corr_base(b, c->fp32, &a, dt, base_pass_grid(c), L.b);
     if (e != hipSuccess) return e;
+    // streams: the orders one after the other; graph: the orders' corrections
+    // (after the base-part pass) and then their epilogues on parallel branches
+    Sink ends[4];
+    int n = 0;
     for (int p = b; p <= pm; ++p) {
         if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
         a.list = c->d_list + c->list_off[p];
         a.count = c->d_cnt + p;
-        e = launch_corr(p, b, pm, c->fp32, &a, dt, list_grid(c, p), L.b);
+        if (L.graph) {
+            ends[n] = L.b;
+            e = launch_corr(p, b, pm, c->fp32, &a, dt, list_grid(c, p), ends[n]);
+            ++n;
+        } else {
+            e = launch_corr(p, b, pm, c->fp32, &a, dt, list_grid(c, p), L.b);
+        }
         if (e != hipSuccess) return e;
     }
-    e = L.join();
-    if (e != hipSuccess) return e;
+    if (L.graph) {
+        if (n == 0 && !L.a.join(L.b)) return hipErrorInvalidValue;
+        for (int i = 0; i < n; ++i)
+            if (!L.a.join(ends[i])) return hipErrorInvalidValue;
+    } else {
+        e = L.join();
+        if (e != hipSuccess) return e;
+    }
+    const Sink origin = L.a;
+    n = 0;
     for (int p = b; p <= pm; ++p) {
         if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
         a.list = c->d_list + c->list_off[p];
         a.count = c->d_cnt + p;
-        e = launch_epi(p, b, c->fp32, mode, &a, list_grid(c, p), L.a);
+        if (L.graph) {
+            ends[n] = origin;
+            e = launch_epi(p, b, c->fp32, mode, &a, list_grid(c, p), ends[n]);
+            ++n;
+        } else {
+            e = launch_epi(p, b, c->fp32, mode, &a, list_grid(c, p), L.a);
+        }
         if (e != hipSuccess) return e;
+    }
+    if (L.graph && n > 0) {
+        L.a.ndep = 0;
+        for (int i = 0; i < n; ++i)
+            if (!L.a.join(ends[i])) return hipErrorInvalidValue;
     }
     return hipSuccess;
 }
@@ -430,23 +461,41 @@ std::vector<long long> step_graph_key(const swe_ctx *c)
             c->list_cnt[0], c->list_cnt[1], c->list_cnt[2], c->list_cnt[3]};
 }
 
+// Steps per replay of the multi-step graph: the gap between two graph
+// launches is several times that between two dependent nodes.
+constexpr int GRAPH_STEPS = 8;
+
+hipError_t build_graph(swe_ctx *c, int nsteps, hipGraph_t *g_out, hipGraphExec_t *x_out)
+{
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    Lanes L(c, g);
+    for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+        e = launch_batch_clock(c->d_inst, c->d_flag, 1, L.a);
+        if (e == hipSuccess) e = c->fp32 ? enqueue_step<float>(L, 0.0, 0.0) : enqueue_step<double>(L, 0.0, 0.0);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(x_out, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        *x_out = nullptr;
+        return e;
+    }
+    *g_out = g;
+    return hipSuccess;
+}
+
 swe_status ensure_step_graph(swe_ctx *c)
 {
     const std::vector<long long> key = step_graph_key(c);
-    if (c->step_exec && key == c->graph_key) return SWE_OK;
+    if (c->step_exec && c->multi_exec && key == c->graph_key) return SWE_OK;
     drop_step_graph(c);
-    hipGraph_t g = nullptr;
-    HIP_TRY(c, hipGraphCreate(&g, 0));
-    Lanes L(c, g);
-    hipError_t e = launch_batch_clock(c->d_inst, c->d_flag, 1, L.a);
-    if (e == hipSuccess) e = c->fp32 ? enqueue_step<float>(L, 0.0, 0.0) : enqueue_step<double>(L, 0.0, 0.0);
-    if (e == hipSuccess) e = hipGraphInstantiate(&c->step_exec, g, nullptr, nullptr, 0);
+    hipError_t e = build_graph(c, 1, &c->step_graph, &c->step_exec);
+    if (e == hipSuccess) e = build_graph(c, GRAPH_STEPS, &c->multi_graph, &c->multi_exec);
     if (e != hipSuccess) {
-        (void)hipGraphDestroy(g);
-        c->step_exec = nullptr;
+        drop_step_graph(c);
         return fail(c, SWE_EDEVICE, std::string("step graph: ") + hipGetErrorString(e));
     }
-    c->step_graph = g;
     c->graph_key = key;
     return SWE_OK;
 }
@@ -1023,7 +1072,9 @@ swe_status swe_step(swe_ctx *c, int64_t nsteps, double dt)
         d.t = t0;
         d.dt = dt;
         hipError_t e = launch_inst_set(c->d_inst, d, c->s_base);
-        for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) e = hipGraphLaunch(c->step_exec, c->s_base);
+        int64_t s = 0;
+        for (; s + GRAPH_STEPS <= nsteps && e == hipSuccess; s += GRAPH_STEPS) e = hipGraphLaunch(c->multi_exec, c->s_base);
+        for (; s < nsteps && e == hipSuccess; ++s) e = hipGraphLaunch(c->step_exec, c->s_base);
         if (e != hipSuccess) return fail(c, SWE_EDEVICE, std::string("step graph launch: ") + hipGetErrorString(e));
         c->t = t0 + (double)nsteps * dt;
         return SWE_OK;
