@@ -214,8 +214,8 @@ def run_separated(prob, precision, steps, warmup, separate=1, chunk=50):
 
 
 def run_batched(count, steps, warmup):
-    """Many independent instances: FP32 and FP64 batched (persistent tile
-    kernels, captured step, autotuned tiles) and the plain FP64 solver (one
+    """Many independent instances: FP32 and FP64 batched (tile-per-block
+    kernels, step graph, autotuned tiles) and the plain FP64 solver (one
     instance at a time, one ordinary launch per stage).  Every instance runs
     warmup + steps steps; the timed region holds the last ``steps`` of all of
     them.  Inputs are resident before timing."""
@@ -429,7 +429,7 @@ def main() -> int:
                    dtype="f32 (f64 bathymetry terms)", roofline=r.pop("roofline"),
                    config={"workload": f"batched: {args.instances} independent instances, log-uniform "
                                        "16k-500k elements, p in {1,2,3}, tidal or hump, random smooth "
-                                       f"bathymetry 50-4000 m, {steps} steps each, persistent tile kernels",
+                                       f"bathymetry 50-4000 m, {steps} steps each, one tile per block",
                            **{k: r.pop(k) for k in ("elements", "orders", "tiles")}}, **r)
     elif args.workload == "served":
         main_s, cap = run_served(args.duration, args.rate, args.capacity_requests, args.tick_steps)

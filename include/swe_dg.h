@@ -180,7 +180,7 @@ void swe_destroy(swe_ctx *ctx);
 
 /* ------------------------------------------------------------------------
  * Batches: many independent instances advanced together.  Every resident
- * instance of one order is covered by one persistent launch per RK stage;
+ * instance of one order is covered by one launch per RK stage (one tile per block);
  * each instance keeps its own time, step size, forcing and step budget on
  * the device, so one step graph (built from kernel nodes, no stream capture,
  * and replayed) serves any resident set.  Other host threads may create and

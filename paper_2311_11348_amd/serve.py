@@ -4,7 +4,7 @@ Requests arrive over time (each: a mesh size, an order, a step count and a
 forcing kind).  Host threads prepare each request's context (mesh upload,
 bathymetry, initial state) as soon as it arrives; the scheduler admits
 prepared requests into the resident batch while their device footprint fits
-the budget, advances every resident instance together (one captured step per
+the budget, advances every resident instance together (one step graph per
 tick, each instance at its own time step and step budget), retires finished
 instances (state copied back to the host) and admits the next ones at every
 tick boundary.  Latency is measured from arrival to the completed copy of the
