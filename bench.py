@@ -168,13 +168,13 @@ def run_uniform(prob, precision, steps, warmup):
     bpe = stage_bytes_per_element(p, word, nv, ne)
     achieved = bpe * ne / launch_s / 1e9
     real = "double" if word == 8 else "float"
-    traffic = measured_traffic([f"k_stage<{p}, {real}, {m}, false>" for m in (1, 2)]) if p == 2 and ne == 524288 else None
+    traffic = measured_traffic([f"k_stage_sh<{p}, {real}, {m}>" for m in (1, 2)]) if p == 2 and ne == 524288 else None
     return {"value": dof / launch_s, "ms_per_step": ms / steps,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
                          "traffic": traffic / 1e9 / launch_s if traffic is not None else None,
                          "traffic_bytes_per_launch": traffic,
-                         "kernel": f"k_stage<{p},{real}>",
+                         "kernel": f"k_stage_sh<{p},{real}> (fused stage, edge fluxes shared within a block)",
                          "bytes_per_launch": bpe * ne, "avg_launch_us": launch_s * 1e6}}
 
 

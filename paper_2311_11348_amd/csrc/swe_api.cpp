@@ -74,6 +74,8 @@ struct swe_ctx {
     int ncon = 0;
     double amp[NCON_MAX] = {0}, omega[NCON_MAX] = {0}, phase[NCON_MAX] = {0};
     // replayed step: one graph per step, clock (time, forcing) on the device
+    unsigned *d_items = nullptr;           // edge items of the shared-flux stage kernel, per block
+    int *d_item_off = nullptr;            // [blocks + 1]
     InstDesc *d_inst = nullptr;
     hipGraph_t step_graph = nullptr, multi_graph = nullptr;   // one step; GRAPH_STEPS steps
     hipGraphExec_t step_exec = nullptr, multi_exec = nullptr;
@@ -132,6 +134,10 @@ void free_mesh(swe_ctx *c)
     drop_step_graph(c);
     if (c->d_inst) (void)hipFree(c->d_inst);
     c->d_inst = nullptr;
+    if (c->d_items) (void)hipFree(c->d_items);
+    if (c->d_item_off) (void)hipFree(c->d_item_off);
+    c->d_items = nullptr;
+    c->d_item_off = nullptr;
     void *ptrs[] = {c->d_vtx, c->d_ev, c->d_nb, c->d_nbk, c->d_p, c->d_C[0], c->d_C[1],
                     c->d_U[0], c->d_U[1], c->d_L, c->d_src, c->d_flag, c->d_part, c->d_mass,
                     c->d_inlist, c->d_Lb, c->d_Lc, c->d_list, c->d_cnt, c->d_pnew, c->d_I};
@@ -256,6 +262,8 @@ hipError_t enqueue_stage(Lanes &L, int mode, int in, int out, double tstage, dou
     a.Uout = out >= 0 ? static_cast<Real *>(c->d_U[out]) : nullptr;
     a.Lout = static_cast<Real *>(Lout);
     L.time(a, mode == MODE_STAGE2 ? 1 : 0, tstage, dt);
+    if (c->d_items && !a.mixed)
+        return launch_stage_sh(c->cfg.p_max, c->fp32, mode, &a, c->d_items, c->d_item_off, L.a);
     return launch_stage(c->cfg.p_max, c->fp32, mode, false, &a, L.a);
 }
 
@@ -873,6 +881,49 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t nv, const double *vxy, int64_t ne, c
     HIP_TRY(c, h2d(c, c->d_nb, nb.data(), sizeof(int) * 3 * S));
     HIP_TRY(c, h2d(c, c->d_nbk, nbk.data(), S));
     c->nb_host = nb;
+#ifndef SWE_SHARED_FLUX
+#define SWE_SHARED_FLUX 1
+#endif
+    if (SWE_SHARED_FLUX && stage_sh_supported(c->cfg.p_max, c->fp32)) {
+        // edge items per block of BLOCK elements, grouped by kind: pairs of
+        // elements of the block (once, from the lower index), neighbours
+        // outside the block, land edges, open edges
+        const int64_t nblk = (ne + BLOCK - 1) / BLOCK;
+        std::vector<unsigned> items;
+        std::vector<int> ioff((size_t)nblk + 1, 0);
+        items.reserve((size_t)ne * 2);
+        for (int64_t bi = 0; bi < nblk; ++bi) {
+            ioff[(size_t)bi] = (int)items.size();
+            const int64_t e0 = bi * BLOCK, e1 = std::min<int64_t>(e0 + BLOCK, ne);
+            for (unsigned kind = 0; kind < 4; ++kind)
+                for (int64_t ei = e0; ei < e1; ++ei)
+                    for (int k = 0; k < 3; ++k) {
+                        const int n = nb[(size_t)k * S + ei];
+                        unsigned kd;
+                        int lb = 0, kb = 0;
+                        if (n >= 0 && n / BLOCK == bi) {
+                            if (n < ei) continue;      // the pair is taken from the lower index
+                            kd = 0;
+                            lb = (int)(n - e0);
+                            kb = (nbk[ei] >> (2 * k)) & 3;
+                        } else if (n >= 0) {
+                            kd = 1;
+                        } else if (n == NB_LAND) {
+                            kd = 2;
+                        } else {
+                            kd = 3;
+                        }
+                        if (kd != kind) continue;
+                        items.push_back((unsigned)(ei - e0) | ((unsigned)k << 8) | ((unsigned)lb << 10) |
+                                        ((unsigned)kb << 18) | (kd << 20));
+                    }
+        }
+        ioff[(size_t)nblk] = (int)items.size();
+        HIP_TRY(c, hipMalloc(&c->d_items, sizeof(unsigned) * std::max<size_t>(items.size(), 1)));
+        HIP_TRY(c, hipMalloc(&c->d_item_off, sizeof(int) * ioff.size()));
+        if (!items.empty()) HIP_TRY(c, h2d(c, c->d_items, items.data(), sizeof(unsigned) * items.size()));
+        HIP_TRY(c, h2d(c, c->d_item_off, ioff.data(), sizeof(int) * ioff.size()));
+    }
     if (separated(c) || c->cfg.adapt) {
         const int KB = K_OF[c->cfg.p_base];
         HIP_TRY(c, hipMalloc(&c->d_inlist, S));
@@ -1268,6 +1319,8 @@ struct swe_batch {
     struct Member { swe_ctx *ctx = nullptr; int64_t bytes = 0; int order = 0; int64_t first = 0, span = 0, vbase = 0, nv = 0; };
     std::vector<Member> mem;
     std::vector<InstDesc> h_inst;
+    unsigned *d_items = nullptr;           // edge items of the shared-flux stage kernel, per block
+    int *d_item_off = nullptr;            // [blocks + 1]
     InstDesc *d_inst = nullptr;
     int *d_flags = nullptr;
     struct Pool { PoolView v{}; RangeAlloc ra; };

@@ -134,6 +134,11 @@ hipError_t emit(Sink &k, const void *fn, dim3 grid, dim3 block, void **args);
 
 hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, hipStream_t s);
 hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, Sink &k);
+// fused stage with each in-block edge flux computed once (edge items built by
+// the host, see swe_kernels.hip); supported for p <= 2, and p = 3 in FP32
+bool stage_sh_supported(int p, bool fp32);
+hipError_t launch_stage_sh(int p, bool fp32, int mode, const void *args, const unsigned *items, const int *item_off,
+                           Sink &k);
 // base-part pass of the correction over the listed elements of every order
 // (args.list = the start of the per-order lists, args.count = the 4 counts)
 hipError_t launch_corr_base(int b, bool fp32, const void *args, double dt, int grid, Sink &k);

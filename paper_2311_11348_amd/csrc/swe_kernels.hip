@@ -722,6 +722,308 @@ __device__ __forceinline__ void finish_stage(const StageArgs<Real> &a, unsigned 
     if (!(Hmean > 0.0) || !isfinite(chk)) flag[0] = 1;
 }
 
+// ------------------------------------------------------------ shared edge fluxes
+// Stage kernel in which each edge flux inside a block of BLOCK consecutive
+// elements is computed once and handed to both sides through LDS:
+//   1. each lane (one element) keeps its state in registers, copies it to LDS
+//      and accumulates its volume and source terms;
+//   2. the block's edge items (host-built: a pair of elements of the block,
+//      or an element and a neighbour outside the block, a land or an open
+//      edge) are spread over the lanes; each computes the Lax-Friedrichs flux
+//      in the first side's orientation, unscaled by dt / |det B|, and stores
+//      it for the first side and, negated and reversed along the edge, for
+//      the second;
+//   3. each lane lifts its three edge fluxes with its own geometry and
+//      finishes the stage.
+// An item packs a (bits 0-7), its local edge (8-9), b (10-17), b's local
+// edge (18-19) and the kind (20-21).
+constexpr unsigned EK_PAIR = 0, EK_EXT = 1, EK_LAND = 2, EK_OPEN = 3;
+
+template <int P, typename Real>
+struct ShLds {
+    static constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
+    Real R[3][K][NT];          // trace matrices
+    Real C[5 * K][BLOCK];      // xi, U, V, u, v modes of the block's elements
+    Real F[3 * NT][3][BLOCK];  // flux modes (component, mode) per local edge and element
+    double W[NT][3][BLOCK];    // bathymetry part of the pressure flux, FP64
+};
+
+template <int P, typename Real>
+__device__ __forceinline__ void traces_of(const ShLds<P, Real> &S, int l, int k, Real (&t)[5][Ord<P>::NT])
+{
+    constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
+#pragma unroll
+    for (int f = 0; f < 5; ++f)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) t[f][c] = Real(0);
+#pragma unroll
+    for (int n = 0; n < K; ++n)
+#pragma unroll
+        for (int c = 0; c < NT && c <= TDEG[n]; ++c) {
+            const Real r = S.R[k][n][c];
+#pragma unroll
+            for (int f = 0; f < 5; ++f) t[f][c] = fma(S.C[f * K + n][l], r, t[f][c]);
+        }
+}
+
+template <int P, typename Real, int MODE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_target<P, Real>(), 8)))
+k_stage_sh(StageArgs<Real> a, const unsigned *items, const int *item_off)
+{
+    constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
+    __shared__ ShLds<P, Real> S;
+    for (int i = threadIdx.x; i < 3 * K * NT; i += BLOCK) {
+        const int k = i / (K * NT), r = i % (K * NT);
+        S.R[k][r / NT][r % NT] = Real(TR[k][r / NT][r % NT]);
+    }
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const MeshView &m = a.m;
+    const int KS = m.KS, stride = m.stride;
+    const unsigned e0 = (unsigned)blk * BLOCK, l = threadIdx.x, e = e0 + l;
+    const bool live = e < (unsigned)m.ne;
+    double xihat = a.xihat, dt = a.dt;
+    if (a.inst) {
+        xihat = MODE == MODE_STAGE2 ? a.inst->xh[1] : a.inst->xh[0];
+        dt = a.inst->dt;
+    }
+    if (MODE == MODE_RHS) dt = 1.0;
+    const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
+    const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
+    const double g = a.ph.g;
+
+    // 1. state to registers and LDS, volume and source terms
+    Geo G;
+    double hbh[3];
+    Fields<P, Real> s;
+    Acc<P, Real> A;
+    const unsigned off = e * (unsigned)sizeof(Real);
+    if (live) {
+        load_geo(m.vtx, bEv, e * 4u, G);
+        hb_modes(G, hbh);
+        load_state<P, Real>(bC, bU, KS, off, s);
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            S.C[0 * K + q][l] = s.xi[q];
+            S.C[1 * K + q][l] = s.U[q];
+            S.C[2 * K + q][l] = s.V[q];
+            S.C[3 * K + q][l] = s.u[q];
+            S.C[4 * K + q][l] = s.v[q];
+        }
+        acc_init<P, Real>(A, s, MODE != MODE_RHS);
+        volume_term<P, Real>(s, hbh, G, g, dt, A);
+        source_term<P, Real>(s, G, a.ph, dt, A);
+    }
+    __syncthreads();
+
+    // 2. one flux per edge item
+    const int i0 = item_off[blk], i1 = item_off[blk + 1];
+    for (int it = i0 + (int)l; it < i1; it += BLOCK) {
+        const unsigned w = items[it];
+        const int la = (int)(w & 255u), ka = (int)((w >> 8) & 3u), lb = (int)((w >> 10) & 255u);
+        const int kb = (int)((w >> 18) & 3u);
+        const unsigned kind = (w >> 20) & 3u;
+        const unsigned ea = e0 + (unsigned)la;
+        const int va = (ka + 1) % 3, vb = (ka + 2) % 3;
+        const double4 pa = m.vtx[(unsigned)bEv.ld(va, ea * 4u)];
+        const double4 pb = m.vtx[(unsigned)bEv.ld(vb, ea * 4u)];
+        const double dx = pb.x - pa.x, dy = pb.y - pa.y;
+        const double len2 = dx * dx + dy * dy;
+        const Real nx = Real(dy), ny = Real(-dx);          // |E| n of side a
+        const double hmid = 0.5 * (pa.z + pb.z);
+        const double hbt[2] = {hmid, (pb.z - pa.z) * INV_2SQRT3};
+        Real tm[5][NT], tp[5][NT];
+        traces_of<P, Real>(S, la, ka, tm);
+        const Real xbm = Real(SQRT2) * S.C[0][la];
+        const Real unbm = fabs(fma(Real(SQRT2) * S.C[3 * K][la], nx, Real(SQRT2) * S.C[4 * K][la] * ny));
+        Real unm[NT], qnm[NT], unp[NT], qnp[NT];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            unm[c] = fma(tm[3][c], nx, tm[4][c] * ny);
+            qnm[c] = fma(tm[1][c], nx, tm[2][c] * ny);
+        }
+        Real xbp, unbp;
+        if (kind == EK_PAIR || kind == EK_EXT) {
+            Real x0, u0, v0;
+            if (kind == EK_PAIR) {
+                traces_of<P, Real>(S, lb, kb, tp);
+                x0 = S.C[0][lb];
+                u0 = S.C[3 * K][lb];
+                v0 = S.C[4 * K][lb];
+            } else {
+                const int nb = bNb.ld(ka, ea * 4u);
+                const int kk = (m.enbk[ea] >> (2 * ka)) & 3;
+                const unsigned un_ = (unsigned)nb * (unsigned)sizeof(Real);
+#pragma unroll
+                for (int f = 0; f < 5; ++f)
+#pragma unroll
+                    for (int c = 0; c < NT; ++c) tp[f][c] = Real(0);
+                x0 = Real(0); u0 = Real(0); v0 = Real(0);
+#pragma unroll
+                for (int n = 0; n < K; ++n) {
+                    const Real fv[5] = {bC.ld(0 * KS + n, un_), bC.ld(1 * KS + n, un_), bC.ld(2 * KS + n, un_),
+                                        bU.ld(0 * KS + n, un_), bU.ld(1 * KS + n, un_)};
+                    if (n == 0) { x0 = fv[0]; u0 = fv[3]; v0 = fv[4]; }
+#pragma unroll
+                    for (int c = 0; c < NT && c <= TDEG[n]; ++c) {
+                        const Real r = S.R[kk][n][c];
+#pragma unroll
+                        for (int f = 0; f < 5; ++f) tp[f][c] = fma(fv[f], r, tp[f][c]);
+                    }
+                }
+            }
+            // the other side runs along the edge in the opposite direction
+#pragma unroll
+            for (int c = 1; c < NT; c += 2)
+#pragma unroll
+                for (int f = 0; f < 5; ++f) tp[f][c] = -tp[f][c];
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                unp[c] = fma(tp[3][c], nx, tp[4][c] * ny);
+                qnp[c] = fma(tp[1][c], nx, tp[2][c] * ny);
+            }
+            xbp = Real(SQRT2) * x0;
+            unbp = fabs(fma(Real(SQRT2) * u0, nx, Real(SQRT2) * v0 * ny));
+        } else if (kind == EK_LAND) {
+            // mirror: xi+ = xi-, normal parts of q and u change sign
+            const Real m2 = Real(-2.0 / len2);
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                tp[0][c] = tm[0][c];
+                unp[c] = -unm[c];
+                qnp[c] = -qnm[c];
+                tp[1][c] = fma(m2 * qnm[c], nx, tm[1][c]);
+                tp[2][c] = fma(m2 * qnm[c], ny, tm[2][c]);
+            }
+            xbp = xbm;
+            unbp = unbm;
+        } else {
+            // open sea: xi+ = xi_hat(t), q and u copied
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                tp[0][c] = c == 0 ? Real(xihat) : Real(0);
+                tp[1][c] = tm[1][c];
+                tp[2][c] = tm[2][c];
+                unp[c] = unm[c];
+                qnp[c] = qnm[c];
+            }
+            xbp = Real(xihat);
+            unbp = unbm;
+        }
+        // penalty from constant parts at the edge midpoint (eq:lambda), times |E|
+        Real lam;
+        if constexpr (std::is_same<Real, double>::value)
+            lam = tmax(unbm, unbp) + sqrt(g * (tmax(xbm, xbp) + hmid) * len2);
+        else
+            lam = tmax(unbm, unbp) + Real(sqrt(g * (double(tmax(xbm, xbp)) + hmid) * len2));
+        const Real hg = Real(0.5 * g);
+        Real F[3][NT];
+        double Wf[NT];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const Real pb = hg * (prod1<NT, Real>(c, tm[0], tm[0]) + prod1<NT, Real>(c, tp[0], tp[0]));
+            const Real mU = prod1<NT, Real>(c, tm[1], unm) + prod1<NT, Real>(c, tp[1], unp);
+            const Real mV = prod1<NT, Real>(c, tm[2], unm) + prod1<NT, Real>(c, tp[2], unp);
+            Real fx = Real(0.5) * (qnm[c] + qnp[c] + lam * (tm[0][c] - tp[0][c]));
+            if (kind == EK_LAND) fx = 0;   // q.n = 0: no mass flux through land
+            F[0][c] = fx;
+            F[1][c] = Real(0.5) * (mU + pb * nx + lam * (tm[1][c] - tp[1][c]));
+            F[2][c] = Real(0.5) * (mV + pb * ny + lam * (tm[2][c] - tp[2][c]));
+            // bathymetry part of the pressure, (P- + P+)/2 = g (xi- + xi+) h_b / 2
+            double wv = 0.0;
+#pragma unroll
+            for (int aa = 0; aa < NT; ++aa) {
+                const double xs = double(tm[0][aa]) + double(tp[0][aa]);
+#pragma unroll
+                for (int bb = 0; bb < 2 && bb < NT; ++bb)
+                    if (TG[c][aa][bb] != 0.0) wv = fma(TG[c][aa][bb] * hbt[bb], xs, wv);
+            }
+            Wf[c] = 0.5 * g * wv;
+        }
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) S.F[j * NT + c][ka][la] = F[j][c];
+            S.W[c][ka][la] = Wf[c];
+        }
+        if (kind == EK_PAIR) {
+            // the second side: the same flux with the opposite normal, reversed along the edge
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) S.F[j * NT + c][kb][lb] = (c & 1) ? F[j][c] : -F[j][c];
+                S.W[c][kb][lb] = (c & 1) ? -Wf[c] : Wf[c];
+            }
+        }
+    }
+    __syncthreads();
+    if (!live) return;
+
+    // 3. lift the three edge fluxes, finish the stage
+    const double dt_det = dt / G.det;
+    const Real sc = Real(dt_det);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int ka = (k + 1) % 3, kb = (k + 2) % 3;
+        const double dx = G.X[kb] - G.X[ka], dy = G.Y[kb] - G.Y[ka];
+        Real FX[NT], FU[NT], FV[NT];
+        double FWx[NT], FWy[NT];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            FX[c] = sc * S.F[0 * NT + c][k][l];
+            FU[c] = sc * S.F[1 * NT + c][k][l];
+            FV[c] = sc * S.F[2 * NT + c][k][l];
+            const double FW = S.W[c][k][l] * dt_det;
+            FWx[c] = FW * dy;
+            FWy[c] = FW * -dx;
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            Real a0 = A.L[0][q], a1 = A.L[1][q], a2 = A.L[2][q];
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                if (TR[k][q][c] == 0.0) continue;
+                const Real r = Real(TR[k][q][c]);
+                a0 = fma(-r, FX[c], a0);
+                a1 = fma(-r, FU[c], a1);
+                a2 = fma(-r, FV[c], a2);
+            }
+            A.L[0][q] = a0; A.L[1][q] = a1; A.L[2][q] = a2;
+            double w0 = A.w(0, q), w1 = A.w(1, q);
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                if (TR[k][q][c] == 0.0) continue;
+                w0 = fma(-TR[k][q][c], FWx[c], w0);
+                w1 = fma(-TR[k][q][c], FWy[c], w1);
+            }
+            A.w(0, q) = w0; A.w(1, q) = w1;
+        }
+    }
+    if constexpr (Acc<P, Real>::SPLIT) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            A.L[1][q] += Real(A.W[0][q]);
+            A.L[2][q] += Real(A.W[1][q]);
+        }
+    }
+    if (a.src) {
+        const Buf<Real> bS(a.src, 3 * KS, stride);
+        const Real rdt = Real(dt);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int q = 0; q < K; ++q) A.L[j][q] = fma(rdt, bS.ld(j * KS + q, off), A.L[j][q]);
+    }
+    if constexpr (MODE == MODE_RHS) {
+        const Buf<Real> bL(a.Lout, 3 * KS, stride);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int q = 0; q < K; ++q) bL.st(j * KS + q, off, A.L[j][q]);
+    } else {
+        finish_stage<P, Real, MODE>(a, e, G, hbh, K, A.L, a.flag);
+    }
+}
+
 // ------------------------------------------------------------ kernels
 // Full stage of every element at one order P (unseparated scheme), or, with
 // SEP, the base part of the order-separated scheme: every element evaluated
@@ -1374,6 +1676,40 @@ hipError_t emit(Sink &k, const void *fn, dim3 grid, dim3 block, void **args)
 hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, Sink &k)
 {
     return fp32 ? stage_r<float>(p, mode, sep, args, k) : stage_r<double>(p, mode, sep, args, k);
+}
+
+template <int P, typename Real>
+hipError_t stage_sh_p(int mode, const void *args, const unsigned *items, const int *item_off, Sink &k)
+{
+    StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
+    if (a.m.ne <= 0) return hipSuccess;
+    void *kargs[] = {&a, &items, &item_off};
+    const void *fn = mode == MODE_RHS      ? reinterpret_cast<const void *>(&k_stage_sh<P, Real, MODE_RHS>)
+                     : mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_stage_sh<P, Real, MODE_STAGE1>)
+                                           : reinterpret_cast<const void *>(&k_stage_sh<P, Real, MODE_STAGE2>);
+    return emit(k, fn, dim3((a.m.ne + BLOCK - 1) / BLOCK), dim3(BLOCK), kargs);
+}
+
+bool stage_sh_supported(int p, bool fp32) { return p >= 0 && (p <= 2 || (p == 3 && fp32)); }
+
+hipError_t launch_stage_sh(int p, bool fp32, int mode, const void *args, const unsigned *items, const int *item_off,
+                           Sink &k)
+{
+    if (fp32) {
+        switch (p) {
+        case 0: return stage_sh_p<0, float>(mode, args, items, item_off, k);
+        case 1: return stage_sh_p<1, float>(mode, args, items, item_off, k);
+        case 2: return stage_sh_p<2, float>(mode, args, items, item_off, k);
+        case 3: return stage_sh_p<3, float>(mode, args, items, item_off, k);
+        }
+    } else {
+        switch (p) {
+        case 0: return stage_sh_p<0, double>(mode, args, items, item_off, k);
+        case 1: return stage_sh_p<1, double>(mode, args, items, item_off, k);
+        case 2: return stage_sh_p<2, double>(mode, args, items, item_off, k);
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, hipStream_t s)
