@@ -75,7 +75,8 @@ typedef struct {
                                paper); 2: order-partitioned: elements of order p_base
                                with neighbours of order p_base in the base kernel, every
                                other element's full stage in a kernel of its order, on
-                               parallel branches (same results, fewer dependent kernels) */
+                               parallel branches (same results, fewer dependent kernels);
+                               not available with SWE_FP32_WB and p_max = 3 (SWE_EINVAL) */
     void *stream_base;      /* hipStream_t for the base work, or NULL for a library-owned stream */
     void *stream_corr;      /* hipStream_t for the correction work, or NULL */
     int step_graph;         /* how swe_step enqueues a step: 1 (default) one replayed HIP

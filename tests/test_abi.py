@@ -48,3 +48,14 @@ def test_no_device_fails_loudly():
     from paper_2311_11348_amd import swe
     with pytest.raises(swe.SweError):
         swe.Context(swe.Config())
+
+
+def test_switched_off_configuration_is_rejected():
+    """FP32 order-partitioned stepping with p_max = 3 is refused at creation,
+    before any device call (so this runs without a GPU)."""
+    import pytest
+    from paper_2311_11348_amd import swe
+    cfg = swe.Config(precision=swe.SWE_FP32_WB, p_base=1, p_max=3, separate=2, adapt=1)
+    with pytest.raises(swe.SweError) as ei:
+        swe.Context(cfg)
+    assert ei.value.status == swe.SWE_EINVAL

@@ -67,6 +67,8 @@ def test_partitioned_adaptive_fp64(graph):
     assert err < 1e-12
 
 
+@pytest.mark.skip(reason="FP32 order-partitioned stepping with orders up to 3 is switched off: one run of it "
+                         "aborted on the device and no cause has been found in the source")
 def test_partitioned_matches_separated_fp32():
     prob = I.config_c3(n=32)
     orc = Oracle.from_problem(prob)
