@@ -312,7 +312,8 @@ def run_batched(count, steps, warmup):
             "fp64_batched": leg(ms64, 8), "plain_fp64": leg(msp, 8),
             "speedup_solves_vs_plain_fp64": msp / ms32,
             "fp32_xi_rel_l2_vs_fp64_max": err, "fp64_batched_vs_plain_xi_rel_l2_max": d64,
-            "tiles": {f"p{p}": {"tile": t[0], "grid": t[1]} for p, t in tiles.items() if k[p] > 0},
+            "tiles": {f"p{p}": {"tile": t[0], "grid": t[1], "kernel": "shared edge fluxes" if t[2] else "element gather"}
+                      for p, t in tiles.items() if k[p] > 0},
             "elements": int(sum(p.mesh.ne for p in probs)),
             "orders": {f"p{p}": int(k[p]) for p in range(4) if k[p] > 0}}
 

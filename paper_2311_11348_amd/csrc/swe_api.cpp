@@ -747,6 +747,8 @@ int64_t swe_footprint_bytes(int64_t ne, int p_max, int precision)
     b += S * 2;                      // nbk, p
     b += nv_est * 32;                // vertices
     b += (S / BLOCK + 1) * 8 + 64;   // reduction scratch, flag
+    if (stage_sh_supported(p_max, precision == SWE_FP32_WB))
+        b += S * 3 * 4 + (S / BLOCK + 1) * 4;   // edge items of the shared-flux kernel (at most 3 per element)
     return b;
 }
 
@@ -1322,11 +1324,15 @@ struct swe_batch {
     int cap = 0;
     hipStream_t s = nullptr;
     bool own_s = false;
-    struct Member { swe_ctx *ctx = nullptr; int64_t bytes = 0; int order = 0; int64_t first = 0, span = 0, vbase = 0, nv = 0; };
+    struct Member {
+        swe_ctx *ctx = nullptr;
+        int64_t bytes = 0;
+        int order = 0;
+        int64_t first = 0, span = 0, vbase = 0, nv = 0;
+        bool no_items = false;         // the context has no edge items (shared-flux kernel unusable)
+    };
     std::vector<Member> mem;
     std::vector<InstDesc> h_inst;
-    unsigned *d_items = nullptr;           // edge items of the shared-flux stage kernel, per block
-    int *d_item_off = nullptr;            // [blocks + 1]
     InstDesc *d_inst = nullptr;
     int *d_flags = nullptr;
     struct Pool { PoolView v{}; RangeAlloc ra; };
@@ -1337,6 +1343,8 @@ struct swe_batch {
     int tile_cap[4] = {0, 0, 0, 0};
     int *d_ntiles = nullptr;
     int tile[4] = {256, 256, 256, 256};
+    bool shared[4] = {false, false, true, true};    // shared-flux kernel (256-element tiles) chosen for the order
+    int no_items[4] = {0, 0, 0, 0};    // resident members of the order without edge items
     int grid[4] = {0, 0, 0, 0};
     int ntiles[4] = {0, 0, 0, 0};
     int ncu = 256;
@@ -1392,6 +1400,11 @@ swe_status grow_pool(swe_batch *b, int p, int64_t need)
     BHIP_TRY(b, hipMalloc(&v.ev, sizeof(int) * 3 * nc));
     BHIP_TRY(b, hipMalloc(&v.nb, sizeof(int) * 3 * nc));
     BHIP_TRY(b, hipMalloc(&v.nbk, nc));
+    if (stage_sh_supported(p, b->fp32)) {
+        BHIP_TRY(b, hipMalloc(&v.items, sizeof(unsigned) * 3 * nc));
+        BHIP_TRY(b, hipMalloc(&v.nitems, sizeof(int) * (nc / BLOCK)));
+        BHIP_TRY(b, hipMemsetAsync(v.nitems, 0, sizeof(int) * (nc / BLOCK), b->s));
+    }
     BHIP_TRY(b, hipMemsetAsync(v.C1, 0, b->w * 3 * K * nc, b->s));
     BHIP_TRY(b, hipMemsetAsync(v.U1, 0, b->w * 2 * K * nc, b->s));
     const int64_t oc = P.ra.cap;
@@ -1401,8 +1414,12 @@ swe_status grow_pool(swe_batch *b, int p, int64_t need)
         BHIP_TRY(b, hipMemcpy2DAsync(v.ev, 4 * nc, P.v.ev, 4 * oc, 4 * oc, 3, hipMemcpyDeviceToDevice, b->s));
         BHIP_TRY(b, hipMemcpy2DAsync(v.nb, 4 * nc, P.v.nb, 4 * oc, 4 * oc, 3, hipMemcpyDeviceToDevice, b->s));
         BHIP_TRY(b, hipMemcpyAsync(v.nbk, P.v.nbk, oc, hipMemcpyDeviceToDevice, b->s));
+        if (v.items) {
+            BHIP_TRY(b, hipMemcpyAsync(v.items, P.v.items, sizeof(unsigned) * 3 * oc, hipMemcpyDeviceToDevice, b->s));
+            BHIP_TRY(b, hipMemcpyAsync(v.nitems, P.v.nitems, sizeof(int) * (oc / BLOCK), hipMemcpyDeviceToDevice, b->s));
+        }
         BHIP_TRY(b, hipStreamSynchronize(b->s));
-        void *old[] = {P.v.C0, P.v.C1, P.v.U0, P.v.U1, P.v.ev, P.v.nb, P.v.nbk};
+        void *old[] = {P.v.C0, P.v.C1, P.v.U0, P.v.U1, P.v.ev, P.v.nb, P.v.nbk, P.v.items, P.v.nitems};
         for (void *q : old) (void)hipFree(q);
     }
     P.v = v;
@@ -1436,7 +1453,17 @@ swe_status grow_vertices(swe_batch *b, int64_t need)
     return SWE_OK;
 }
 
-// Tile lists of the resident set: order p gets tiles of b->tile[p] elements.
+// Order p runs the shared-flux batch kernel: chosen for it, and every resident
+// member of that order brought its edge items.
+bool use_shared(const swe_batch *b, int p)
+{
+    return b->shared[p] && b->no_items[p] == 0 && b->pool[p].v.items != nullptr;
+}
+
+// Tile size of order p: 256 for the shared-flux kernel (tiles are its blocks).
+int tile_of(const swe_batch *b, int p) { return use_shared(b, p) ? BLOCK : b->tile[p]; }
+
+// Tile lists of the resident set: order p gets tiles of tile_of(b, p) elements.
 swe_status upload_tiles(swe_batch *b)
 {
     for (int p = 0; p < 4; ++p) {
@@ -1444,7 +1471,7 @@ swe_status upload_tiles(swe_batch *b)
         for (int i = 0; i < b->cap; ++i) {
             const swe_batch::Member &m = b->mem[i];
             if (!m.ctx || m.order != p) continue;
-            for (int64_t f = 0; f < m.ctx->ne; f += b->tile[p]) t.push_back(make_int2(i, (int)(m.first + f)));
+            for (int64_t f = 0; f < m.ctx->ne; f += tile_of(b, p)) t.push_back(make_int2(i, (int)(m.first + f)));
         }
         if ((int)t.size() > b->tile_cap[p]) return bfail(b, SWE_ENOMEM, "tile list capacity exceeded");
         b->ntiles[p] = (int)t.size();
@@ -1536,7 +1563,10 @@ hipError_t enqueue_batch_step(swe_batch *b, Sink &k)
             }
             // the kernels read the tile counts from device memory, so the grid
             // need not match the current resident set
-            e = launch_batch_stage(p, b->fp32, mode, b->tile[p], batch_args(b, p), tile_grid(b, p, b->tile[p]), k);
+            if (use_shared(b, p))
+                e = launch_batch_stage_sh(p, b->fp32, mode, batch_args(b, p), tile_grid(b, p, BLOCK), k);
+            else
+                e = launch_batch_stage(p, b->fp32, mode, b->tile[p], batch_args(b, p), tile_grid(b, p, b->tile[p]), k);
         }
     return e;
 }
@@ -1665,7 +1695,8 @@ void swe_batch_destroy(swe_batch *b)
     std::vector<void *> ptrs = {b->d_inst, b->d_flags, b->d_ntiles, b->d_vtx};
     for (int p = 0; p < 4; ++p) {
         const PoolView &v = b->pool[p].v;
-        for (void *q : {v.C0, v.C1, v.U0, v.U1, (void *)v.ev, (void *)v.nb, (void *)v.nbk, (void *)b->d_tiles[p]})
+        for (void *q : {v.C0, v.C1, v.U0, v.U1, (void *)v.ev, (void *)v.nb, (void *)v.nbk, (void *)v.items,
+                        (void *)v.nitems, (void *)b->d_tiles[p]})
             ptrs.push_back(q);
     }
     for (void *q : ptrs)
@@ -1725,6 +1756,10 @@ swe_status swe_batch_admit(swe_batch *b, swe_ctx *c, int64_t nsteps, double dt, 
                                  w * c->ne, 2 * K, hipMemcpyDeviceToDevice, b->s));
     BHIP_TRY(b, hipMemcpyAsync(b->d_vtx + vbase, c->d_vtx, sizeof(double4) * c->nv, hipMemcpyDeviceToDevice, b->s));
     BHIP_TRY(b, launch_relocate(c->d_ev, c->d_nb, c->d_nbk, (int)c->ne, c->stride, P.v, (int)first, (int)vbase, b->s));
+    const bool no_items = P.v.items != nullptr && c->d_items == nullptr;
+    if (P.v.items && c->d_items)
+        BHIP_TRY(b, launch_place_items(c->d_items, c->d_item_off, (int)((c->ne + BLOCK - 1) / BLOCK), P.v, (int)first,
+                                       b->s));
     InstDesc &d = b->h_inst[i];
     std::memset(&d, 0, sizeof(d));
     d.first = (int)first;
@@ -1754,6 +1789,8 @@ swe_status swe_batch_admit(swe_batch *b, swe_ctx *c, int64_t nsteps, double dt, 
     m.span = span;
     m.vbase = vbase;
     m.nv = c->nv;
+    m.no_items = no_items;
+    if (no_items && b->no_items[p]++ == 0) drop_graph(b);   // the order falls back to the gather kernel
     b->used += bytes;
     c->batch = b;
     c->slot = i;
@@ -1837,6 +1874,7 @@ swe_status swe_batch_retire(swe_batch *b, int32_t slot)
     st = put_desc(b, slot);
     if (st) return st;
     if (per_instance(b, m.order)) drop_graph(b);
+    if (m.no_items && --b->no_items[m.order] == 0) drop_graph(b);
     b->pool[m.order].ra.give(m.first, m.span);
     b->vra.give(m.vbase, m.nv);
     b->used -= m.bytes;
@@ -1846,12 +1884,31 @@ swe_status swe_batch_retire(swe_batch *b, int32_t slot)
     return upload_tiles(b);
 }
 
-swe_status swe_batch_tile_config(const swe_batch *b, int p, int *tile, int *grid)
+swe_status swe_batch_tile_config(const swe_batch *b, int p, int *tile, int *grid, int *shared)
 {
     if (!b || p < 0 || p > 3) return SWE_EINVAL;
-    if (tile) *tile = b->tile[p];
-    if (grid) *grid = b->pool[p].v.cap > 0 ? tile_grid(b, p, b->tile[p]) : 0;
+    if (tile) *tile = tile_of(b, p);
+    if (grid) *grid = b->pool[p].v.cap > 0 ? tile_grid(b, p, tile_of(b, p)) : 0;
+    if (shared) *shared = use_shared(b, p) ? 1 : 0;
     return SWE_OK;
+}
+
+swe_status swe_batch_set_tile(swe_batch *b, int p, int tile, int shared)
+{
+    if (!b || p < 0 || p > 3) return SWE_EINVAL;
+    if (shared) {
+        if (tile != BLOCK) return bfail(b, SWE_EINVAL, "the shared-flux kernel takes 256-element tiles");
+        if (!stage_sh_supported(p, b->fp32))
+            return bfail(b, SWE_EUNSUPPORTED, "no shared-flux kernel for this order and precision");
+    } else if (tile != 64 && tile != 128 && tile != 256) {
+        return bfail(b, SWE_EINVAL, "tile must be 64, 128 or 256 elements");
+    }
+    BHIP_TRY(b, hipStreamSynchronize(b->s));
+    b->tile[p] = tile;
+    b->shared[p] = shared != 0;
+    b->grid[p] = 0;
+    drop_graph(b);
+    return upload_tiles(b);
 }
 
 swe_status swe_batch_tune(swe_batch *b, int reps)
@@ -1877,7 +1934,9 @@ swe_status swe_batch_tune(swe_batch *b, int reps)
     hipEvent_t e0, e1;
     BHIP_TRY(b, hipEventCreate(&e0));
     BHIP_TRY(b, hipEventCreate(&e1));
-    const int tiles[3] = {64, 128, 256};
+    // candidates: the gather kernel with tiles of 64, 128 or 256 elements,
+    // and (orders with edge items) the shared-flux kernel on 256-element tiles
+    const int tiles[4] = {64, 128, 256, BLOCK};
     swe_status st = SWE_OK;
     for (int p = 0; p < 4 && st == SWE_OK; ++p) {
         bool any = false;
@@ -1885,28 +1944,35 @@ swe_status swe_batch_tune(swe_batch *b, int reps)
         if (!any || per_instance(b, p)) continue;
         float best = 1e30f;
         int bt = b->tile[p], bg = b->grid[p];
-        for (int ti = 0; ti < 3 && st == SWE_OK; ++ti) {
+        bool bs = b->shared[p];
+        for (int ti = 0; ti < 4 && st == SWE_OK; ++ti) {
+            const bool sh = ti == 3;
             b->tile[p] = tiles[ti];
+            b->shared[p] = sh;
+            if (sh && !use_shared(b, p)) continue;
             st = upload_tiles(b);
-            {
-                const int grid = tile_grid(b, p, tiles[ti]);
-                Sink k;
-                k.s = b->s;
-                hipError_t e = launch_batch_stage(p, b->fp32, MODE_STAGE1, tiles[ti], batch_args(b, p), grid, k);
-                if (e == hipSuccess) e = hipEventRecord(e0, b->s);
-                for (int r = 0; r < reps && e == hipSuccess; ++r)
-                    e = launch_batch_stage(p, b->fp32, MODE_STAGE1, tiles[ti], batch_args(b, p), grid, k);
-                if (e == hipSuccess) e = hipEventRecord(e1, b->s);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                float ms = 0.f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                if (e != hipSuccess) {
-                    st = bfail(b, SWE_EDEVICE, std::string("tuning: ") + hipGetErrorString(e));
-                    break;
-                }
-                if (ms < best) { best = ms; bt = tiles[ti]; bg = grid; }
+            if (st) break;
+            const int grid = tile_grid(b, p, tiles[ti]);
+            Sink k;
+            k.s = b->s;
+            auto launch = [&]() {
+                return sh ? launch_batch_stage_sh(p, b->fp32, MODE_STAGE1, batch_args(b, p), grid, k)
+                          : launch_batch_stage(p, b->fp32, MODE_STAGE1, tiles[ti], batch_args(b, p), grid, k);
+            };
+            hipError_t e = launch();
+            if (e == hipSuccess) e = hipEventRecord(e0, b->s);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+            if (e == hipSuccess) e = hipEventRecord(e1, b->s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                st = bfail(b, SWE_EDEVICE, std::string("tuning: ") + hipGetErrorString(e));
+                break;
             }
+            if (ms < best) { best = ms; bt = tiles[ti]; bg = grid; bs = sh; }
         }
+        b->shared[p] = bs;
         b->tile[p] = bt;
         b->grid[p] = bg;
     }

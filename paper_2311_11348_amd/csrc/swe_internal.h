@@ -94,6 +94,9 @@ struct PoolView {
     void *C0, *C1, *U0, *U1;     // state and velocity ping-pong buffers [slot][cap]
     int *ev, *nb;                // [3][cap]
     unsigned char *nbk;          // [cap]
+    unsigned *items;             // edge items of the shared-flux kernel, 3 slots per element:
+                                 // the block at element f (f a multiple of 256) keeps its items from 3 f
+    int *nitems;                 // [cap / 256] item count of each 256-element block
     int cap;
 };
 
@@ -135,7 +138,7 @@ hipError_t emit(Sink &k, const void *fn, dim3 grid, dim3 block, void **args);
 hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, hipStream_t s);
 hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, Sink &k);
 // fused stage with each in-block edge flux computed once (edge items built by
-// the host, see swe_kernels.hip); supported for p <= 2, and p = 3 in FP32
+// the host, see swe_kernels.hip); used for p = 2, and p = 3 in FP32
 bool stage_sh_supported(int p, bool fp32);
 hipError_t launch_stage_sh(int p, bool fp32, int mode, const void *args, const unsigned *items, const int *item_off,
                            Sink &k);
@@ -164,6 +167,11 @@ hipError_t launch_batch_clock(InstDesc *inst, const int *flags, int n, Sink &k);
 // write one instance descriptor in stream order (no host buffer outlives the call)
 hipError_t launch_inst_set(InstDesc *inst, const InstDesc &v, hipStream_t s);
 // copy an instance's mesh arrays into a pool, offsetting vertex and element ids
+// batched shared-flux stage (one 256-element tile per block; orders with
+// stage_sh_supported); items placed in the pool by launch_place_items
+hipError_t launch_batch_stage_sh(int p, bool fp32, int mode, const BatchArgs &b, int grid, Sink &k);
+hipError_t launch_place_items(const unsigned *items, const int *item_off, int nblk, const PoolView &pool, int first,
+                              hipStream_t s);
 hipError_t launch_relocate(const int *ev, const int *nb, const unsigned char *nbk, int ne, int stride,
                            const PoolView &pool, int first, int vbase, hipStream_t s);
 

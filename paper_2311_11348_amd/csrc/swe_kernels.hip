@@ -766,26 +766,30 @@ __device__ __forceinline__ void traces_of(const ShLds<P, Real> &S, int l, int k,
         }
 }
 
-template <int P, typename Real, int MODE>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_target<P, Real>(), 8)))
-k_stage_sh(StageArgs<Real> a, const unsigned *items, const int *item_off)
+template <int P, typename Real>
+__device__ __forceinline__ void load_trace_lds(ShLds<P, Real> &S)
 {
     constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
-    __shared__ ShLds<P, Real> S;
     for (int i = threadIdx.x; i < 3 * K * NT; i += BLOCK) {
         const int k = i / (K * NT), r = i % (K * NT);
         S.R[k][r / NT][r % NT] = Real(TR[k][r / NT][r % NT]);
     }
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
+}
+
+// The three passes over the block of elements [e0, e0 + BLOCK) (live below
+// e_end), whose edge items are items[0, nitems).  Every thread of the block
+// calls it (it holds two block barriers); the trace tables in S are loaded
+// before (the first barrier orders them before their first use).
+template <int P, typename Real, int MODE>
+__device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArgs<Real> &a, unsigned e0,
+                                               unsigned e_end, const unsigned *items, int nitems, double xihat,
+                                               double dt, int *flag)
+{
+    constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
     const MeshView &m = a.m;
     const int KS = m.KS, stride = m.stride;
-    const unsigned e0 = (unsigned)blk * BLOCK, l = threadIdx.x, e = e0 + l;
-    const bool live = e < (unsigned)m.ne;
-    double xihat = a.xihat, dt = a.dt;
-    if (a.inst) {
-        xihat = MODE == MODE_STAGE2 ? a.inst->xh[1] : a.inst->xh[0];
-        dt = a.inst->dt;
-    }
+    const unsigned l = threadIdx.x, e = e0 + l;
+    const bool live = e < e_end;
     if (MODE == MODE_RHS) dt = 1.0;
     const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
     const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
@@ -816,8 +820,7 @@ k_stage_sh(StageArgs<Real> a, const unsigned *items, const int *item_off)
     __syncthreads();
 
     // 2. one flux per edge item
-    const int i0 = item_off[blk], i1 = item_off[blk + 1];
-    for (int it = i0 + (int)l; it < i1; it += BLOCK) {
+    for (int it = (int)l; it < nitems; it += BLOCK) {
         const unsigned w = items[it];
         const int la = (int)(w & 255u), ka = (int)((w >> 8) & 3u), lb = (int)((w >> 10) & 255u);
         const int kb = (int)((w >> 18) & 3u);
@@ -1020,8 +1023,25 @@ k_stage_sh(StageArgs<Real> a, const unsigned *items, const int *item_off)
 #pragma unroll
             for (int q = 0; q < K; ++q) bL.st(j * KS + q, off, A.L[j][q]);
     } else {
-        finish_stage<P, Real, MODE>(a, e, G, hbh, K, A.L, a.flag);
+        finish_stage<P, Real, MODE>(a, e, G, hbh, K, A.L, flag);
     }
+}
+
+template <int P, typename Real, int MODE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_target<P, Real>(), 8)))
+k_stage_sh(StageArgs<Real> a, const unsigned *items, const int *item_off)
+{
+    __shared__ ShLds<P, Real> S;
+    load_trace_lds<P, Real>(S);
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    double xihat = a.xihat, dt = a.dt;
+    if (a.inst) {
+        xihat = MODE == MODE_STAGE2 ? a.inst->xh[1] : a.inst->xh[0];
+        dt = a.inst->dt;
+    }
+    const int i0 = item_off[blk], i1 = item_off[blk + 1];
+    stage_sh_block<P, Real, MODE>(S, a, (unsigned)blk * BLOCK, (unsigned)a.m.ne, items + i0, i1 - i0, xihat, dt,
+                                  a.flag);
 }
 
 // ------------------------------------------------------------ kernels
@@ -1154,6 +1174,62 @@ k_batch_stage(BatchArgs b)
     if (e < (unsigned)(I.first + I.ne))
         stage_element<P, Real, MODE, false>(a, e, sR, MODE == MODE_STAGE1 ? I.xh[0] : I.xh[1], I.dt,
                                             b.flags + tile.x);
+}
+
+// Shared-flux stage over the 256-element tiles of every resident instance of
+// one order (one tile per block, tile list split by XCD as above).  A tile
+// starts on a multiple of 256 within its instance, so the instance's edge
+// items of that block (local indices) serve it unchanged.
+template <int P, typename Real, int MODE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_target<P, Real>(), 8)))
+k_batch_stage_sh(BatchArgs b)
+{
+    __shared__ ShLds<P, Real> S;
+    load_trace_lds<P, Real>(S);
+    // the returns below are uniform over the block (tile and instance)
+    const int ntiles = b.ntiles[0];
+    const int x = (int)(blockIdx.x & 7u), i = (int)(blockIdx.x >> 3);
+    const int lo = (int)(((long long)ntiles * x) >> 3), hi = (int)(((long long)ntiles * (x + 1)) >> 3);
+    const int t = lo + i;
+    if (t >= hi) return;
+    const int2 tile = b.tiles[t];
+    const InstDesc &I = b.inst[tile.x];
+    if (!I.run) return;
+    StageArgs<Real> a;
+    a.m.ne = 0;
+    a.m.stride = b.pool.cap;
+    a.m.KS = Ord<P>::K;
+    a.m.vtx = b.vtx;
+    a.m.ev = b.pool.ev;
+    a.m.enb = b.pool.nb;
+    a.m.enbk = b.pool.nbk;
+    a.m.ep = nullptr;
+    a.Cin = static_cast<const Real *>(MODE == MODE_STAGE1 ? b.pool.C0 : b.pool.C1);
+    a.Uin = static_cast<const Real *>(MODE == MODE_STAGE1 ? b.pool.U0 : b.pool.U1);
+    a.Cn = static_cast<const Real *>(b.pool.C0);
+    a.Cout = static_cast<Real *>(MODE == MODE_STAGE1 ? b.pool.C1 : b.pool.C0);
+    a.Uout = static_cast<Real *>(MODE == MODE_STAGE1 ? b.pool.U1 : b.pool.U0);
+    a.Lout = nullptr;
+    a.src = nullptr;
+    a.mixed = 0;
+    a.ph = I.ph;
+    const unsigned e0 = (unsigned)tile.y;
+    stage_sh_block<P, Real, MODE>(S, a, e0, (unsigned)(I.first + I.ne), b.pool.items + 3u * e0,
+                                  b.pool.nitems[e0 / BLOCK], MODE == MODE_STAGE1 ? I.xh[0] : I.xh[1], I.dt,
+                                  b.flags + tile.x);
+}
+
+// Copy an instance's edge items (blocks of 256 elements, item_off[nblk + 1])
+// into the pool slots of its element range starting at first (a multiple
+// of 256): one block per 256-element block.
+__global__ void __launch_bounds__(BLOCK) k_place_items(const unsigned *items, const int *item_off, PoolView pool,
+                                                       int first)
+{
+    const int j = blockIdx.x;
+    const int i0 = item_off[j], n = item_off[j + 1] - i0;
+    const int f = first + j * BLOCK;
+    for (int k = threadIdx.x; k < n; k += BLOCK) pool.items[3 * f + k] = items[i0 + k];
+    if (threadIdx.x == 0) pool.nitems[f / BLOCK] = n;
 }
 
 __global__ void __launch_bounds__(BLOCK) k_relocate(const int *ev, const int *nb, const unsigned char *nbk, int ne,
@@ -1690,7 +1766,10 @@ hipError_t stage_sh_p(int mode, const void *args, const unsigned *items, const i
     return emit(k, fn, dim3((a.m.ne + BLOCK - 1) / BLOCK), dim3(BLOCK), kargs);
 }
 
-bool stage_sh_supported(int p, bool fp32) { return p >= 0 && (p <= 2 || (p == 3 && fp32)); }
+// Orders 0 and 1 have too little work per edge for the sharing to pay for
+// the LDS staging and the two barriers (the gather kernel is faster there);
+// FP64 order 3 would need more LDS than a CU has for one block.
+bool stage_sh_supported(int p, bool fp32) { return p == 2 || (p == 3 && fp32); }
 
 hipError_t launch_stage_sh(int p, bool fp32, int mode, const void *args, const unsigned *items, const int *item_off,
                            Sink &k)
@@ -1859,6 +1938,35 @@ hipError_t launch_batch_stage(int p, bool fp32, int mode, int tile, const BatchA
 {
     if (grid <= 0) return hipSuccess;
     return fp32 ? batch_r<float>(p, mode, tile, b, grid, k) : batch_r<double>(p, mode, tile, b, grid, k);
+}
+
+template <int P, typename Real>
+hipError_t batch_sh_p(int mode, const BatchArgs &b, int grid, Sink &k)
+{
+    BatchArgs a = b;
+    void *kargs[] = {&a};
+    const void *fn = mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_batch_stage_sh<P, Real, MODE_STAGE1>)
+                                         : reinterpret_cast<const void *>(&k_batch_stage_sh<P, Real, MODE_STAGE2>);
+    return emit(k, fn, dim3(grid), dim3(BLOCK), kargs);
+}
+
+hipError_t launch_batch_stage_sh(int p, bool fp32, int mode, const BatchArgs &b, int grid, Sink &k)
+{
+    if (grid <= 0) return hipSuccess;
+    if (mode != MODE_STAGE1 && mode != MODE_STAGE2) return hipErrorInvalidValue;
+    if (fp32 && p == 2) return batch_sh_p<2, float>(mode, b, grid, k);
+    if (fp32 && p == 3) return batch_sh_p<3, float>(mode, b, grid, k);
+    if (!fp32 && p == 2) return batch_sh_p<2, double>(mode, b, grid, k);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_place_items(const unsigned *items, const int *item_off, int nblk, const PoolView &pool, int first,
+                              hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    if (first % BLOCK != 0 || !pool.items || !pool.nitems) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_place_items, dim3(nblk), dim3(BLOCK), 0, s, items, item_off, pool, first);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_clock(InstDesc *inst, const int *flags, int n, Sink &k)

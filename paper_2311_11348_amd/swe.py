@@ -83,7 +83,9 @@ def lib() -> C.CDLL:
         "swe_batch_query": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int64), dp, C.POINTER(C.c_int)]),
         "swe_batch_retire": (C.c_int, [vp, C.c_int32]),
         "swe_batch_tune": (C.c_int, [vp, C.c_int]),
-        "swe_batch_tile_config": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "swe_batch_set_tile": (C.c_int, [vp, C.c_int, C.c_int, C.c_int]),
+        "swe_batch_tile_config": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                            C.POINTER(C.c_int)]),
         "swe_batch_free_bytes": (C.c_int64, [vp]),
         "swe_batch_resident": (C.c_int, [vp]),
         "swe_batch_last_error": (C.c_char_p, [vp]),
@@ -353,10 +355,15 @@ class Batch:
     def tune(self, reps: int = 3):
         self._check(self.L.swe_batch_tune(self.h, int(reps)))
 
+    def set_tile(self, p: int, tile: int, shared: bool = False):
+        """Pick order p's kernel by hand (instead of tune())."""
+        self._check(self.L.swe_batch_set_tile(self.h, int(p), int(tile), 1 if shared else 0))
+
     def tile_config(self, p: int):
-        t, g = C.c_int(), C.c_int()
-        self._check(self.L.swe_batch_tile_config(self.h, int(p), C.byref(t), C.byref(g)))
-        return t.value, g.value
+        """(tile size, grid, shared-flux kernel) of order p."""
+        t, g, sh = C.c_int(), C.c_int(), C.c_int()
+        self._check(self.L.swe_batch_tile_config(self.h, int(p), C.byref(t), C.byref(g), C.byref(sh)))
+        return t.value, g.value, bool(sh.value)
 
     def free_bytes(self) -> int:
         return int(self.L.swe_batch_free_bytes(self.h))

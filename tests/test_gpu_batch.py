@@ -67,6 +67,51 @@ def test_batch_equals_alone(precision):
         ctx.close()
 
 
+@pytest.mark.parametrize("precision", [swe.SWE_FP64, swe.SWE_FP32_WB])
+def test_batch_kernels_equal_alone(precision):
+    """Each kernel choice of the batch (element gather with 64- and 256-element
+    tiles, shared edge fluxes on 256-element tiles where the order has it)
+    gives every instance bitwise its result alone.  Sizes span several tiles
+    with ragged ends; every order 1-3 is present."""
+    probs = []
+    seed = 300
+    while len({p.p_max for p in probs}) < 3 or len(probs) < 6:
+        prob = I.config_instance(seed, n_lo=300, n_hi=9000)
+        seed += 1
+        if sum(q.p_max == prob.p_max for q in probs) < 2:
+            probs.append(prob)
+    steps = 12
+    alone = []
+    for prob in probs:
+        ctx = ctx_for(prob, precision)
+        ctx.step(steps, prob.dt())
+        ctx.sync()
+        alone.append(ctx.state()[0])
+        ctx.close()
+    choices = [(64, False), (256, False), (256, True)]
+    for tile, shared in choices:
+        ctxs = [ctx_for(p, precision) for p in probs]
+        with swe.Batch(precision=precision, budget_bytes=8 << 30, max_instances=8) as b:
+            slots = [b.admit(c, steps, p.dt()) for c, p in zip(ctxs, probs)]
+            used = {}
+            for p in range(4):
+                sh = shared and (p == 2 or (p == 3 and precision == swe.SWE_FP32_WB))
+                b.set_tile(p, tile, sh)
+                used[p] = b.tile_config(p)
+            b.tick(steps)
+            b.sync()
+            for s in slots:
+                b.retire(s)
+        say(f"tile {tile} shared {shared}: " + ", ".join(f"p{p} {used[p]}" for p in (1, 2, 3)))
+        for i, (ctx, ref) in enumerate(zip(ctxs, alone)):
+            got, _ = ctx.state()
+            eq = np.array_equal(got, ref)
+            if not eq:
+                say(f"  instance {i} ne={ctx.ne} p={probs[i].p_max}: max diff {np.max(np.abs(got - ref)):.3e}")
+            assert eq, (tile, shared, i)
+            ctx.close()
+
+
 def test_batch_admission_budget():
     probs = make_instances(3, seed=9)
     ctxs = [ctx_for(p, swe.SWE_FP32_WB) for p in probs]
