@@ -927,10 +927,17 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t nv, const double *vxy, int64_t ne, c
                     }
         }
         ioff[(size_t)nblk] = (int)items.size();
-        HIP_TRY(c, hipMalloc(&c->d_items, sizeof(unsigned) * std::max<size_t>(items.size(), 1)));
-        HIP_TRY(c, hipMalloc(&c->d_item_off, sizeof(int) * ioff.size()));
-        if (!items.empty()) HIP_TRY(c, h2d(c, c->d_items, items.data(), sizeof(unsigned) * items.size()));
-        HIP_TRY(c, h2d(c, c->d_item_off, ioff.data(), sizeof(int) * ioff.size()));
+        // the kernel takes at most two items per lane; a block with more
+        // (a mesh ordering with long block boundaries) leaves the mesh to
+        // the element-gather kernel
+        int most = 0;
+        for (int64_t bi = 0; bi < nblk; ++bi) most = std::max(most, ioff[(size_t)bi + 1] - ioff[(size_t)bi]);
+        if (most <= 2 * BLOCK) {
+            HIP_TRY(c, hipMalloc(&c->d_items, sizeof(unsigned) * std::max<size_t>(items.size(), 1)));
+            HIP_TRY(c, hipMalloc(&c->d_item_off, sizeof(int) * ioff.size()));
+            if (!items.empty()) HIP_TRY(c, h2d(c, c->d_items, items.data(), sizeof(unsigned) * items.size()));
+            HIP_TRY(c, h2d(c, c->d_item_off, ioff.data(), sizeof(int) * ioff.size()));
+        }
     }
     if (separated(c) || c->cfg.adapt) {
         const int KB = K_OF[c->cfg.p_base];

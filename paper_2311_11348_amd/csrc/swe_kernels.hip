@@ -739,13 +739,38 @@ __device__ __forceinline__ void finish_stage(const StageArgs<Real> &a, unsigned 
 // edge (18-19) and the kind (20-21).
 constexpr unsigned EK_PAIR = 0, EK_EXT = 1, EK_LAND = 2, EK_OPEN = 3;
 
+// Waves per SIMD the shared-flux kernels are built for: what their LDS
+// allows (FP32 p = 2: 46 KB per 256-element block, three blocks per CU; FP32
+// p = 3 and FP64 p = 2: 62 and 74 KB, two blocks).
+template <int P, typename Real>
+constexpr int sh_waves()
+{
+    return (P <= 2 && !std::is_same<Real, double>::value) ? 3 : 2;
+}
+
+// Per-block LDS.  The state copy C is read by the edge pass only; the
+// per-edge results F, W are written after it (every lane holds its items'
+// results in registers across a barrier), so the two share the storage.
 template <int P, typename Real>
 struct ShLds {
     static constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
-    Real R[3][K][NT];          // trace matrices
-    Real C[5 * K][BLOCK];      // xi, U, V, u, v modes of the block's elements
-    Real F[3 * NT][3][BLOCK];  // flux modes (component, mode) per local edge and element
-    double W[NT][3][BLOCK];    // bathymetry part of the pressure flux, FP64
+    Real R[3][K][NT];              // trace matrices
+    union {
+        Real C[5 * K][BLOCK];      // xi, U, V, u, v modes of the block's elements
+        struct {
+            Real F[3 * NT][3][BLOCK];  // flux modes (component, mode) per local edge and element
+            double W[NT][3][BLOCK];    // bathymetry part of the pressure flux, FP64
+        } E;
+    } U;
+};
+
+// An edge item's results, kept in registers until the state copy is no
+// longer read.
+template <int P, typename Real>
+struct ShItem {
+    static constexpr int NT = Ord<P>::NT;
+    Real F[3][NT];
+    double W[NT];
 };
 
 template <int P, typename Real>
@@ -762,7 +787,7 @@ __device__ __forceinline__ void traces_of(const ShLds<P, Real> &S, int l, int k,
         for (int c = 0; c < NT && c <= TDEG[n]; ++c) {
             const Real r = S.R[k][n][c];
 #pragma unroll
-            for (int f = 0; f < 5; ++f) t[f][c] = fma(S.C[f * K + n][l], r, t[f][c]);
+            for (int f = 0; f < 5; ++f) t[f][c] = fma(S.U.C[f * K + n][l], r, t[f][c]);
         }
 }
 
@@ -776,10 +801,174 @@ __device__ __forceinline__ void load_trace_lds(ShLds<P, Real> &S)
     }
 }
 
-// The three passes over the block of elements [e0, e0 + BLOCK) (live below
-// e_end), whose edge items are items[0, nitems).  Every thread of the block
-// calls it (it holds two block barriers); the trace tables in S are loaded
-// before (the first barrier orders them before their first use).
+// The Lax-Friedrichs flux of one edge item, in the first side's orientation
+// and unscaled by dt / |det B| (the edge pass of the shared-flux kernels).
+template <int P, typename Real>
+__device__ __forceinline__ void sh_flux(const ShLds<P, Real> &S, const MeshView &m, const Buf<Real> &bC,
+                                        const Buf<Real> &bU, const Buf<int> &bEv, const Buf<int> &bNb, unsigned e0,
+                                        unsigned w, double xihat, double g, ShItem<P, Real> &out)
+{
+    constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
+    const int KS = m.KS;
+    const int la = (int)(w & 255u), ka = (int)((w >> 8) & 3u), lb = (int)((w >> 10) & 255u);
+    const int kb = (int)((w >> 18) & 3u);
+    const unsigned kind = (w >> 20) & 3u;
+    const unsigned ea = e0 + (unsigned)la;
+    const int va = (ka + 1) % 3, vb = (ka + 2) % 3;
+    const double4 pa = m.vtx[(unsigned)bEv.ld(va, ea * 4u)];
+    const double4 pb = m.vtx[(unsigned)bEv.ld(vb, ea * 4u)];
+    const double dx = pb.x - pa.x, dy = pb.y - pa.y;
+    const double len2 = dx * dx + dy * dy;
+    const Real nx = Real(dy), ny = Real(-dx);          // |E| n of side a
+    const double hmid = 0.5 * (pa.z + pb.z);
+    const double hbt[2] = {hmid, (pb.z - pa.z) * INV_2SQRT3};
+    Real tm[5][NT], tp[5][NT];
+    traces_of<P, Real>(S, la, ka, tm);
+    const Real xbm = Real(SQRT2) * S.U.C[0][la];
+    const Real unbm = fabs(fma(Real(SQRT2) * S.U.C[3 * K][la], nx, Real(SQRT2) * S.U.C[4 * K][la] * ny));
+    Real unm[NT], qnm[NT], unp[NT], qnp[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+        unm[c] = fma(tm[3][c], nx, tm[4][c] * ny);
+        qnm[c] = fma(tm[1][c], nx, tm[2][c] * ny);
+    }
+    Real xbp, unbp;
+    if (kind == EK_PAIR || kind == EK_EXT) {
+        Real x0, u0, v0;
+        if (kind == EK_PAIR) {
+            traces_of<P, Real>(S, lb, kb, tp);
+            x0 = S.U.C[0][lb];
+            u0 = S.U.C[3 * K][lb];
+            v0 = S.U.C[4 * K][lb];
+        } else {
+            const int nb = bNb.ld(ka, ea * 4u);
+            const int kk = (m.enbk[ea] >> (2 * ka)) & 3;
+            const unsigned un_ = (unsigned)nb * (unsigned)sizeof(Real);
+#pragma unroll
+            for (int f = 0; f < 5; ++f)
+#pragma unroll
+                for (int c = 0; c < NT; ++c) tp[f][c] = Real(0);
+            x0 = Real(0); u0 = Real(0); v0 = Real(0);
+#pragma unroll
+            for (int n = 0; n < K; ++n) {
+                const Real fv[5] = {bC.ld(0 * KS + n, un_), bC.ld(1 * KS + n, un_), bC.ld(2 * KS + n, un_),
+                                    bU.ld(0 * KS + n, un_), bU.ld(1 * KS + n, un_)};
+                if (n == 0) { x0 = fv[0]; u0 = fv[3]; v0 = fv[4]; }
+#pragma unroll
+                for (int c = 0; c < NT && c <= TDEG[n]; ++c) {
+                    const Real r = S.R[kk][n][c];
+#pragma unroll
+                    for (int f = 0; f < 5; ++f) tp[f][c] = fma(fv[f], r, tp[f][c]);
+                }
+            }
+        }
+        // the other side runs along the edge in the opposite direction
+#pragma unroll
+        for (int c = 1; c < NT; c += 2)
+#pragma unroll
+            for (int f = 0; f < 5; ++f) tp[f][c] = -tp[f][c];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            unp[c] = fma(tp[3][c], nx, tp[4][c] * ny);
+            qnp[c] = fma(tp[1][c], nx, tp[2][c] * ny);
+        }
+        xbp = Real(SQRT2) * x0;
+        unbp = fabs(fma(Real(SQRT2) * u0, nx, Real(SQRT2) * v0 * ny));
+    } else if (kind == EK_LAND) {
+        // mirror: xi+ = xi-, normal parts of q and u change sign
+        const Real m2 = Real(-2.0 / len2);
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            tp[0][c] = tm[0][c];
+            unp[c] = -unm[c];
+            qnp[c] = -qnm[c];
+            tp[1][c] = fma(m2 * qnm[c], nx, tm[1][c]);
+            tp[2][c] = fma(m2 * qnm[c], ny, tm[2][c]);
+        }
+        xbp = xbm;
+        unbp = unbm;
+    } else {
+        // open sea: xi+ = xi_hat(t), q and u copied
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            tp[0][c] = c == 0 ? Real(xihat) : Real(0);
+            tp[1][c] = tm[1][c];
+            tp[2][c] = tm[2][c];
+            unp[c] = unm[c];
+            qnp[c] = qnm[c];
+        }
+        xbp = Real(xihat);
+        unbp = unbm;
+    }
+    // penalty from constant parts at the edge midpoint (eq:lambda), times |E|
+    Real lam;
+    if constexpr (std::is_same<Real, double>::value)
+        lam = tmax(unbm, unbp) + sqrt(g * (tmax(xbm, xbp) + hmid) * len2);
+    else
+        lam = tmax(unbm, unbp) + Real(sqrt(g * (double(tmax(xbm, xbp)) + hmid) * len2));
+    const Real hg = Real(0.5 * g);
+    Real (&F)[3][NT] = out.F;
+    double (&Wf)[NT] = out.W;
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+        const Real pb = hg * (prod1<NT, Real>(c, tm[0], tm[0]) + prod1<NT, Real>(c, tp[0], tp[0]));
+        const Real mU = prod1<NT, Real>(c, tm[1], unm) + prod1<NT, Real>(c, tp[1], unp);
+        const Real mV = prod1<NT, Real>(c, tm[2], unm) + prod1<NT, Real>(c, tp[2], unp);
+        Real fx = Real(0.5) * (qnm[c] + qnp[c] + lam * (tm[0][c] - tp[0][c]));
+        if (kind == EK_LAND) fx = 0;   // q.n = 0: no mass flux through land
+        F[0][c] = fx;
+        F[1][c] = Real(0.5) * (mU + pb * nx + lam * (tm[1][c] - tp[1][c]));
+        F[2][c] = Real(0.5) * (mV + pb * ny + lam * (tm[2][c] - tp[2][c]));
+        // bathymetry part of the pressure, (P- + P+)/2 = g (xi- + xi+) h_b / 2
+        double wv = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < NT; ++aa) {
+            const double xs = double(tm[0][aa]) + double(tp[0][aa]);
+#pragma unroll
+            for (int bb = 0; bb < 2 && bb < NT; ++bb)
+                if (TG[c][aa][bb] != 0.0) wv = fma(TG[c][aa][bb] * hbt[bb], xs, wv);
+        }
+        Wf[c] = 0.5 * g * wv;
+    }
+}
+
+// Hand an item's flux to its sides: as computed to the first, negated and
+// reversed along the edge to the second (a pair inside the block).
+template <int P, typename Real>
+__device__ __forceinline__ void sh_store(ShLds<P, Real> &S, unsigned w, const ShItem<P, Real> &r)
+{
+    constexpr int NT = Ord<P>::NT;
+    const int la = (int)(w & 255u), ka = (int)((w >> 8) & 3u), lb = (int)((w >> 10) & 255u);
+    const int kb = (int)((w >> 18) & 3u);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) S.U.E.F[j * NT + c][ka][la] = r.F[j][c];
+        S.U.E.W[c][ka][la] = r.W[c];
+    }
+    if (((w >> 20) & 3u) == EK_PAIR) {
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) S.U.E.F[j * NT + c][kb][lb] = (c & 1) ? r.F[j][c] : -r.F[j][c];
+            S.U.E.W[c][kb][lb] = (c & 1) ? -r.W[c] : r.W[c];
+        }
+    }
+}
+
+// The passes over the block of elements [e0, e0 + BLOCK) (live below e_end),
+// whose edge items are items[0, nitems), nitems <= 2 BLOCK.  Every thread of
+// the block calls it (it holds three block barriers); the trace tables in S
+// are loaded before (the first barrier orders them before their first use).
+//   1. each lane (one element) loads its state into registers and copies it
+//      to LDS;
+//   2. each lane computes the flux of at most two edge items (a pair of
+//      elements of the block, an element and a neighbour outside it, a land
+//      or an open edge) from the state copies and keeps it in registers;
+//      once every lane is done reading the copies, the fluxes overwrite them,
+//      each stored for its first side and, for a pair, for the second;
+//   3. each lane adds its volume and source terms, lifts its three edge
+//      fluxes with its own geometry and finishes the stage.
 template <int P, typename Real, int MODE>
 __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArgs<Real> &a, unsigned e0,
                                                unsigned e_end, const unsigned *items, int nitems, double xihat,
@@ -795,173 +984,50 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
     const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
     const double g = a.ph.g;
 
-    // 1. state to registers and LDS, volume and source terms
-    Geo G;
-    double hbh[3];
+    // 1. state to registers and LDS
     Fields<P, Real> s;
-    Acc<P, Real> A;
     const unsigned off = e * (unsigned)sizeof(Real);
     if (live) {
-        load_geo(m.vtx, bEv, e * 4u, G);
-        hb_modes(G, hbh);
         load_state<P, Real>(bC, bU, KS, off, s);
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            S.C[0 * K + q][l] = s.xi[q];
-            S.C[1 * K + q][l] = s.U[q];
-            S.C[2 * K + q][l] = s.V[q];
-            S.C[3 * K + q][l] = s.u[q];
-            S.C[4 * K + q][l] = s.v[q];
+            S.U.C[0 * K + q][l] = s.xi[q];
+            S.U.C[1 * K + q][l] = s.U[q];
+            S.U.C[2 * K + q][l] = s.V[q];
+            S.U.C[3 * K + q][l] = s.u[q];
+            S.U.C[4 * K + q][l] = s.v[q];
         }
-        acc_init<P, Real>(A, s, MODE != MODE_RHS);
-        volume_term<P, Real>(s, hbh, G, g, dt, A);
-        source_term<P, Real>(s, G, a.ph, dt, A);
     }
     __syncthreads();
 
-    // 2. one flux per edge item
-    for (int it = (int)l; it < nitems; it += BLOCK) {
-        const unsigned w = items[it];
-        const int la = (int)(w & 255u), ka = (int)((w >> 8) & 3u), lb = (int)((w >> 10) & 255u);
-        const int kb = (int)((w >> 18) & 3u);
-        const unsigned kind = (w >> 20) & 3u;
-        const unsigned ea = e0 + (unsigned)la;
-        const int va = (ka + 1) % 3, vb = (ka + 2) % 3;
-        const double4 pa = m.vtx[(unsigned)bEv.ld(va, ea * 4u)];
-        const double4 pb = m.vtx[(unsigned)bEv.ld(vb, ea * 4u)];
-        const double dx = pb.x - pa.x, dy = pb.y - pa.y;
-        const double len2 = dx * dx + dy * dy;
-        const Real nx = Real(dy), ny = Real(-dx);          // |E| n of side a
-        const double hmid = 0.5 * (pa.z + pb.z);
-        const double hbt[2] = {hmid, (pb.z - pa.z) * INV_2SQRT3};
-        Real tm[5][NT], tp[5][NT];
-        traces_of<P, Real>(S, la, ka, tm);
-        const Real xbm = Real(SQRT2) * S.C[0][la];
-        const Real unbm = fabs(fma(Real(SQRT2) * S.C[3 * K][la], nx, Real(SQRT2) * S.C[4 * K][la] * ny));
-        Real unm[NT], qnm[NT], unp[NT], qnp[NT];
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            unm[c] = fma(tm[3][c], nx, tm[4][c] * ny);
-            qnm[c] = fma(tm[1][c], nx, tm[2][c] * ny);
-        }
-        Real xbp, unbp;
-        if (kind == EK_PAIR || kind == EK_EXT) {
-            Real x0, u0, v0;
-            if (kind == EK_PAIR) {
-                traces_of<P, Real>(S, lb, kb, tp);
-                x0 = S.C[0][lb];
-                u0 = S.C[3 * K][lb];
-                v0 = S.C[4 * K][lb];
-            } else {
-                const int nb = bNb.ld(ka, ea * 4u);
-                const int kk = (m.enbk[ea] >> (2 * ka)) & 3;
-                const unsigned un_ = (unsigned)nb * (unsigned)sizeof(Real);
-#pragma unroll
-                for (int f = 0; f < 5; ++f)
-#pragma unroll
-                    for (int c = 0; c < NT; ++c) tp[f][c] = Real(0);
-                x0 = Real(0); u0 = Real(0); v0 = Real(0);
-#pragma unroll
-                for (int n = 0; n < K; ++n) {
-                    const Real fv[5] = {bC.ld(0 * KS + n, un_), bC.ld(1 * KS + n, un_), bC.ld(2 * KS + n, un_),
-                                        bU.ld(0 * KS + n, un_), bU.ld(1 * KS + n, un_)};
-                    if (n == 0) { x0 = fv[0]; u0 = fv[3]; v0 = fv[4]; }
-#pragma unroll
-                    for (int c = 0; c < NT && c <= TDEG[n]; ++c) {
-                        const Real r = S.R[kk][n][c];
-#pragma unroll
-                        for (int f = 0; f < 5; ++f) tp[f][c] = fma(fv[f], r, tp[f][c]);
-                    }
-                }
-            }
-            // the other side runs along the edge in the opposite direction
-#pragma unroll
-            for (int c = 1; c < NT; c += 2)
-#pragma unroll
-                for (int f = 0; f < 5; ++f) tp[f][c] = -tp[f][c];
-#pragma unroll
-            for (int c = 0; c < NT; ++c) {
-                unp[c] = fma(tp[3][c], nx, tp[4][c] * ny);
-                qnp[c] = fma(tp[1][c], nx, tp[2][c] * ny);
-            }
-            xbp = Real(SQRT2) * x0;
-            unbp = fabs(fma(Real(SQRT2) * u0, nx, Real(SQRT2) * v0 * ny));
-        } else if (kind == EK_LAND) {
-            // mirror: xi+ = xi-, normal parts of q and u change sign
-            const Real m2 = Real(-2.0 / len2);
-#pragma unroll
-            for (int c = 0; c < NT; ++c) {
-                tp[0][c] = tm[0][c];
-                unp[c] = -unm[c];
-                qnp[c] = -qnm[c];
-                tp[1][c] = fma(m2 * qnm[c], nx, tm[1][c]);
-                tp[2][c] = fma(m2 * qnm[c], ny, tm[2][c]);
-            }
-            xbp = xbm;
-            unbp = unbm;
-        } else {
-            // open sea: xi+ = xi_hat(t), q and u copied
-#pragma unroll
-            for (int c = 0; c < NT; ++c) {
-                tp[0][c] = c == 0 ? Real(xihat) : Real(0);
-                tp[1][c] = tm[1][c];
-                tp[2][c] = tm[2][c];
-                unp[c] = unm[c];
-                qnp[c] = qnm[c];
-            }
-            xbp = Real(xihat);
-            unbp = unbm;
-        }
-        // penalty from constant parts at the edge midpoint (eq:lambda), times |E|
-        Real lam;
-        if constexpr (std::is_same<Real, double>::value)
-            lam = tmax(unbm, unbp) + sqrt(g * (tmax(xbm, xbp) + hmid) * len2);
-        else
-            lam = tmax(unbm, unbp) + Real(sqrt(g * (double(tmax(xbm, xbp)) + hmid) * len2));
-        const Real hg = Real(0.5 * g);
-        Real F[3][NT];
-        double Wf[NT];
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            const Real pb = hg * (prod1<NT, Real>(c, tm[0], tm[0]) + prod1<NT, Real>(c, tp[0], tp[0]));
-            const Real mU = prod1<NT, Real>(c, tm[1], unm) + prod1<NT, Real>(c, tp[1], unp);
-            const Real mV = prod1<NT, Real>(c, tm[2], unm) + prod1<NT, Real>(c, tp[2], unp);
-            Real fx = Real(0.5) * (qnm[c] + qnp[c] + lam * (tm[0][c] - tp[0][c]));
-            if (kind == EK_LAND) fx = 0;   // q.n = 0: no mass flux through land
-            F[0][c] = fx;
-            F[1][c] = Real(0.5) * (mU + pb * nx + lam * (tm[1][c] - tp[1][c]));
-            F[2][c] = Real(0.5) * (mV + pb * ny + lam * (tm[2][c] - tp[2][c]));
-            // bathymetry part of the pressure, (P- + P+)/2 = g (xi- + xi+) h_b / 2
-            double wv = 0.0;
-#pragma unroll
-            for (int aa = 0; aa < NT; ++aa) {
-                const double xs = double(tm[0][aa]) + double(tp[0][aa]);
-#pragma unroll
-                for (int bb = 0; bb < 2 && bb < NT; ++bb)
-                    if (TG[c][aa][bb] != 0.0) wv = fma(TG[c][aa][bb] * hbt[bb], xs, wv);
-            }
-            Wf[c] = 0.5 * g * wv;
-        }
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j) S.F[j * NT + c][ka][la] = F[j][c];
-            S.W[c][ka][la] = Wf[c];
-        }
-        if (kind == EK_PAIR) {
-            // the second side: the same flux with the opposite normal, reversed along the edge
-#pragma unroll
-            for (int c = 0; c < NT; ++c) {
-#pragma unroll
-                for (int j = 0; j < 3; ++j) S.F[j * NT + c][kb][lb] = (c & 1) ? F[j][c] : -F[j][c];
-                S.W[c][kb][lb] = (c & 1) ? -Wf[c] : Wf[c];
-            }
-        }
+    // 2. the fluxes of this lane's (at most two) edge items
+    const int n = nitems < 2 * BLOCK ? nitems : 2 * BLOCK;
+    const int it0 = (int)l, it1 = (int)l + BLOCK;
+    unsigned w0 = 0u, w1 = 0u;
+    ShItem<P, Real> r0, r1;
+    if (it0 < n) {
+        w0 = items[it0];
+        sh_flux<P, Real>(S, m, bC, bU, bEv, bNb, e0, w0, xihat, g, r0);
     }
+    if (it1 < n) {
+        w1 = items[it1];
+        sh_flux<P, Real>(S, m, bC, bU, bEv, bNb, e0, w1, xihat, g, r1);
+    }
+    __syncthreads();
+    if (it0 < n) sh_store<P, Real>(S, w0, r0);
+    if (it1 < n) sh_store<P, Real>(S, w1, r1);
     __syncthreads();
     if (!live) return;
 
-    // 3. lift the three edge fluxes, finish the stage
+    // 3. volume and source terms, the three edge fluxes lifted, the stage finished
+    Geo G;
+    double hbh[3];
+    load_geo(m.vtx, bEv, e * 4u, G);
+    hb_modes(G, hbh);
+    Acc<P, Real> A;
+    acc_init<P, Real>(A, s, MODE != MODE_RHS);
+    volume_term<P, Real>(s, hbh, G, g, dt, A);
+    source_term<P, Real>(s, G, a.ph, dt, A);
     const double dt_det = dt / G.det;
     const Real sc = Real(dt_det);
 #pragma unroll
@@ -972,10 +1038,10 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
         double FWx[NT], FWy[NT];
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
-            FX[c] = sc * S.F[0 * NT + c][k][l];
-            FU[c] = sc * S.F[1 * NT + c][k][l];
-            FV[c] = sc * S.F[2 * NT + c][k][l];
-            const double FW = S.W[c][k][l] * dt_det;
+            FX[c] = sc * S.U.E.F[0 * NT + c][k][l];
+            FU[c] = sc * S.U.E.F[1 * NT + c][k][l];
+            FV[c] = sc * S.U.E.F[2 * NT + c][k][l];
+            const double FW = S.U.E.W[c][k][l] * dt_det;
             FWx[c] = FW * dy;
             FWy[c] = FW * -dx;
         }
@@ -1028,7 +1094,7 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
 }
 
 template <int P, typename Real, int MODE>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_target<P, Real>(), 8)))
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sh_waves<P, Real>(), 8)))
 k_stage_sh(StageArgs<Real> a, const unsigned *items, const int *item_off)
 {
     __shared__ ShLds<P, Real> S;
@@ -1181,7 +1247,7 @@ k_batch_stage(BatchArgs b)
 // starts on a multiple of 256 within its instance, so the instance's edge
 // items of that block (local indices) serve it unchanged.
 template <int P, typename Real, int MODE>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_target<P, Real>(), 8)))
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sh_waves<P, Real>(), 8)))
 k_batch_stage_sh(BatchArgs b)
 {
     __shared__ ShLds<P, Real> S;
