@@ -1350,7 +1350,7 @@ struct swe_batch {
     int tile_cap[4] = {0, 0, 0, 0};
     int *d_ntiles = nullptr;
     int tile[4] = {256, 256, 256, 256};
-    bool shared[4] = {false, false, true, true};    // shared-flux kernel (256-element tiles) chosen for the order
+    bool shared[4] = {false, true, true, true};     // shared-flux kernel (256-element tiles) chosen for the order
     int no_items[4] = {0, 0, 0, 0};    // resident members of the order without edge items
     int grid[4] = {0, 0, 0, 0};
     int ntiles[4] = {0, 0, 0, 0};

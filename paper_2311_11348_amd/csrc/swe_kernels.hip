@@ -739,9 +739,9 @@ __device__ __forceinline__ void finish_stage(const StageArgs<Real> &a, unsigned 
 // edge (18-19) and the kind (20-21).
 constexpr unsigned EK_PAIR = 0, EK_EXT = 1, EK_LAND = 2, EK_OPEN = 3;
 
-// Waves per SIMD the shared-flux kernels are built for: what their LDS
-// allows (FP32 p = 2: 46 KB per 256-element block, three blocks per CU; FP32
-// p = 3 and FP64 p = 2: 62 and 74 KB, two blocks).
+// Waves per SIMD the shared-flux kernels are built for at least: what their
+// LDS allows (FP32 p = 2: 46 KB per 256-element block, three blocks per CU;
+// FP32 p = 3 and FP64 p = 2: 62 and 74 KB, two blocks; p = 1 needs less).
 template <int P, typename Real>
 constexpr int sh_waves()
 {
@@ -1832,10 +1832,10 @@ hipError_t stage_sh_p(int mode, const void *args, const unsigned *items, const i
     return emit(k, fn, dim3((a.m.ne + BLOCK - 1) / BLOCK), dim3(BLOCK), kargs);
 }
 
-// Orders 0 and 1 have too little work per edge for the sharing to pay for
-// the LDS staging and the two barriers (the gather kernel is faster there);
-// FP64 order 3 would need more LDS than a CU has for one block.
-bool stage_sh_supported(int p, bool fp32) { return p == 2 || (p == 3 && fp32); }
+// Order 0 has too little work per edge for the sharing to pay for the LDS
+// staging and the barriers; FP64 order 3 would need more LDS than a CU has
+// for one block.
+bool stage_sh_supported(int p, bool fp32) { return (p >= 1 && p <= 2) || (p == 3 && fp32); }
 
 hipError_t launch_stage_sh(int p, bool fp32, int mode, const void *args, const unsigned *items, const int *item_off,
                            Sink &k)
@@ -2020,8 +2020,10 @@ hipError_t launch_batch_stage_sh(int p, bool fp32, int mode, const BatchArgs &b,
 {
     if (grid <= 0) return hipSuccess;
     if (mode != MODE_STAGE1 && mode != MODE_STAGE2) return hipErrorInvalidValue;
+    if (fp32 && p == 1) return batch_sh_p<1, float>(mode, b, grid, k);
     if (fp32 && p == 2) return batch_sh_p<2, float>(mode, b, grid, k);
     if (fp32 && p == 3) return batch_sh_p<3, float>(mode, b, grid, k);
+    if (!fp32 && p == 1) return batch_sh_p<1, double>(mode, b, grid, k);
     if (!fp32 && p == 2) return batch_sh_p<2, double>(mode, b, grid, k);
     return hipErrorInvalidValue;
 }
