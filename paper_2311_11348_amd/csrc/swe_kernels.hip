@@ -724,19 +724,12 @@ __device__ __forceinline__ void finish_stage(const StageArgs<Real> &a, unsigned 
 
 // ------------------------------------------------------------ shared edge fluxes
 // Stage kernel in which each edge flux inside a block of BLOCK consecutive
-// elements is computed once and handed to both sides through LDS:
-//   1. each lane (one element) keeps its state in registers, copies it to LDS
-//      and accumulates its volume and source terms;
-//   2. the block's edge items (host-built: a pair of elements of the block,
-//      or an element and a neighbour outside the block, a land or an open
-//      edge) are spread over the lanes; each computes the Lax-Friedrichs flux
-//      in the first side's orientation, unscaled by dt / |det B|, and stores
-//      it for the first side and, negated and reversed along the edge, for
-//      the second;
-//   3. each lane lifts its three edge fluxes with its own geometry and
-//      finishes the stage.
-// An item packs a (bits 0-7), its local edge (8-9), b (10-17), b's local
-// edge (18-19) and the kind (20-21).
+// elements is computed once and handed to both sides through LDS (the passes
+// are described at stage_sh_block).  The block's edge items are host-built:
+// a pair of elements of the block (taken once, from the lower index), an
+// element and a neighbour outside the block, a land or an open edge.  An
+// item packs a (bits 0-7), its local edge (8-9), b (10-17), b's local edge
+// (18-19) and the kind (20-21).
 constexpr unsigned EK_PAIR = 0, EK_EXT = 1, EK_LAND = 2, EK_OPEN = 3;
 
 // Waves per SIMD the shared-flux kernels are built for at least: what their
