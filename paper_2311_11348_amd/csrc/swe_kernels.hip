@@ -1340,6 +1340,9 @@ template <int B, typename Real>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
 k_corr_base(StageArgs<Real> a, double dt)
 {
+    // the listed elements' kernels run beside the base kernel over all
+    // elements and end the stage: their waves issue first on a shared SIMD
+    __builtin_amdgcn_s_setprio(2);
     constexpr int KB = Ord<B>::K, NTB = Ord<B>::NT;
     __shared__ Real sRb[3][KB][NTB];
     load_trace_table<KB, NTB, Real>(sRb);
@@ -1385,6 +1388,9 @@ template <int P, int B, int PN, typename Real>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<(P > PN ? P : PN), Real>(), 8)))
 k_corr(StageArgs<Real> a, double dt)
 {
+    // the listed elements' kernels run beside the base kernel over all
+    // elements and end the stage: their waves issue first on a shared SIMD
+    __builtin_amdgcn_s_setprio(2);
     constexpr int K = Ord<P>::K, KB = Ord<B>::K;
     constexpr int KN = Ord<PN>::K, NX = (P > PN ? P : PN) + 1;
     __shared__ Real sR[3][KN][NX];
@@ -1462,6 +1468,9 @@ template <int P, int PN, typename Real, int MODE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<(P > PN ? P : PN), Real>(), 8)))
 k_full(StageArgs<Real> a)
 {
+    // the listed elements' kernels run beside the base kernel over all
+    // elements and end the stage: their waves issue first on a shared SIMD
+    __builtin_amdgcn_s_setprio(2);
     constexpr int NX = (P > PN ? P : PN) + 1, KN = Ord<PN>::K;
     __shared__ Real sR[3][KN][NX];
     load_trace_table<KN, NX, Real>(sR);
