@@ -977,10 +977,16 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
     const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
     const double g = a.ph.g;
 
-    // 1. state to registers and LDS
+    // 1. state to registers and LDS; in FP32 also the geometry, whose
+    //    latency then hides behind the edge pass (in FP64 the registers it
+    //    would hold across that pass are not there)
+    constexpr bool early_geo = !std::is_same<Real, double>::value;
     Fields<P, Real> s;
+    Geo G;
+    double hbh[3];
     const unsigned off = e * (unsigned)sizeof(Real);
     if (live) {
+        if constexpr (early_geo) load_geo(m.vtx, bEv, e * 4u, G);
         load_state<P, Real>(bC, bU, KS, off, s);
 #pragma unroll
         for (int q = 0; q < K; ++q) {
@@ -1013,9 +1019,7 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
     if (!live) return;
 
     // 3. volume and source terms, the three edge fluxes lifted, the stage finished
-    Geo G;
-    double hbh[3];
-    load_geo(m.vtx, bEv, e * 4u, G);
+    if constexpr (!early_geo) load_geo(m.vtx, bEv, e * 4u, G);
     hb_modes(G, hbh);
     Acc<P, Real> A;
     acc_init<P, Real>(A, s, MODE != MODE_RHS);
