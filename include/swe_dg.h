@@ -229,15 +229,14 @@ swe_status swe_batch_retire(swe_batch *b, int32_t slot);
 
 /* Time the candidates on the resident set and keep the fastest per order:
  * the element-gather kernel with tiles of 64, 128 or 256 elements and, for
- * orders 1 and 2 (and 3 in FP32), the kernel that computes each edge flux
- * inside a 256-element tile once and shares it through LDS; reps timed
- * launches each. */
+ * orders 1 to 3, the kernel that computes each edge flux inside a
+ * 256-element tile once and shares it through LDS; reps timed launches
+ * each. */
 swe_status swe_batch_tune(swe_batch *b, int reps);
 
 /* Choose the kernel of order p by hand instead of swe_batch_tune: the gather
  * kernel with tile = 64, 128 or 256 elements (shared = 0), or the shared-flux
- * kernel (shared = 1, tile = 256; SWE_EUNSUPPORTED for order 0 and FP64
- * order 3).  Takes effect from the next tick.  If a resident member
+ * kernel (shared = 1, tile = 256; SWE_EUNSUPPORTED for order 0).  Takes effect from the next tick.  If a resident member
  * of the order has no edge items, the order keeps the gather kernel. */
 swe_status swe_batch_set_tile(swe_batch *b, int p, int tile, int shared);
 

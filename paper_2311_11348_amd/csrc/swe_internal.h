@@ -138,7 +138,7 @@ hipError_t emit(Sink &k, const void *fn, dim3 grid, dim3 block, void **args);
 hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, hipStream_t s);
 hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, Sink &k);
 // fused stage with each in-block edge flux computed once (edge items built by
-// the host, see swe_kernels.hip); used for p = 1 and 2, and p = 3 in FP32
+// the host, see swe_kernels.hip); used for p = 1 to 3
 bool stage_sh_supported(int p, bool fp32);
 hipError_t launch_stage_sh(int p, bool fp32, int mode, const void *args, const unsigned *items, const int *item_off,
                            Sink &k);

@@ -734,11 +734,14 @@ constexpr unsigned EK_PAIR = 0, EK_EXT = 1, EK_LAND = 2, EK_OPEN = 3;
 
 // Waves per SIMD the shared-flux kernels are built for at least: what their
 // LDS allows (FP32 p = 2: 46 KB per 256-element block, three blocks per CU;
-// FP32 p = 3 and FP64 p = 2: 62 and 74 KB, two blocks; p = 1 needs less).
+// FP32 p = 3 and FP64 p = 2: 62 and 74 KB, two blocks; FP64 p = 3: 103 KB,
+// one block, whose registers then spill into accumulation registers rather
+// than scratch; p = 1 needs less).
 template <int P, typename Real>
 constexpr int sh_waves()
 {
-    return (P <= 2 && !std::is_same<Real, double>::value) ? 3 : 2;
+    constexpr bool dbl = std::is_same<Real, double>::value;
+    return (P <= 2 && !dbl) ? 3 : (P == 3 && dbl) ? 1 : 2;
 }
 
 // Per-block LDS.  The state copy C is read by the edge pass only; the
@@ -1839,9 +1842,12 @@ hipError_t stage_sh_p(int mode, const void *args, const unsigned *items, const i
 }
 
 // Order 0 has too little work per edge for the sharing to pay for the LDS
-// staging and the barriers; FP64 order 3 would need more LDS than a CU has
-// for one block.
-bool stage_sh_supported(int p, bool fp32) { return (p >= 1 && p <= 2) || (p == 3 && fp32); }
+// staging and the barriers.
+bool stage_sh_supported(int p, bool fp32)
+{
+    (void)fp32;
+    return p >= 1 && p <= 3;
+}
 
 hipError_t launch_stage_sh(int p, bool fp32, int mode, const void *args, const unsigned *items, const int *item_off,
                            Sink &k)
@@ -1858,6 +1864,7 @@ hipError_t launch_stage_sh(int p, bool fp32, int mode, const void *args, const u
         case 0: return stage_sh_p<0, double>(mode, args, items, item_off, k);
         case 1: return stage_sh_p<1, double>(mode, args, items, item_off, k);
         case 2: return stage_sh_p<2, double>(mode, args, items, item_off, k);
+        case 3: return stage_sh_p<3, double>(mode, args, items, item_off, k);
         }
     }
     return hipErrorInvalidValue;
@@ -2031,6 +2038,7 @@ hipError_t launch_batch_stage_sh(int p, bool fp32, int mode, const BatchArgs &b,
     if (fp32 && p == 3) return batch_sh_p<3, float>(mode, b, grid, k);
     if (!fp32 && p == 1) return batch_sh_p<1, double>(mode, b, grid, k);
     if (!fp32 && p == 2) return batch_sh_p<2, double>(mode, b, grid, k);
+    if (!fp32 && p == 3) return batch_sh_p<3, double>(mode, b, grid, k);
     return hipErrorInvalidValue;
 }
 

@@ -95,7 +95,7 @@ def test_batch_kernels_equal_alone(precision):
             slots = [b.admit(c, steps, p.dt()) for c, p in zip(ctxs, probs)]
             used = {}
             for p in range(4):
-                sh = shared and (p in (1, 2) or (p == 3 and precision == swe.SWE_FP32_WB))
+                sh = shared and p >= 1
                 b.set_tile(p, tile, sh)
                 used[p] = b.tile_config(p)
             b.tick(steps)
