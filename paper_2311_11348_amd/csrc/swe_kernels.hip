@@ -132,6 +132,26 @@ struct Geo {
     double X[3], Y[3], h[3];     // vertices and depths
 };
 
+// Geometry from the element's vertex ids (already loaded).
+__device__ __forceinline__ void geo_from_ids(const double4 *vtx, const int (&id3)[3], Geo &G)
+{
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const double4 p = vtx[(unsigned)id3[v]];
+        G.X[v] = p.x;
+        G.Y[v] = p.y;
+        G.h[v] = p.z;
+    }
+    const double a00 = G.X[1] - G.X[0], a01 = G.X[2] - G.X[0];
+    const double a10 = G.Y[1] - G.Y[0], a11 = G.Y[2] - G.Y[0];
+    G.det = a00 * a11 - a01 * a10;
+    const double id = 1.0 / G.det;
+    G.b00 = a11 * id;
+    G.b01 = -a01 * id;
+    G.b10 = -a10 * id;
+    G.b11 = a00 * id;
+}
+
 __device__ __forceinline__ void load_geo(const double4 *vtx, const Buf<int> &ev, unsigned offi, Geo &G)
 {
 #pragma unroll
@@ -982,14 +1002,21 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
 
     // 1. state to registers and LDS; in FP32 also the geometry, whose
     //    latency then hides behind the edge pass (in FP64 the registers it
-    //    would hold across that pass are not there)
+    //    would hold across that pass are not there: only the vertex ids are
+    //    loaded here)
     constexpr bool early_geo = !std::is_same<Real, double>::value;
     Fields<P, Real> s;
     Geo G;
     double hbh[3];
+    int id3[3] = {0, 0, 0};
     const unsigned off = e * (unsigned)sizeof(Real);
     if (live) {
-        if constexpr (early_geo) load_geo(m.vtx, bEv, e * 4u, G);
+        if constexpr (early_geo) {
+            load_geo(m.vtx, bEv, e * 4u, G);
+        } else {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) id3[v] = bEv.ld(v, e * 4u);
+        }
         load_state<P, Real>(bC, bU, KS, off, s);
 #pragma unroll
         for (int q = 0; q < K; ++q) {
@@ -1022,7 +1049,7 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
     if (!live) return;
 
     // 3. volume and source terms, the three edge fluxes lifted, the stage finished
-    if constexpr (!early_geo) load_geo(m.vtx, bEv, e * 4u, G);
+    if constexpr (!early_geo) geo_from_ids(m.vtx, id3, G);
     hb_modes(G, hbh);
     Acc<P, Real> A;
     acc_init<P, Real>(A, s, MODE != MODE_RHS);
