@@ -138,3 +138,76 @@ def test_states_and_steps_refused_and_recovered():
         got, _ = ctx.state()
     ref = orc.step(c0, 2, 0.5)
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def isolated_triangles(count, p, seed=11):
+    """count disjoint triangles (every edge land): 3 edge items per element,
+    more than the shared-flux kernel takes per block."""
+    rng = np.random.default_rng(seed)
+    vxy, tri = [], []
+    for i in range(count):
+        x0, y0 = (i % 20) * 1.2e4, (i // 20) * 1.2e4
+        a = rng.uniform(5e3, 9e3)
+        vxy += [[x0, y0], [x0 + a, y0 + 1e3], [x0 + 2e3, y0 + a]]
+        tri.append([3 * i, 3 * i + 1, 3 * i + 2])
+    vxy, tri = np.array(vxy), np.array(tri, np.int32)
+    mesh = I.Mesh(vxy=vxy, tri=tri, tag=np.zeros((count, 3), np.int8))
+    hb = rng.uniform(20.0, 80.0, len(vxy))
+
+    def ic(x, y):
+        return 0.2 * np.sin(x / 3e3) * np.cos(y / 4e3), 1.0 + 0.0 * x, -0.5 + 0.0 * y
+
+    return I.Problem(name="isolated", mesh=mesh, hb_vertex=hb, ic=ic, p=np.full(count, p, np.int8), p_base=p,
+                     p_max=p, f_coriolis=1e-4)
+
+
+@pytest.mark.parametrize("precision", [swe.SWE_FP64, swe.SWE_FP32_WB])
+def test_too_many_items_fall_back_to_gather(precision):
+    """A mesh whose blocks hold more edge items than the shared-flux kernel
+    takes runs on the element-gather kernel: alone against the oracle, and in
+    a batch (its order then falls back for every member) bitwise equal to
+    alone, beside an ordinary member of the same order."""
+    p = 2
+    prob = isolated_triangles(300, p)
+    orc = Oracle.from_problem(prob)
+    c0 = orc.project(prob.ic)
+    dt, steps = 0.5, 6
+    ref = orc.step(c0, steps, dt)
+    other = I.config_instance(301, n_lo=2000, n_hi=4000)
+    other.p_max = other.p_base = p
+    other.p = np.full(other.mesh.ne, p, np.int8)
+    with swe.context_for(prob, precision=precision) as ctx:
+        ctx.set_state(c0)
+        ctx.step(steps, dt)
+        ctx.sync()
+        alone_iso, _ = ctx.state()
+    with swe.context_for(other, precision=precision) as ctx:
+        ctx.set_state_fn(other.ic)
+        ctx.step(steps, other.dt())
+        ctx.sync()
+        alone_other, _ = ctx.state()
+    tol = 1e-12 if precision == swe.SWE_FP64 else 1e-5
+    err = np.linalg.norm(alone_iso - ref) / np.linalg.norm(ref)
+    say(f"isolated triangles precision={precision}: rel L2 vs oracle {err:.2e}")
+    assert err < tol
+    c_iso = swe.context_for(prob, precision=precision)
+    c_iso.set_state(c0)
+    c_oth = swe.context_for(other, precision=precision)
+    c_oth.set_state_fn(other.ic)
+    with swe.Batch(precision=precision, budget_bytes=4 << 30, max_instances=4) as b:
+        s1 = b.admit(c_oth, steps, other.dt())
+        s2 = b.admit(c_iso, steps, dt)
+        b.set_tile(p, 256, True)          # asked for, but a member has no edge items
+        tile, _, shared = b.tile_config(p)
+        say(f"  batch order {p}: tile {tile}, shared {shared}")
+        assert not shared
+        b.tick(steps)
+        b.sync()
+        b.retire(s1)
+        b.retire(s2)
+    got_iso, _ = c_iso.state()
+    got_oth, _ = c_oth.state()
+    c_iso.close()
+    c_oth.close()
+    assert np.array_equal(got_iso, alone_iso)
+    assert np.array_equal(got_oth, alone_other)
