@@ -286,15 +286,6 @@ int list_grid(const swe_ctx *c, int p)
     return (c->list_cnt[p] + BLOCK - 1) / BLOCK;
 }
 
-// Grid of the correction's base pass over the lists of every order.
-int base_pass_grid(const swe_ctx *c)
-{
-    if (c->cfg.adapt) return (int)((c->ne + BLOCK - 1) / BLOCK);   // the lists hold each element at most once
-    int sum = 0;
-    for (int p = 0; p < 4; ++p) sum += c->list_cnt[p];
-    return (sum + BLOCK - 1) / BLOCK;
-}
-
 // Order adaptation at the start of a step, from the state in buffer 0.
 template <typename Real>
 hipError_t enqueue_adapt(Lanes &L, double tn)
@@ -339,12 +330,8 @@ hipError_t enqueue_separated(Lanes &L, int mode, int in, int out, double tstage,
     if (e != hipSuccess) return e;
     e = launch_stage(b, c->fp32, mode, true, &a, L.a);
     if (e != hipSuccess) return e;
-    a.list = c->d_list;
-    a.count = c->d_cnt;
-    e = launch_corr_base(b, c->fp32, &a, dt, base_pass_grid(c), L.b);
-    if (e != hipSuccess) return e;
     // streams: the orders one after the other; graph: the orders' corrections
-    // (after the base-part pass) and then their epilogues on parallel branches
+    // and then their epilogues on parallel branches
     Sink ends[4];
     int n = 0;
     for (int p = b; p <= pm; ++p) {
@@ -635,7 +622,6 @@ hipError_t enqueue_rhs_split(swe_ctx *c, double t)
     hipError_t e = launch_stage(b, c->fp32, MODE_RHS, false, &a, c->s_base);
     a.list = c->d_list;
     a.count = c->d_cnt;
-    if (e == hipSuccess) e = launch_corr_base(b, c->fp32, &a, 1.0, base_pass_grid(c), c->s_base);
     for (int p = b; p <= pm && e == hipSuccess; ++p) {
         if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
         a.list = c->d_list + c->list_off[p];

@@ -142,10 +142,6 @@ hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, 
 bool stage_sh_supported(int p, bool fp32);
 hipError_t launch_stage_sh(int p, bool fp32, int mode, const void *args, const unsigned *items, const int *item_off,
                            Sink &k);
-// base-part pass of the correction over the listed elements of every order
-// (args.list = the start of the per-order lists, args.count = the 4 counts)
-hipError_t launch_corr_base(int b, bool fp32, const void *args, double dt, int grid, Sink &k);
-hipError_t launch_corr_base(int b, bool fp32, const void *args, double dt, int grid, hipStream_t s);
 hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, hipStream_t s);
 hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, Sink &k);
 hipError_t launch_epi(int p, int b, bool fp32, int mode, const void *args, int grid, hipStream_t s);

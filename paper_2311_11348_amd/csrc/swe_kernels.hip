@@ -1362,62 +1362,12 @@ __global__ void __launch_bounds__(BLOCK) k_batch_clock(InstDesc *inst, const int
     I.steps_left -= 1;
 }
 
-// Correction of the order-separated scheme, in two passes over the listed
-// elements (one element per lane):
-//  1. k_corr_base<B>: minus dt times the base part (rows below K(B), the
-//     element's and its neighbours' first K(B) modes), for the listed
-//     elements of every order;
-//  2. k_corr<P,B,PN>: for the listed elements of order P (neighbours of order
-//     <= PN), adds dt times the full right-hand side on top.
-// Each pass holds one right-hand side evaluation in registers.
-template <int B, typename Real>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
-k_corr_base(StageArgs<Real> a, double dt)
-{
-    // the listed elements' kernels run beside the base kernel over all
-    // elements and end the stage: their waves issue first on a shared SIMD
-    __builtin_amdgcn_s_setprio(2);
-    constexpr int KB = Ord<B>::K, NTB = Ord<B>::NT;
-    __shared__ Real sRb[3][KB][NTB];
-    load_trace_table<KB, NTB, Real>(sRb);
-    __syncthreads();
-    const MeshView &m = a.m;
-    const int KS = m.KS, stride = m.stride;
-    const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
-    const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
-    const Buf<Real> bL(a.Lc, 3 * KS, stride);
-    double xihat = a.xihat;
-    if (a.inst) {
-        // the clock of a replayed step lives on the device
-        xihat = a.inst->xh[a.stage];
-        dt = a.inst->dt;
-    }
-    // thread i takes entry i of the concatenated lists of orders B..3 (the
-    // grid covers their total length): one element per thread, no loop around
-    // the evaluation
-    int j = blockIdx.x * BLOCK + threadIdx.x, p = B;
-    while (p < 4 && j >= a.count[p]) {
-        j -= a.count[p];
-        ++p;
-    }
-    if (p >= 4) return;
-    const unsigned e = (unsigned)a.list[(size_t)p * (size_t)m.ne + (size_t)j];
-    const unsigned off = e * (unsigned)sizeof(Real);
-    Geo G;
-    load_geo(m.vtx, bEv, e * 4u, G);
-    double hbh[3];
-    hb_modes(G, hbh);
-    Fields<B, Real> sb;
-    load_state<B, Real>(bC, bU, KS, off, sb);
-    Acc<B, Real> Ab;
-    acc_init<B, Real>(Ab, sb, false);
-    element_rhs<B, B, Real>(a, e, bC, bU, bNb, sb, G, hbh, dt, sRb, Ab, xihat);
-#pragma unroll
-    for (int jj = 0; jj < 3; ++jj)
-#pragma unroll
-        for (int q = 0; q < KB; ++q) bL.st(jj * KS + q, off, -Ab.L[jj][q]);
-}
-
+// Correction of the order-separated scheme for the listed elements of order
+// P (neighbours of order <= PN), one element per lane and no loop around an
+// evaluation: dt times the full right-hand side, minus dt times the base part
+// (rows below K(B), the element's and its neighbours' first K(B) modes) in
+// the rows below K(B).  The base part is evaluated first and kept, negated,
+// in registers; then the full one.
 template <int P, int B, int PN, typename Real>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<(P > PN ? P : PN), Real>(), 8)))
 k_corr(StageArgs<Real> a, double dt)
@@ -1425,10 +1375,12 @@ k_corr(StageArgs<Real> a, double dt)
     // the listed elements' kernels run beside the base kernel over all
     // elements and end the stage: their waves issue first on a shared SIMD
     __builtin_amdgcn_s_setprio(2);
-    constexpr int K = Ord<P>::K, KB = Ord<B>::K;
+    constexpr int K = Ord<P>::K, KB = Ord<B>::K, NTB = Ord<B>::NT;
     constexpr int KN = Ord<PN>::K, NX = (P > PN ? P : PN) + 1;
     __shared__ Real sR[3][KN][NX];
+    __shared__ Real sRb[3][KB][NTB];
     load_trace_table<KN, NX, Real>(sR);
+    load_trace_table<KB, NTB, Real>(sRb);
     __syncthreads();
     const MeshView &m = a.m;
     const int KS = m.KS, stride = m.stride;
@@ -1450,6 +1402,18 @@ k_corr(StageArgs<Real> a, double dt)
     load_geo(m.vtx, bEv, e * 4u, G);
     double hbh[3];
     hb_modes(G, hbh);
+    Real minus_base[3][KB];
+    {
+        Fields<B, Real> sb;
+        load_state<B, Real>(bC, bU, KS, off, sb);
+        Acc<B, Real> Ab;
+        acc_init<B, Real>(Ab, sb, false);
+        element_rhs<B, B, Real>(a, e, bC, bU, bNb, sb, G, hbh, dt, sRb, Ab, xihat);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int q = 0; q < KB; ++q) minus_base[j][q] = -Ab.L[j][q];
+    }
     Fields<P, Real> s;
     load_state<P, Real>(bC, bU, KS, off, s);
     Acc<P, Real> A;
@@ -1460,7 +1424,7 @@ k_corr(StageArgs<Real> a, double dt)
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             Real v = A.L[j][q];
-            if (q < KB) v += bL.ld(j * KS + q, off);   // minus the base part (pass 1)
+            if (q < KB) v += minus_base[j][q];
             bL.st(j * KS + q, off, v);
         }
 }
@@ -1902,33 +1866,6 @@ hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, 
     Sink k;
     k.s = s;
     return launch_stage(p, fp32, mode, sep, args, k);
-}
-
-template <typename Real>
-hipError_t corr_base_r(int b, const void *args, double dt, int grid, Sink &s)
-{
-    StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
-    void *kargs[] = {&a, &dt};
-    const dim3 g(grid), bl(BLOCK);
-    switch (b) {
-    case 0: return emit(s, reinterpret_cast<const void *>(&k_corr_base<0, Real>), g, bl, kargs);
-    case 1: return emit(s, reinterpret_cast<const void *>(&k_corr_base<1, Real>), g, bl, kargs);
-    case 2: return emit(s, reinterpret_cast<const void *>(&k_corr_base<2, Real>), g, bl, kargs);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_corr_base(int b, bool fp32, const void *args, double dt, int grid, Sink &k)
-{
-    if (grid <= 0) return hipSuccess;
-    return fp32 ? corr_base_r<float>(b, args, dt, grid, k) : corr_base_r<double>(b, args, dt, grid, k);
-}
-
-hipError_t launch_corr_base(int b, bool fp32, const void *args, double dt, int grid, hipStream_t s)
-{
-    Sink k;
-    k.s = s;
-    return launch_corr_base(b, fp32, args, dt, grid, k);
 }
 
 hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, Sink &k)
