@@ -277,14 +277,16 @@ hipError_t enqueue_stage(swe_ctx *c, int mode, int in, int out, double tstage, d
 
 bool separated(const swe_ctx *c) { return c->cfg.separate && c->cfg.p_base < c->cfg.p_max; }
 
-// Grid of a correction/epilogue launch (one listed element per thread): exact
-// for static lists; with adaptivity the lengths live on the device and the
-// grid covers every element.
-int list_grid(const swe_ctx *c, int p)
+// Blocks per order of a one-launch list kernel (every order's list fits):
+// with adaptivity the lengths live on the device and each may reach ne.
+int list_blocks(const swe_ctx *c)
 {
     if (c->cfg.adapt) return (int)((c->ne + BLOCK - 1) / BLOCK);
-    return (c->list_cnt[p] + BLOCK - 1) / BLOCK;
+    int most = 0;
+    for (int p = c->cfg.p_base; p <= c->cfg.p_max; ++p) most = std::max(most, c->list_cnt[p]);
+    return (most + BLOCK - 1) / BLOCK;
 }
+
 
 // Order adaptation at the start of a step, from the state in buffer 0.
 template <typename Real>
@@ -330,52 +332,16 @@ hipError_t enqueue_separated(Lanes &L, int mode, int in, int out, double tstage,
     if (e != hipSuccess) return e;
     e = launch_stage(b, c->fp32, mode, true, &a, L.a);
     if (e != hipSuccess) return e;
-    // streams: the orders one after the other; graph: the orders' corrections
-    // and then their epilogues on parallel branches
-    Sink ends[4];
-    int n = 0;
-    for (int p = b; p <= pm; ++p) {
-        if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
-        a.list = c->d_list + c->list_off[p];
-        a.count = c->d_cnt + p;
-        if (L.graph) {
-            ends[n] = L.b;
-            e = launch_corr(p, b, pm, c->fp32, &a, dt, list_grid(c, p), ends[n]);
-            ++n;
-        } else {
-            e = launch_corr(p, b, pm, c->fp32, &a, dt, list_grid(c, p), L.b);
-        }
-        if (e != hipSuccess) return e;
-    }
-    if (L.graph) {
-        if (n == 0 && !L.a.join(L.b)) return hipErrorInvalidValue;
-        for (int i = 0; i < n; ++i)
-            if (!L.a.join(ends[i])) return hipErrorInvalidValue;
-    } else {
-        e = L.join();
-        if (e != hipSuccess) return e;
-    }
-    const Sink origin = L.a;
-    n = 0;
-    for (int p = b; p <= pm; ++p) {
-        if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
-        a.list = c->d_list + c->list_off[p];
-        a.count = c->d_cnt + p;
-        if (L.graph) {
-            ends[n] = origin;
-            e = launch_epi(p, b, c->fp32, mode, &a, list_grid(c, p), ends[n]);
-            ++n;
-        } else {
-            e = launch_epi(p, b, c->fp32, mode, &a, list_grid(c, p), L.a);
-        }
-        if (e != hipSuccess) return e;
-    }
-    if (L.graph && n > 0) {
-        L.a.ndep = 0;
-        for (int i = 0; i < n; ++i)
-            if (!L.a.join(ends[i])) return hipErrorInvalidValue;
-    }
-    return hipSuccess;
+    // the corrections of every order in one launch on branch B, then (after
+    // the join) the epilogues of every order in one launch
+    a.list = c->d_list;
+    a.count = c->d_cnt;
+    const int nblk = list_blocks(c), lcap = (int)c->ne;
+    e = launch_corr_all(b, pm, c->fp32, &a, dt, nblk, lcap, L.b);
+    if (e != hipSuccess) return e;
+    e = L.join();
+    if (e != hipSuccess) return e;
+    return launch_epi_all(b, pm, c->fp32, mode, &a, nblk, lcap, L.a);
 }
 
 // Order-partitioned stage: the base kernel does every element of order
@@ -399,30 +365,15 @@ hipError_t enqueue_partitioned(Lanes &L, int mode, int in, int out, double tstag
     a.skip_listed = 1;
     hipError_t e = L.fork();
     if (e != hipSuccess) return e;
-    const Sink origin = L.b;   // graph: what the stage starts after
     e = launch_stage(b, c->fp32, mode, true, &a, L.a);
     if (e != hipSuccess) return e;
+    // the listed elements of every order in one launch on branch B
     a.skip_listed = 0;
-    Sink ends[4];
-    int nends = 0;
-    for (int p = b; p <= pm; ++p) {
-        if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
-        a.list = c->d_list + c->list_off[p];
-        a.count = c->d_cnt + p;
-        if (L.graph) {
-            // each order on a branch of its own
-            ends[nends] = origin;
-            e = launch_full(p, pm, c->fp32, mode, &a, list_grid(c, p), ends[nends]);
-            ++nends;
-        } else {
-            e = launch_full(p, pm, c->fp32, mode, &a, list_grid(c, p), L.b);
-        }
-        if (e != hipSuccess) return e;
-    }
-    if (!L.graph) return L.join();
-    for (int i = 0; i < nends; ++i)
-        if (!L.a.join(ends[i])) return hipErrorInvalidValue;
-    return hipSuccess;
+    a.list = c->d_list;
+    a.count = c->d_cnt;
+    e = launch_full_all(b, pm, c->fp32, mode, &a, list_blocks(c), (int)c->ne, L.b);
+    if (e != hipSuccess) return e;
+    return L.join();
 }
 
 // One SSP-RK2 step (order update first when adaptive).
@@ -622,11 +573,10 @@ hipError_t enqueue_rhs_split(swe_ctx *c, double t)
     hipError_t e = launch_stage(b, c->fp32, MODE_RHS, false, &a, c->s_base);
     a.list = c->d_list;
     a.count = c->d_cnt;
-    for (int p = b; p <= pm && e == hipSuccess; ++p) {
-        if (!c->cfg.adapt && c->list_cnt[p] == 0) continue;
-        a.list = c->d_list + c->list_off[p];
-        a.count = c->d_cnt + p;
-        e = launch_corr(p, b, pm, c->fp32, &a, 1.0, list_grid(c, p), c->s_base);
+    if (e == hipSuccess) {
+        Sink k;
+        k.s = c->s_base;
+        e = launch_corr_all(b, pm, c->fp32, &a, 1.0, list_blocks(c), (int)c->ne, k);
     }
     return e;
 }

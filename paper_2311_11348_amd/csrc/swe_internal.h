@@ -142,12 +142,13 @@ hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, 
 bool stage_sh_supported(int p, bool fp32);
 hipError_t launch_stage_sh(int p, bool fp32, int mode, const void *args, const unsigned *items, const int *item_off,
                            Sink &k);
-hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, hipStream_t s);
-hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, Sink &k);
-hipError_t launch_epi(int p, int b, bool fp32, int mode, const void *args, int grid, hipStream_t s);
-// full stage of the listed elements of order p (neighbours of order <= pn)
-hipError_t launch_full(int p, int pn, bool fp32, int mode, const void *args, int grid, Sink &k);
-hipError_t launch_epi(int p, int b, bool fp32, int mode, const void *args, int grid, Sink &k);
+// The listed elements of every order in one launch (orders lo..pn, nblk
+// blocks per order; lists at args.list + p * lcap, lengths args.count[p]):
+// full stage (order-partitioned scheme), correction and epilogue (order-
+// separated scheme, lo = b)
+hipError_t launch_full_all(int lo, int pn, bool fp32, int mode, const void *args, int nblk, int lcap, Sink &k);
+hipError_t launch_corr_all(int b, int pn, bool fp32, const void *args, double dt, int nblk, int lcap, Sink &k);
+hipError_t launch_epi_all(int b, int pn, bool fp32, int mode, const void *args, int nblk, int lcap, Sink &k);
 hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s);
 hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, int p_hi, double *I_out,
                             signed char *p_new, Sink &k);

@@ -1362,41 +1362,80 @@ __global__ void __launch_bounds__(BLOCK) k_batch_clock(InstDesc *inst, const int
     I.steps_left -= 1;
 }
 
-// Correction of the order-separated scheme for the listed elements of order
-// P (neighbours of order <= PN), one element per lane and no loop around an
-// evaluation: dt times the full right-hand side, minus dt times the base part
-// (rows below K(B), the element's and its neighbours' first K(B) modes) in
-// the rows below K(B).  The base part is evaluated first and kept, negated,
-// in registers; then the full one.
-template <int P, int B, int PN, typename Real>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<(P > PN ? P : PN), Real>(), 8)))
-k_corr(StageArgs<Real> a, double dt)
+// ------------------------------------------------------------ listed elements, every order in one launch
+// The kernels of the listed elements take every order in one launch: block b
+// works on order lo + b / nblk (each block runs one order's code) and on
+// entry (b % nblk) * BLOCK + lane of that order's list (at a.list + p * lcap;
+// its length a.count[p]).  A step graph dispatches its nodes one after
+// another, microseconds apart, so one node per stage for all orders ends the
+// stage sooner than one node per order.
+__device__ __forceinline__ int list_order(int lo, int nblk) { return lo + (int)blockIdx.x / nblk; }
+__device__ __forceinline__ int list_entry(int nblk) { return ((int)blockIdx.x % nblk) * BLOCK + (int)threadIdx.x; }
+
+// full stage of listed element e of order P (order-partitioned scheme)
+template <int P, int PN, typename Real, int MODE>
+__device__ __forceinline__ void full_element(const StageArgs<Real> &a, unsigned e,
+                                             const Real (*sR)[Ord<PN>::K][PN + 1], double xihat, double dt)
 {
-    // the listed elements' kernels run beside the base kernel over all
-    // elements and end the stage: their waves issue first on a shared SIMD
-    __builtin_amdgcn_s_setprio(2);
-    constexpr int K = Ord<P>::K, KB = Ord<B>::K, NTB = Ord<B>::NT;
-    constexpr int KN = Ord<PN>::K, NX = (P > PN ? P : PN) + 1;
-    __shared__ Real sR[3][KN][NX];
-    __shared__ Real sRb[3][KB][NTB];
-    load_trace_table<KN, NX, Real>(sR);
-    load_trace_table<KB, NTB, Real>(sRb);
-    __syncthreads();
     const MeshView &m = a.m;
     const int KS = m.KS, stride = m.stride;
-    const int count = a.count[0];
+    const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
+    const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
+    const unsigned off = e * (unsigned)sizeof(Real);
+    Geo G;
+    load_geo(m.vtx, bEv, e * 4u, G);
+    double hbh[3];
+    hb_modes(G, hbh);
+    Fields<P, Real> s;
+    load_state<P, Real>(bC, bU, KS, off, s);
+    Acc<P, Real> A;
+    acc_init<P, Real>(A, s, true);
+    element_rhs<P, PN, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A, xihat);
+    finish_stage<P, Real, MODE>(a, e, G, hbh, Ord<P>::K, A.L, a.flag);
+}
+
+template <int PN, typename Real, int MODE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<PN, Real>(), 8)))
+k_full_all(StageArgs<Real> a, int lo, int nblk, int lcap)
+{
+    // beside the base kernel over all elements, these end the stage: their
+    // waves issue first on a shared SIMD
+    __builtin_amdgcn_s_setprio(2);
+    constexpr int NX = PN + 1, KN = Ord<PN>::K;
+    __shared__ Real sR[3][KN][NX];
+    load_trace_table<KN, NX, Real>(sR);
+    __syncthreads();
+    const int p = list_order(lo, nblk), i = list_entry(nblk);
+    if (p > PN || i >= a.count[p]) return;
+    const unsigned e = (unsigned)a.list[(size_t)p * (size_t)lcap + (size_t)i];
+    double xihat = a.xihat, dt = a.dt;
+    if (a.inst) {
+        xihat = MODE == MODE_STAGE2 ? a.inst->xh[1] : a.inst->xh[0];
+        dt = a.inst->dt;
+    }
+    switch (p) {
+    case 0: full_element<0, PN, Real, MODE>(a, e, sR, xihat, dt); break;
+    case 1: if constexpr (PN >= 1) full_element<1, PN, Real, MODE>(a, e, sR, xihat, dt); break;
+    case 2: if constexpr (PN >= 2) full_element<2, PN, Real, MODE>(a, e, sR, xihat, dt); break;
+    case 3: if constexpr (PN >= 3) full_element<3, PN, Real, MODE>(a, e, sR, xihat, dt); break;
+    }
+}
+
+// correction of listed element e of order P (order-separated scheme): dt
+// times the full right-hand side, minus dt times the base part (rows below
+// K(B), the element's and its neighbours' first K(B) modes) in the rows below
+// K(B); the base part is evaluated first and kept, negated, in registers
+template <int P, int B, int PN, typename Real>
+__device__ __forceinline__ void corr_element(const StageArgs<Real> &a, unsigned e,
+                                             const Real (*sR)[Ord<PN>::K][PN + 1],
+                                             const Real (*sRb)[Ord<B>::K][Ord<B>::NT], double xihat, double dt)
+{
+    constexpr int K = Ord<P>::K, KB = Ord<B>::K;
+    const MeshView &m = a.m;
+    const int KS = m.KS, stride = m.stride;
     const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
     const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
     const Buf<Real> bL(a.Lc, 3 * KS, stride);
-    double xihat = a.xihat;
-    if (a.inst) {
-        xihat = a.inst->xh[a.stage];
-        dt = a.inst->dt;
-    }
-    // one listed element per thread (the grid covers the list), no loop
-    const int i = blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= count) return;
-    const unsigned e = (unsigned)a.list[i];
     const unsigned off = e * (unsigned)sizeof(Real);
     Geo G;
     load_geo(m.vtx, bEv, e * 4u, G);
@@ -1429,21 +1468,45 @@ k_corr(StageArgs<Real> a, double dt)
         }
 }
 
-// Epilogue of the order-separated scheme for the listed elements of order P:
-// stage value = (base partial value, or c for modes >= K(B)) + correction.
+template <int B, int PN, typename Real>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<PN, Real>(), 8)))
+k_corr_all(StageArgs<Real> a, double dt, int nblk, int lcap)
+{
+    __builtin_amdgcn_s_setprio(2);   // as in k_full_all
+    constexpr int KB = Ord<B>::K, NTB = Ord<B>::NT;
+    constexpr int KN = Ord<PN>::K, NX = PN + 1;
+    __shared__ Real sR[3][KN][NX];
+    __shared__ Real sRb[3][KB][NTB];
+    load_trace_table<KN, NX, Real>(sR);
+    load_trace_table<KB, NTB, Real>(sRb);
+    __syncthreads();
+    const int p = list_order(B, nblk), i = list_entry(nblk);
+    if (p > PN || i >= a.count[p]) return;
+    const unsigned e = (unsigned)a.list[(size_t)p * (size_t)lcap + (size_t)i];
+    double xihat = a.xihat;
+    if (a.inst) {
+        // the clock of a replayed step lives on the device
+        xihat = a.inst->xh[a.stage];
+        dt = a.inst->dt;
+    }
+    switch (p) {
+    case 0: if constexpr (B <= 0) corr_element<0, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
+    case 1: if constexpr (B <= 1 && PN >= 1) corr_element<1, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
+    case 2: if constexpr (B <= 2 && PN >= 2) corr_element<2, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
+    case 3: if constexpr (B <= 3 && PN >= 3) corr_element<3, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
+    }
+}
+
+// epilogue of listed element e of order P (order-separated scheme): stage
+// value = (base partial value, or c for modes >= K(B)) + correction
 template <int P, typename Real, int MODE>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
-k_epi(StageArgs<Real> a, int KB)
+__device__ __forceinline__ void epi_element(const StageArgs<Real> &a, unsigned e, int KB)
 {
     constexpr int K = Ord<P>::K;
     const MeshView &m = a.m;
     const int KS = m.KS, stride = m.stride;
-    const int count = a.count[0];
     const Buf<Real> bC(a.Cin, 3 * KS, stride), bL(a.Lc, 3 * KS, stride), bB(a.Lb, 3 * KB, stride);
     const Buf<int> bEv(m.ev, 3, stride);
-    const int i = blockIdx.x * BLOCK + threadIdx.x;   // one listed element per thread
-    if (i >= count) return;
-    const unsigned e = (unsigned)a.list[i];
     const unsigned off = e * (unsigned)sizeof(Real);
     Geo G;
 #pragma unroll
@@ -1459,44 +1522,19 @@ k_epi(StageArgs<Real> a, int KB)
     finish_stage<P, Real, MODE>(a, e, G, hbh, K, L, a.flag);
 }
 
-// Order-partitioned scheme: the full stage of the listed elements of order P
-// (neighbours of order <= PN), one element per lane over the device-side list;
-// the base kernel skips these elements, so no epilogue joins the two.
-template <int P, int PN, typename Real, int MODE>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<(P > PN ? P : PN), Real>(), 8)))
-k_full(StageArgs<Real> a)
+template <int PN, typename Real, int MODE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
+k_epi_all(StageArgs<Real> a, int KB, int lo, int nblk, int lcap)
 {
-    // the listed elements' kernels run beside the base kernel over all
-    // elements and end the stage: their waves issue first on a shared SIMD
-    __builtin_amdgcn_s_setprio(2);
-    constexpr int NX = (P > PN ? P : PN) + 1, KN = Ord<PN>::K;
-    __shared__ Real sR[3][KN][NX];
-    load_trace_table<KN, NX, Real>(sR);
-    __syncthreads();
-    const MeshView &m = a.m;
-    const int KS = m.KS, stride = m.stride;
-    const int count = a.count[0];
-    const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
-    const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
-    double xihat = a.xihat, dt = a.dt;
-    if (a.inst) {
-        xihat = MODE == MODE_STAGE2 ? a.inst->xh[1] : a.inst->xh[0];
-        dt = a.inst->dt;
+    const int p = list_order(lo, nblk), i = list_entry(nblk);
+    if (p > PN || i >= a.count[p]) return;
+    const unsigned e = (unsigned)a.list[(size_t)p * (size_t)lcap + (size_t)i];
+    switch (p) {
+    case 0: epi_element<0, Real, MODE>(a, e, KB); break;
+    case 1: if constexpr (PN >= 1) epi_element<1, Real, MODE>(a, e, KB); break;
+    case 2: if constexpr (PN >= 2) epi_element<2, Real, MODE>(a, e, KB); break;
+    case 3: if constexpr (PN >= 3) epi_element<3, Real, MODE>(a, e, KB); break;
     }
-    const int i = blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= count) return;
-    const unsigned e = (unsigned)a.list[i];
-    const unsigned off = e * (unsigned)sizeof(Real);
-    Geo G;
-    load_geo(m.vtx, bEv, e * 4u, G);
-    double hbh[3];
-    hb_modes(G, hbh);
-    Fields<P, Real> s;
-    load_state<P, Real>(bC, bU, KS, off, s);
-    Acc<P, Real> A;
-    acc_init<P, Real>(A, s, true);
-    element_rhs<P, PN, Real>(a, e, bC, bU, bNb, s, G, hbh, dt, sR, A, xihat);
-    finish_stage<P, Real, MODE>(a, e, G, hbh, Ord<P>::K, A.L, a.flag);
 }
 
 // ------------------------------------------------------------ p-adaptivity
@@ -1722,57 +1760,6 @@ hipError_t stage_r(int p, int mode, bool sep, const void *args, Sink &s)
     return hipErrorInvalidValue;
 }
 
-template <int P, int B, int PN, typename Real>
-hipError_t corr_pbn(const StageArgs<Real> &a, double dt, int grid, Sink &s)
-{
-    StageArgs<Real> aa = a;
-    void *kargs[] = {&aa, &dt};
-    return emit(s, reinterpret_cast<const void *>(&k_corr<P, B, PN, Real>), dim3(grid), dim3(BLOCK), kargs);
-}
-
-template <int B, int PN, typename Real>
-hipError_t corr_bn(int p, const StageArgs<Real> &a, double dt, int grid, Sink &s)
-{
-    if (p < B || p > PN) return hipErrorInvalidValue;
-    if constexpr (B <= 0 && 0 <= PN) if (p == 0) return corr_pbn<0, B, PN, Real>(a, dt, grid, s);
-    if constexpr (B <= 1 && 1 <= PN) if (p == 1) return corr_pbn<1, B, PN, Real>(a, dt, grid, s);
-    if constexpr (B <= 2 && 2 <= PN) if (p == 2) return corr_pbn<2, B, PN, Real>(a, dt, grid, s);
-    if constexpr (B <= 3 && 3 <= PN) if (p == 3) return corr_pbn<3, B, PN, Real>(a, dt, grid, s);
-    return hipErrorInvalidValue;
-}
-
-template <typename Real>
-hipError_t corr_r(int p, int b, int pn, const void *args, double dt, int grid, Sink &s)
-{
-    const StageArgs<Real> &a = *static_cast<const StageArgs<Real> *>(args);
-    if (b == 0 && pn == 1) return corr_bn<0, 1, Real>(p, a, dt, grid, s);
-    if (b == 0 && pn == 2) return corr_bn<0, 2, Real>(p, a, dt, grid, s);
-    if (b == 0 && pn == 3) return corr_bn<0, 3, Real>(p, a, dt, grid, s);
-    if (b == 1 && pn == 2) return corr_bn<1, 2, Real>(p, a, dt, grid, s);
-    if (b == 1 && pn == 3) return corr_bn<1, 3, Real>(p, a, dt, grid, s);
-    if (b == 2 && pn == 3) return corr_bn<2, 3, Real>(p, a, dt, grid, s);
-    return hipErrorInvalidValue;
-}
-
-template <typename Real>
-hipError_t epi_r(int p, int mode, int KB, const void *args, int grid, Sink &s)
-{
-    StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
-    void *kargs[] = {&a, &KB};
-#define SWE_EPI(PP)                                                                                     \
-    if (p == PP)                                                                                        \
-        return emit(s,                                                                                  \
-                    mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_epi<PP, Real, MODE_STAGE1>)    \
-                                        : reinterpret_cast<const void *>(&k_epi<PP, Real, MODE_STAGE2>),   \
-                    dim3(grid), dim3(BLOCK), kargs);
-    SWE_EPI(0)
-    SWE_EPI(1)
-    SWE_EPI(2)
-    SWE_EPI(3)
-#undef SWE_EPI
-    return hipErrorInvalidValue;
-}
-
 template <int P, typename Real>
 hipError_t usolve_p(const void *args, hipStream_t s)
 {
@@ -1868,70 +1855,82 @@ hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, 
     return launch_stage(p, fp32, mode, sep, args, k);
 }
 
-hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, Sink &k)
-{
-    if (grid <= 0) return hipSuccess;
-    return fp32 ? corr_r<float>(p, b, pn, args, dt, grid, k) : corr_r<double>(p, b, pn, args, dt, grid, k);
-}
-
-hipError_t launch_corr(int p, int b, int pn, bool fp32, const void *args, double dt, int grid, hipStream_t s)
-{
-    Sink k;
-    k.s = s;
-    return launch_corr(p, b, pn, fp32, args, dt, grid, k);
-}
-
-template <int P, int PN, typename Real>
-hipError_t full_ppn(int mode, const void *args, int grid, Sink &s)
+template <int PN, typename Real>
+hipError_t full_all_r(int mode, const void *args, int lo, int nblk, int lcap, Sink &s)
 {
     StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
-    void *kargs[] = {&a};
+    void *kargs[] = {&a, &lo, &nblk, &lcap};
+    const dim3 g((PN - lo + 1) * nblk), b(BLOCK);
     return emit(s,
-                mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_full<P, PN, Real, MODE_STAGE1>)
-                                    : reinterpret_cast<const void *>(&k_full<P, PN, Real, MODE_STAGE2>),
-                dim3(grid), dim3(BLOCK), kargs);
+                mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_full_all<PN, Real, MODE_STAGE1>)
+                                    : reinterpret_cast<const void *>(&k_full_all<PN, Real, MODE_STAGE2>),
+                g, b, kargs);
 }
 
-template <int PN, typename Real>
-hipError_t full_pn(int p, int mode, const void *args, int grid, Sink &s)
+hipError_t launch_full_all(int lo, int pn, bool fp32, int mode, const void *args, int nblk, int lcap, Sink &k)
 {
-    if (p > PN) return hipErrorInvalidValue;
-    if constexpr (0 <= PN) if (p == 0) return full_ppn<0, PN, Real>(mode, args, grid, s);
-    if constexpr (1 <= PN) if (p == 1) return full_ppn<1, PN, Real>(mode, args, grid, s);
-    if constexpr (2 <= PN) if (p == 2) return full_ppn<2, PN, Real>(mode, args, grid, s);
-    if constexpr (3 <= PN) if (p == 3) return full_ppn<3, PN, Real>(mode, args, grid, s);
-    return hipErrorInvalidValue;
-}
-
-template <typename Real>
-hipError_t full_r(int p, int pn, int mode, const void *args, int grid, Sink &s)
-{
+    if (nblk <= 0) return hipSuccess;
+    if (lo < 0 || lo > pn || pn < 1 || pn > 3 || (mode != MODE_STAGE1 && mode != MODE_STAGE2))
+        return hipErrorInvalidValue;
     switch (pn) {
-    case 1: return full_pn<1, Real>(p, mode, args, grid, s);
-    case 2: return full_pn<2, Real>(p, mode, args, grid, s);
-    case 3: return full_pn<3, Real>(p, mode, args, grid, s);
+    case 1: return fp32 ? full_all_r<1, float>(mode, args, lo, nblk, lcap, k) : full_all_r<1, double>(mode, args, lo, nblk, lcap, k);
+    case 2: return fp32 ? full_all_r<2, float>(mode, args, lo, nblk, lcap, k) : full_all_r<2, double>(mode, args, lo, nblk, lcap, k);
+    case 3: return fp32 ? full_all_r<3, float>(mode, args, lo, nblk, lcap, k) : full_all_r<3, double>(mode, args, lo, nblk, lcap, k);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_full(int p, int pn, bool fp32, int mode, const void *args, int grid, Sink &k)
+template <int B, int PN, typename Real>
+hipError_t corr_all_r(const void *args, double dt, int nblk, int lcap, Sink &s)
 {
-    if (grid <= 0) return hipSuccess;
-    return fp32 ? full_r<float>(p, pn, mode, args, grid, k) : full_r<double>(p, pn, mode, args, grid, k);
+    StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
+    void *kargs[] = {&a, &dt, &nblk, &lcap};
+    return emit(s, reinterpret_cast<const void *>(&k_corr_all<B, PN, Real>), dim3((PN - B + 1) * nblk), dim3(BLOCK),
+                kargs);
 }
 
-hipError_t launch_epi(int p, int b, bool fp32, int mode, const void *args, int grid, Sink &k)
+template <typename Real>
+hipError_t corr_all_t(int b, int pn, const void *args, double dt, int nblk, int lcap, Sink &k)
 {
-    if (grid <= 0) return hipSuccess;
+    if (b == 0 && pn == 1) return corr_all_r<0, 1, Real>(args, dt, nblk, lcap, k);
+    if (b == 0 && pn == 2) return corr_all_r<0, 2, Real>(args, dt, nblk, lcap, k);
+    if (b == 0 && pn == 3) return corr_all_r<0, 3, Real>(args, dt, nblk, lcap, k);
+    if (b == 1 && pn == 2) return corr_all_r<1, 2, Real>(args, dt, nblk, lcap, k);
+    if (b == 1 && pn == 3) return corr_all_r<1, 3, Real>(args, dt, nblk, lcap, k);
+    if (b == 2 && pn == 3) return corr_all_r<2, 3, Real>(args, dt, nblk, lcap, k);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_corr_all(int b, int pn, bool fp32, const void *args, double dt, int nblk, int lcap, Sink &k)
+{
+    if (nblk <= 0) return hipSuccess;
+    return fp32 ? corr_all_t<float>(b, pn, args, dt, nblk, lcap, k) : corr_all_t<double>(b, pn, args, dt, nblk, lcap, k);
+}
+
+template <int PN, typename Real>
+hipError_t epi_all_r(int mode, int KB, const void *args, int lo, int nblk, int lcap, Sink &s)
+{
+    StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
+    void *kargs[] = {&a, &KB, &lo, &nblk, &lcap};
+    const dim3 g((PN - lo + 1) * nblk), b(BLOCK);
+    return emit(s,
+                mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_epi_all<PN, Real, MODE_STAGE1>)
+                                    : reinterpret_cast<const void *>(&k_epi_all<PN, Real, MODE_STAGE2>),
+                g, b, kargs);
+}
+
+hipError_t launch_epi_all(int b, int pn, bool fp32, int mode, const void *args, int nblk, int lcap, Sink &k)
+{
+    if (nblk <= 0) return hipSuccess;
+    if (b < 0 || b > pn || pn < 1 || pn > 3 || (mode != MODE_STAGE1 && mode != MODE_STAGE2))
+        return hipErrorInvalidValue;
     const int KB = (b + 1) * (b + 2) / 2;
-    return fp32 ? epi_r<float>(p, mode, KB, args, grid, k) : epi_r<double>(p, mode, KB, args, grid, k);
-}
-
-hipError_t launch_epi(int p, int b, bool fp32, int mode, const void *args, int grid, hipStream_t s)
-{
-    Sink k;
-    k.s = s;
-    return launch_epi(p, b, fp32, mode, args, grid, k);
+    switch (pn) {
+    case 1: return fp32 ? epi_all_r<1, float>(mode, KB, args, b, nblk, lcap, k) : epi_all_r<1, double>(mode, KB, args, b, nblk, lcap, k);
+    case 2: return fp32 ? epi_all_r<2, float>(mode, KB, args, b, nblk, lcap, k) : epi_all_r<2, double>(mode, KB, args, b, nblk, lcap, k);
+    case 3: return fp32 ? epi_all_r<3, float>(mode, KB, args, b, nblk, lcap, k) : epi_all_r<3, double>(mode, KB, args, b, nblk, lcap, k);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s)
