@@ -1,7 +1,7 @@
 """Throughput of the DG shallow-water hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload tidal|tsunami|static32|batched|served]
+                    [--workload tidal|tsunami|static32|dambreak|batched|served]
 
 tidal (default): 512x512x2 triangulation of a 100 km square, nodes jittered
   by U(-0.2h, 0.2h) (seed 2), uniform order p = 2, bathymetry
@@ -16,6 +16,13 @@ tsunami: 256x256x2 jittered (seed 3), linear shelf 4000 m -> 50 m, 2 m hump,
   path (corrections on a second stream) beside it.
 static32: the tidal mesh with base order 1 and every 32nd element at order 2,
   order-separated on two streams, FP32 path.
+dambreak: the paper's radial dam break on 1024x1024x2 = 2,097,152 jittered
+  triangles of [0,5]^2 (g = 1, h_b = 0.5 m, walls, linear friction), 100
+  steps of 1e-5 s as in its static runs: uniform p0, p1, p2 (fused kernel)
+  and every 32nd element at the higher order (p0-1, p1-2; order-partitioned
+  and order-separated), FP64 and FP32, each beside the paper's own time per
+  stage on its hardware (context).  The value is static 1/32 p1-2,
+  order-partitioned, FP64.
 batched: 64 independent instances (seeds 4000+i), log-uniform 16k-500k
   elements, p in {1,2,3}, tidal or hump, random smooth bathymetry, 300 steps
   each; FP32 and FP64 batched against the plain FP64 solver run one instance
@@ -175,7 +182,8 @@ def run_uniform(prob, precision, steps, warmup):
                          "frac": achieved / HBM_PEAK_GBS,
                          "traffic": traffic / 1e9 / launch_s if traffic is not None else None,
                          "traffic_bytes_per_launch": traffic,
-                         "kernel": f"k_stage_sh<{p},{real}> (fused stage, edge fluxes shared within a block)",
+                         "kernel": f"k_stage_sh<{p},{real}> (fused stage, edge fluxes shared within a block)"
+                                   if p >= 1 else f"k_stage<{p},{real}> (fused stage, element gather)",
                          "bytes_per_launch": bpe * ne, "avg_launch_us": launch_s * 1e6}}
 
 
@@ -212,6 +220,51 @@ def run_separated(prob, precision, steps, warmup, separate=1, chunk=50):
     frac = kdist / kdist.sum()
     return {"value": dof_stages / (ms * 1e-3), "ms_per_step": ms / steps,
             "order_fractions": {f"p{i}": float(frac[i]) for i in range(4) if frac[i] > 0}}
+
+
+# The paper's times per RK stage (ms) for the dam break on 2,097,152
+# triangles (Fig. flow_non-separated, the separated-kernel figure and
+# Tab. timings): Jetson AGX Xavier (ARM-AGX: 3 Carmel cores + integrated Volta
+# GPU) and 2x EPYC 7742 + Quadro RTX 6000 (AMD-RTX).  Context, not targets.
+DAMBREAK_PAPER_MS = {
+    "p0": {"ARM-AGX GPU": 28.86, "ARM-AGX CPU": 55.11},
+    "p1": {"ARM-AGX GPU": 174.55, "ARM-AGX CPU": 342.31},
+    "p2": {"ARM-AGX GPU": 806.55, "ARM-AGX CPU": 1425.03},
+    "p0-1 1/32": {"ARM-AGX GPU unseparated": 118.87, "ARM-AGX GPU separated": 144.55,
+                  "ARM-AGX CPU+GPU separated": 127.40, "AMD-RTX CPU separated": 24.85,
+                  "AMD-RTX GPU separated": 16.12, "AMD-RTX CPU+GPU separated": 101.0},
+    "p1-2 1/32": {"ARM-AGX CPU unseparated": 517.70, "ARM-AGX GPU separated": 714.25,
+                  "ARM-AGX CPU+GPU separated": 460.01, "AMD-RTX CPU separated": 68.05,
+                  "AMD-RTX GPU separated": 72.39, "AMD-RTX CPU+GPU separated": 222.2},
+}
+
+
+def run_dambreak(steps, warmup, n=1024):
+    """The radial dam break: uniform orders on the fused stage kernel, the
+    statically adaptive 1/32 setups on the order-partitioned and
+    order-separated schemes; FP64 and FP32."""
+    import numpy as np
+    from paper_2311_11348_amd import inputs as I
+    from paper_2311_11348_amd import swe
+    out = {}
+    setups = [("p0", 0, 0, 0), ("p1", 1, 1, 0), ("p2", 2, 2, 0), ("p0-1 1/32", 0, 1, 32), ("p1-2 1/32", 1, 2, 32)]
+    for name, lo, hi, every in setups:
+        prob = I.config_dambreak(n=n, p_lo=lo, p_hi=hi, every=every)
+        dof = 3 * sum(K_OF_P[q] * c for q, c in enumerate(np.bincount(prob.p, minlength=4)))
+        row = {"dof_per_stage": int(dof)}
+        for prec, tag in ((swe.SWE_FP64, "fp64"), (swe.SWE_FP32_WB, "fp32")):
+            print(f"bench: dambreak {name} {tag} ({prob.mesh.ne} elements)", file=sys.stderr, flush=True)
+            if every == 0:
+                r = run_uniform(prob, prec, steps, warmup)
+                row[tag] = {"scheme": "fused", "ms_per_stage": r["ms_per_step"] / 2, "value": r["value"],
+                            "hbm_frac": r["roofline"]["frac"], "kernel": r["roofline"]["kernel"]}
+            else:
+                for sep, scheme in ((2, "partitioned"), (1, "separated")):
+                    r = run_separated(prob, prec, steps, warmup, separate=sep)
+                    row[f"{tag}_{scheme}"] = {"ms_per_stage": r["ms_per_step"] / 2, "value": r["value"]}
+        row["paper_ms_per_stage"] = DAMBREAK_PAPER_MS[name]
+        out[name] = row
+    return out
 
 
 def run_batched(count, steps, warmup):
@@ -364,7 +417,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", choices=["tidal", "tsunami", "static32", "batched", "served"], default="tidal")
+    ap.add_argument("--workload", choices=["tidal", "tsunami", "static32", "dambreak", "batched", "served"],
+                    default="tidal")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--duration", type=float, default=120.0)
     ap.add_argument("--rate", type=float, default=20.0)
@@ -429,6 +483,20 @@ def main() -> int:
                    separated_fp32={"value": rs["value"], "ms_per_step": rs["ms_per_step"],
                                    "dtype": "f32 (f64 bathymetry terms)",
                                    "scheme": "base + corrections on a second stream, joined by epilogues"})
+    elif args.workload == "dambreak":
+        steps = args.steps if args.steps != 500 else 100
+        n = args.n or 1024
+        rows = run_dambreak(steps, args.warmup, n=n)
+        head = rows["p1-2 1/32"]["fp64_partitioned"]
+        best_ms = min(rows["p1-2 1/32"]["paper_ms_per_stage"].values())
+        out.update(steps=steps, value=head["value"], ms_per_step=2 * head["ms_per_stage"], dtype="f64",
+                   vs_baseline=best_ms / head["ms_per_stage"] if n == 1024 else None,
+                   baseline={"what": "the paper's fastest time per stage for static 1/32 p1-2 on 2,097,152 "
+                                     "triangles (AMD-RTX, CPU, separated), on its own hardware", "ms": best_ms},
+                   config={"workload": f"dambreak: {n}x{n}x2 jittered triangulation of [0,5]^2, "
+                                       f"{2 * n * n} elements, g=1, h_b=0.5 m, linear friction, dt=1e-5 s; "
+                                       "headline: every 32nd element p=2, base p=1, order-partitioned, FP64",
+                           "elements": 2 * n * n}, setups=rows)
     elif args.workload == "batched":
         steps = args.steps if args.steps != 500 else 300
         r = run_batched(args.instances, steps, args.warmup)

@@ -239,14 +239,18 @@ class Problem:
     adapt: int = 0
     adapt_tau: float = 1e-3
     bathy: Optional[Callable] = None
+    dt_fixed: Optional[float] = None   # a prescribed step instead of the CFL rule
 
     def dt(self) -> float:
         """Fixed step from the analytic initial state at the vertices and centroids.
 
         dt = CFL * min_e d_e / ((2 p_max + 1) * max(|u0| + sqrt(g H0))), with d_e
         the inscribed-circle diameter.  Only point values of the initial
-        condition and bathymetry are used.
+        condition and bathymetry are used.  ``dt_fixed``, when set, is returned
+        instead.
         """
+        if self.dt_fixed is not None:
+            return float(self.dt_fixed)
         pts = np.concatenate([self.mesh.vxy, self.mesh.centroids()], axis=0)
         xi, U, V = self.ic(pts[:, 0], pts[:, 1])
         if self.bathy is not None:
@@ -284,6 +288,33 @@ def config_c3(n: int = 256, seed: int = 3) -> Problem:
     return _problem("c3", mesh, bathy_shelf(), ic_gaussian(2.0, 2.0e4, L_DOMAIN / 4, L_DOMAIN / 2),
                     1, 1, 3, f_coriolis=CORIOLIS_BAHAMAS, friction=FRICTION_QUADRATIC,
                     friction_coef=CF_BAHAMAS, steps=1000, adapt=1, adapt_tau=1e-3)
+
+
+DAMBREAK_LENGTH = 5.0
+DAMBREAK_DT = 1.0e-5
+
+
+def config_dambreak(n: int = 1024, p_lo: int = 1, p_hi: int = 2, every: int = 32, seed: int = 6,
+                    dt_fixed: Optional[float] = DAMBREAK_DT) -> Problem:
+    """Radial dam break of Sec. "Radial dam break" with the physical values of
+    its table of physical quantities: [0,5]^2, g = 1, constant bathymetry
+    0.5 m, walls on every side, Coriolis 1e-5 1/s, linear friction
+    tau_bf = 1e-4 H (that is -1e-4 q), the discontinuous radial elevation at
+    rest.  The mesh is the n x n x 2 triangulation with interior nodes
+    jittered by U(-0.2h, 0.2h) (n = 1024: 2,097,152 triangles, the count
+    the paper measures on).  Orders: p_lo everywhere and p_hi on every
+    ``every``-th element in mesh order (the statically adaptive setups;
+    every = 1 gives uniform p_hi, every = 0 uniform p_lo), base order p_lo.
+    Time step: the static runs' 1e-5 s unless ``dt_fixed`` is None (then the
+    CFL rule)."""
+    mesh = structured_mesh(n, length=DAMBREAK_LENGTH, jitter=0.2, seed=seed)
+    p = np.full(mesh.ne, p_lo, np.int8)
+    if every > 0:
+        p[::every] = p_hi
+    p_max = int(p.max())
+    return _problem(f"dambreak{n}", mesh, bathy_flat(0.5), ic_dambreak(), p, min(p_lo, p_max), p_max, g=1.0,
+                    f_coriolis=1.0e-5, friction=FRICTION_LINEAR, friction_coef=1.0e-4, steps=100,
+                    dt_fixed=dt_fixed)
 
 
 def instance_mesh_n(n_elements: float) -> int:

@@ -1,0 +1,81 @@
+"""The paper's radial dam break (discontinuous radial elevation at rest on
+[0,5]^2, g = 1, flat 0.5 m bathymetry, walls, linear friction) against the
+oracle.
+
+Small mesh (16x16x2): uniform p0, p1, p2 on the fused stage kernel and the
+statically adaptive setups (every 32nd element at the higher order, p0-1 and
+p1-2) on the order-partitioned and order-separated schemes, FP64 and FP32,
+ten steps at the CFL step.  Full size (1024x1024x2 = 2,097,152 triangles, the
+mesh the paper measures on): static 1/32 p1-2, order-partitioned FP64, one
+step of the static runs' 1e-5 s, state and step increment against the
+oracle on every element.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2311_11348_amd import inputs as I
+from paper_2311_11348_amd import swe
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    assert np.all(np.isfinite(a)), "non-finite values in the GPU result"
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+SETUPS = {"p0": (0, 0, 0), "p1": (1, 1, 0), "p2": (2, 2, 0), "p0-1 1/32": (0, 1, 32), "p1-2 1/32": (1, 2, 32)}
+
+
+@pytest.mark.parametrize("name,separate", [("p0", 0), ("p1", 0), ("p2", 0), ("p0-1 1/32", 1), ("p0-1 1/32", 2),
+                                           ("p1-2 1/32", 1), ("p1-2 1/32", 2)])
+@pytest.mark.parametrize("precision", [swe.SWE_FP64, swe.SWE_FP32_WB])
+def test_dambreak_small_matches_oracle(name, separate, precision):
+    lo, hi, every = SETUPS[name]
+    prob = I.config_dambreak(n=16, p_lo=lo, p_hi=hi, every=every, dt_fixed=None)
+    orc = Oracle.from_problem(prob)
+    c0 = orc.project(prob.ic)
+    dt, steps = prob.dt(), 10
+    ref = orc.step(c0, steps, dt)
+    with swe.context_for(prob, precision=precision, separate=separate) as ctx:
+        ctx.set_state(c0)
+        before, _ = ctx.state()
+        ctx.step(steps, dt)
+        ctx.sync()
+        got, t = ctx.state()
+    err, err_inc = rel(got, ref), rel(got - before, ref - c0)
+    say(f"dambreak {name} separate={separate} precision={precision}: {prob.mesh.ne} elements, "
+        f"{int((prob.p == hi).sum())} at p{hi}; rel L2 {err:.2e}, increment {err_inc:.2e}")
+    assert abs(t - steps * dt) < 1e-12
+    if precision == swe.SWE_FP64:
+        assert err < 1e-12 and err_inc < 1e-9
+    else:
+        assert err < 1e-5 and err_inc < 1e-3
+
+
+def test_dambreak_full_size_static32_p12():
+    prob = I.config_dambreak(n=1024, p_lo=1, p_hi=2, every=32)
+    say(f"dambreak full size: {prob.mesh.ne} elements, oracle set-up")
+    orc = Oracle.from_problem(prob)
+    c0 = orc.project(prob.ic)
+    dt = prob.dt()
+    say("  oracle step")
+    ref = orc.step(c0, 1, dt)
+    say("  GPU step (order-partitioned, FP64)")
+    with swe.context_for(prob, precision=swe.SWE_FP64, separate=2) as ctx:
+        ctx.set_state(c0)
+        before, _ = ctx.state()
+        ctx.step(1, dt)
+        ctx.sync()
+        got, _ = ctx.state()
+    err, err_inc = rel(got, ref), rel(got - before, ref - c0)
+    say(f"  rel L2 {err:.2e}, increment {err_inc:.2e} (increment / state {rel(ref, c0):.1e})")
+    assert err < 1e-12 and err_inc < 1e-9
