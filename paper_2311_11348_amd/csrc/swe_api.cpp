@@ -277,6 +277,19 @@ hipError_t enqueue_stage(swe_ctx *c, int mode, int in, int out, double tstage, d
 
 bool separated(const swe_ctx *c) { return c->cfg.separate && c->cfg.p_base < c->cfg.p_max; }
 
+// Base pass of the order-separated and order-partitioned schemes: the
+// shared-flux kernel at the base order where there is one (edge items built,
+// base order 1..3), else the element-gather kernel.
+template <typename Real>
+hipError_t launch_base(Lanes &L, int mode, StageArgs<Real> &a)
+{
+    swe_ctx *c = L.c;
+    const int b = c->cfg.p_base;
+    if (c->d_items && stage_sh_supported(b, c->fp32))
+        return launch_stage_sh(b, c->fp32, mode, &a, c->d_items, c->d_item_off, L.a);
+    return launch_stage(b, c->fp32, mode, true, &a, L.a);
+}
+
 // Blocks per order of a one-launch list kernel (every order's list fits):
 // with adaptivity the lengths live on the device and each may reach ne.
 int list_blocks(const swe_ctx *c)
@@ -330,7 +343,7 @@ hipError_t enqueue_separated(Lanes &L, int mode, int in, int out, double tstage,
     a.Lc = static_cast<Real *>(c->d_Lc);
     hipError_t e = L.fork();
     if (e != hipSuccess) return e;
-    e = launch_stage(b, c->fp32, mode, true, &a, L.a);
+    e = launch_base<Real>(L, mode, a);
     if (e != hipSuccess) return e;
     // the corrections of every order in one launch on branch B, then (after
     // the join) the epilogues of every order in one launch
@@ -365,7 +378,7 @@ hipError_t enqueue_partitioned(Lanes &L, int mode, int in, int out, double tstag
     a.skip_listed = 1;
     hipError_t e = L.fork();
     if (e != hipSuccess) return e;
-    e = launch_stage(b, c->fp32, mode, true, &a, L.a);
+    e = launch_base<Real>(L, mode, a);
     if (e != hipSuccess) return e;
     // the listed elements of every order in one launch on branch B
     a.skip_listed = 0;

@@ -1047,6 +1047,12 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
     if (it1 < n) sh_store<P, Real>(S, w1, r1);
     __syncthreads();
     if (!live) return;
+    // base pass of the order-partitioned scheme: a listed element belongs to
+    // the full-order kernel of its order (the fluxes of its edges above were
+    // taken at the base order, which is exact only for unlisted elements,
+    // whose neighbours all have the base order)
+    const bool listed = a.inlist && a.inlist[e];
+    if (a.skip_listed && listed) return;
 
     // 3. volume and source terms, the three edge fluxes lifted, the stage finished
     if constexpr (!early_geo) geo_from_ids(m.vtx, id3, G);
@@ -1116,6 +1122,16 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
 #pragma unroll
             for (int q = 0; q < K; ++q) bL.st(j * KS + q, off, A.L[j][q]);
     } else {
+        if (a.Lb && listed) {
+            // base pass of the order-separated scheme: the listed element's
+            // base part waits in Lb for the epilogue
+            const Buf<Real> bB(a.Lb, 3 * K, stride);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int q = 0; q < K; ++q) bB.st(j * K + q, off, A.L[j][q]);
+            return;
+        }
         finish_stage<P, Real, MODE>(a, e, G, hbh, K, A.L, flag);
     }
 }
@@ -1124,6 +1140,7 @@ template <int P, typename Real, int MODE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sh_waves<P, Real>(), 8)))
 k_stage_sh(StageArgs<Real> a, const unsigned *items, const int *item_off)
 {
+    if (a.inst && !a.inst->run) return;   // the step's clock stopped (failure): the whole block leaves
     __shared__ ShLds<P, Real> S;
     load_trace_lds<P, Real>(S);
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -1398,6 +1415,7 @@ template <int PN, typename Real, int MODE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<PN, Real>(), 8)))
 k_full_all(StageArgs<Real> a, int lo, int nblk, int lcap)
 {
+    if (a.inst && !a.inst->run) return;   // the step's clock stopped (failure)
     // beside the base kernel over all elements, these end the stage: their
     // waves issue first on a shared SIMD
     __builtin_amdgcn_s_setprio(2);
@@ -1472,6 +1490,7 @@ template <int B, int PN, typename Real>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<PN, Real>(), 8)))
 k_corr_all(StageArgs<Real> a, double dt, int nblk, int lcap)
 {
+    if (a.inst && !a.inst->run) return;   // the step's clock stopped (failure)
     __builtin_amdgcn_s_setprio(2);   // as in k_full_all
     constexpr int KB = Ord<B>::K, NTB = Ord<B>::NT;
     constexpr int KN = Ord<PN>::K, NX = PN + 1;
@@ -1526,6 +1545,7 @@ template <int PN, typename Real, int MODE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
 k_epi_all(StageArgs<Real> a, int KB, int lo, int nblk, int lcap)
 {
+    if (a.inst && !a.inst->run) return;   // the step's clock stopped (failure)
     const int p = list_order(lo, nblk), i = list_entry(nblk);
     if (p > PN || i >= a.count[p]) return;
     const unsigned e = (unsigned)a.list[(size_t)p * (size_t)lcap + (size_t)i];
