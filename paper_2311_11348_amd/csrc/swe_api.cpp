@@ -64,6 +64,12 @@ struct swe_ctx {
     int list_off[5] = {0, 0, 0, 0, 0};
     int list_cnt[4] = {0, 0, 0, 0};
     std::vector<int> nb_host;             // [3][stride] neighbour ids / boundary codes
+    std::vector<unsigned char> nbk_host;  // [stride] neighbours' local edge ids, 2 bits per edge
+    // static order map of a separated context: elements renumbered so that
+    // the unlisted ones come first and each order's listed ones follow in
+    // one contiguous range (each group in Morton order)
+    bool grouped = false;
+    int64_t n_unlisted = 0;
     hipEvent_t ev_ready = nullptr, ev_corr = nullptr;
     swe_batch *batch = nullptr;           // resident in this batch, or null
     int slot = -1;
@@ -378,8 +384,14 @@ hipError_t enqueue_partitioned(Lanes &L, int mode, int in, int out, double tstag
     a.skip_listed = 1;
     hipError_t e = L.fork();
     if (e != hipSuccess) return e;
-    e = launch_base<Real>(L, mode, a);
-    if (e != hipSuccess) return e;
+    // with the elements grouped (static order map) the unlisted ones are the
+    // first n_unlisted: the base kernel covers their blocks only
+    if (!c->grouped || c->n_unlisted > 0) {
+        a.blocks = c->grouped ? (int)((c->n_unlisted + BLOCK - 1) / BLOCK) : 0;
+        e = launch_base<Real>(L, mode, a);
+        if (e != hipSuccess) return e;
+        a.blocks = 0;
+    }
     // the listed elements of every order in one launch on branch B
     a.skip_listed = 0;
     a.list = c->d_list;
@@ -592,6 +604,144 @@ hipError_t enqueue_rhs_split(swe_ctx *c, double t)
         e = launch_corr_all(b, pm, c->fp32, &a, 1.0, list_blocks(c), (int)c->ne, k);
     }
     return e;
+}
+
+#ifndef SWE_SHARED_FLUX
+#define SWE_SHARED_FLUX 1
+#endif
+// Edge items of the shared-flux stage kernel for the current numbering
+// (replacing any built before); none when a block would hold more than the
+// kernel takes.
+swe_status build_items(swe_ctx *c)
+{
+    if (c->d_items) (void)hipFree(c->d_items);
+    if (c->d_item_off) (void)hipFree(c->d_item_off);
+    c->d_items = nullptr;
+    c->d_item_off = nullptr;
+    if (SWE_SHARED_FLUX && stage_sh_supported(c->cfg.p_max, c->fp32)) {
+        const int64_t ne = c->ne;
+        const int S = c->stride;
+        // edge items per block of BLOCK elements, grouped by kind: pairs of
+        // elements of the block (once, from the lower index), neighbours
+        // outside the block, land edges, open edges
+        const int64_t nblk = (ne + BLOCK - 1) / BLOCK;
+        std::vector<unsigned> items;
+        std::vector<int> ioff((size_t)nblk + 1, 0);
+        items.reserve((size_t)ne * 2);
+        for (int64_t bi = 0; bi < nblk; ++bi) {
+            ioff[(size_t)bi] = (int)items.size();
+            const int64_t e0 = bi * BLOCK, e1 = std::min<int64_t>(e0 + BLOCK, ne);
+            for (unsigned kind = 0; kind < 4; ++kind)
+                for (int64_t ei = e0; ei < e1; ++ei)
+                    for (int k = 0; k < 3; ++k) {
+                        const int n = c->nb_host[(size_t)k * S + ei];
+                        unsigned kd;
+                        int lb = 0, kb = 0;
+                        if (n >= 0 && n / BLOCK == bi) {
+                            if (n < ei) continue;      // the pair is taken from the lower index
+                            kd = 0;
+                            lb = (int)(n - e0);
+                            kb = (c->nbk_host[ei] >> (2 * k)) & 3;
+                        } else if (n >= 0) {
+                            kd = 1;
+                        } else if (n == NB_LAND) {
+                            kd = 2;
+                        } else {
+                            kd = 3;
+                        }
+                        if (kd != kind) continue;
+                        items.push_back((unsigned)(ei - e0) | ((unsigned)k << 8) | ((unsigned)lb << 10) |
+                                        ((unsigned)kb << 18) | (kd << 20));
+                    }
+        }
+        ioff[(size_t)nblk] = (int)items.size();
+        // the kernel takes at most two items per lane; a block with more
+        // (a mesh ordering with long block boundaries) leaves the mesh to
+        // the element-gather kernel
+        int most = 0;
+        for (int64_t bi = 0; bi < nblk; ++bi) most = std::max(most, ioff[(size_t)bi + 1] - ioff[(size_t)bi]);
+        if (most <= 2 * BLOCK) {
+            HIP_TRY(c, hipMalloc(&c->d_items, sizeof(unsigned) * std::max<size_t>(items.size(), 1)));
+            HIP_TRY(c, hipMalloc(&c->d_item_off, sizeof(int) * ioff.size()));
+            if (!items.empty()) HIP_TRY(c, h2d(c, c->d_items, items.data(), sizeof(unsigned) * items.size()));
+            HIP_TRY(c, h2d(c, c->d_item_off, ioff.data(), sizeof(int) * ioff.size()));
+        }
+    }
+    return SWE_OK;
+}
+
+// Renumber the elements: new internal index i is the element at old index
+// order[i].  Every element-indexed array kept here and on the device follows
+// (the state itself is written again by the caller); step graphs are dropped.
+swe_status relayout(swe_ctx *c, const std::vector<int> &order)
+{
+    const int64_t ne = c->ne;
+    const int S = c->stride;
+    std::vector<int> inew(ne);
+    for (int64_t i = 0; i < ne; ++i) inew[order[i]] = (int)i;
+    std::vector<double> src;
+    if (c->d_src) {
+        src.resize((size_t)ne * 3 * c->K);
+        const swe_status st = download(c, c->d_src, 3, src.data(), false);
+        if (st) return st;
+    }
+    std::vector<int> e_perm(ne), ev((size_t)3 * S, 0), nb((size_t)3 * S, NB_LAND);
+    std::vector<unsigned char> nbk(S, 0);
+    std::vector<double> sfac(ne);
+    std::vector<signed char> pe(ne);
+    for (int64_t i = 0; i < ne; ++i) {
+        const int o = order[i];
+        e_perm[i] = c->e_perm[o];
+        sfac[i] = c->sfac[o];
+        pe[i] = c->p[o];
+        nbk[i] = c->nbk_host[o];
+        for (int k = 0; k < 3; ++k) {
+            ev[(size_t)k * S + i] = c->ev[(size_t)k * S + o];
+            const int n = c->nb_host[(size_t)k * S + o];
+            nb[(size_t)k * S + i] = n >= 0 ? inew[n] : n;
+        }
+    }
+    c->e_perm.swap(e_perm);
+    for (int64_t i = 0; i < ne; ++i) c->e_iperm[c->e_perm[i]] = (int)i;
+    c->ev.swap(ev);
+    c->nb_host.swap(nb);
+    c->nbk_host.swap(nbk);
+    c->sfac.swap(sfac);
+    c->p.swap(pe);
+    drop_step_graph(c);
+    HIP_TRY(c, h2d(c, c->d_ev, c->ev.data(), sizeof(int) * 3 * S));
+    HIP_TRY(c, h2d(c, c->d_nb, c->nb_host.data(), sizeof(int) * 3 * S));
+    HIP_TRY(c, h2d(c, c->d_nbk, c->nbk_host.data(), S));
+    swe_status st = build_items(c);
+    if (st) return st;
+    if (c->d_src) st = upload_state(c, src.data(), c->d_src);
+    return st;
+}
+
+// Static order map of a separated context: unlisted elements first, then the
+// listed elements of each order, every group in the current (Morton) order,
+// so that each order's list is one contiguous range of element slots.
+swe_status group_by_lists(swe_ctx *c)
+{
+    const int b = c->cfg.p_base, S = c->stride;
+    const int64_t ne = c->ne;
+    std::vector<std::vector<int>> grp(5);
+    for (int64_t i = 0; i < ne; ++i) {
+        bool listed = c->p[i] > b;
+        for (int k = 0; k < 3 && !listed; ++k) {
+            const int n = c->nb_host[(size_t)k * S + i];
+            if (n >= 0 && c->p[n] > b) listed = true;
+        }
+        grp[listed ? 1 + c->p[i] : 0].push_back((int)i);
+    }
+    std::vector<int> order;
+    order.reserve(ne);
+    for (const auto &g : grp) order.insert(order.end(), g.begin(), g.end());
+    c->n_unlisted = (int64_t)grp[0].size();
+    c->grouped = true;
+    for (int64_t i = 0; i < ne; ++i)
+        if (order[i] != (int)i) return relayout(c, order);
+    return SWE_OK;
 }
 
 }  // namespace
@@ -838,56 +988,12 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t nv, const double *vxy, int64_t ne, c
     HIP_TRY(c, h2d(c, c->d_nb, nb.data(), sizeof(int) * 3 * S));
     HIP_TRY(c, h2d(c, c->d_nbk, nbk.data(), S));
     c->nb_host = nb;
-#ifndef SWE_SHARED_FLUX
-#define SWE_SHARED_FLUX 1
-#endif
-    if (SWE_SHARED_FLUX && stage_sh_supported(c->cfg.p_max, c->fp32)) {
-        // edge items per block of BLOCK elements, grouped by kind: pairs of
-        // elements of the block (once, from the lower index), neighbours
-        // outside the block, land edges, open edges
-        const int64_t nblk = (ne + BLOCK - 1) / BLOCK;
-        std::vector<unsigned> items;
-        std::vector<int> ioff((size_t)nblk + 1, 0);
-        items.reserve((size_t)ne * 2);
-        for (int64_t bi = 0; bi < nblk; ++bi) {
-            ioff[(size_t)bi] = (int)items.size();
-            const int64_t e0 = bi * BLOCK, e1 = std::min<int64_t>(e0 + BLOCK, ne);
-            for (unsigned kind = 0; kind < 4; ++kind)
-                for (int64_t ei = e0; ei < e1; ++ei)
-                    for (int k = 0; k < 3; ++k) {
-                        const int n = nb[(size_t)k * S + ei];
-                        unsigned kd;
-                        int lb = 0, kb = 0;
-                        if (n >= 0 && n / BLOCK == bi) {
-                            if (n < ei) continue;      // the pair is taken from the lower index
-                            kd = 0;
-                            lb = (int)(n - e0);
-                            kb = (nbk[ei] >> (2 * k)) & 3;
-                        } else if (n >= 0) {
-                            kd = 1;
-                        } else if (n == NB_LAND) {
-                            kd = 2;
-                        } else {
-                            kd = 3;
-                        }
-                        if (kd != kind) continue;
-                        items.push_back((unsigned)(ei - e0) | ((unsigned)k << 8) | ((unsigned)lb << 10) |
-                                        ((unsigned)kb << 18) | (kd << 20));
-                    }
-        }
-        ioff[(size_t)nblk] = (int)items.size();
-        // the kernel takes at most two items per lane; a block with more
-        // (a mesh ordering with long block boundaries) leaves the mesh to
-        // the element-gather kernel
-        int most = 0;
-        for (int64_t bi = 0; bi < nblk; ++bi) most = std::max(most, ioff[(size_t)bi + 1] - ioff[(size_t)bi]);
-        if (most <= 2 * BLOCK) {
-            HIP_TRY(c, hipMalloc(&c->d_items, sizeof(unsigned) * std::max<size_t>(items.size(), 1)));
-            HIP_TRY(c, hipMalloc(&c->d_item_off, sizeof(int) * ioff.size()));
-            if (!items.empty()) HIP_TRY(c, h2d(c, c->d_items, items.data(), sizeof(unsigned) * items.size()));
-            HIP_TRY(c, h2d(c, c->d_item_off, ioff.data(), sizeof(int) * ioff.size()));
-        }
-    }
+    c->nbk_host = nbk;
+    c->grouped = false;
+    c->n_unlisted = ne;
+    swe_status st0 = SWE_OK;
+    st0 = build_items(c);
+    if (st0) return st0;
     if (separated(c) || c->cfg.adapt) {
         const int KB = K_OF[c->cfg.p_base];
         HIP_TRY(c, hipMalloc(&c->d_inlist, S));
@@ -946,6 +1052,10 @@ swe_status swe_set_order(swe_ctx *c, const int8_t *p)
     swe_status st = swe_get_state(c, coef.data(), &t);
     if (st) return st;
     for (int64_t i = 0; i < c->ne; ++i) c->p[i] = p[c->e_perm[i]];
+    if (separated(c) && !c->cfg.adapt) {
+        st = group_by_lists(c);
+        if (st) return st;
+    }
     st = upload_order(c);
     if (st) return st;
     st = build_lists(c);

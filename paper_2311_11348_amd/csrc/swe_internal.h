@@ -70,6 +70,7 @@ struct StageArgs {
     int e_off;
     int stage;           // with inst: which stage time of the step (0 or 1) a kernel without MODE uses
     int skip_listed;     // base kernel of the order-partitioned scheme: listed elements are not its work
+    int blocks;          // stage launchers: cover the first blocks * BLOCK elements only (0: all)
 };
 
 struct InstDesc;

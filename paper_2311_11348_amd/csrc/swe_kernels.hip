@@ -1752,7 +1752,8 @@ hipError_t stage_p(int mode, const void *args, Sink &s)
 {
     StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
     if (a.m.ne <= 0) return hipSuccess;
-    const dim3 grid((a.m.ne + BLOCK - 1) / BLOCK), block(BLOCK);
+    const int nb = (a.m.ne + BLOCK - 1) / BLOCK;
+    const dim3 grid(a.blocks > 0 && a.blocks < nb ? a.blocks : nb), block(BLOCK);
     void *kargs[] = {&a};
     const void *fn = mode == MODE_RHS      ? reinterpret_cast<const void *>(&k_stage<P, Real, MODE_RHS, false>)
                      : mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_stage<P, Real, MODE_STAGE1, SEP>)
@@ -1836,7 +1837,8 @@ hipError_t stage_sh_p(int mode, const void *args, const unsigned *items, const i
     const void *fn = mode == MODE_RHS      ? reinterpret_cast<const void *>(&k_stage_sh<P, Real, MODE_RHS>)
                      : mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_stage_sh<P, Real, MODE_STAGE1>)
                                            : reinterpret_cast<const void *>(&k_stage_sh<P, Real, MODE_STAGE2>);
-    return emit(k, fn, dim3((a.m.ne + BLOCK - 1) / BLOCK), dim3(BLOCK), kargs);
+    const int nb = (a.m.ne + BLOCK - 1) / BLOCK;
+    return emit(k, fn, dim3(a.blocks > 0 && a.blocks < nb ? a.blocks : nb), dim3(BLOCK), kargs);
 }
 
 // Order 0 has too little work per edge for the sharing to pay for the LDS
