@@ -82,6 +82,7 @@ struct swe_ctx {
     // replayed step: one graph per step, clock (time, forcing) on the device
     unsigned *d_items = nullptr;           // edge items of the shared-flux stage kernel, per block
     int *d_item_off = nullptr;            // [blocks + 1]
+    int64_t item_blocks = 0;              // the leading blocks whose items are built
     InstDesc *d_inst = nullptr;
     hipGraph_t step_graph = nullptr, multi_graph = nullptr;   // one step; GRAPH_STEPS steps
     hipGraphExec_t step_exec = nullptr, multi_exec = nullptr;
@@ -189,6 +190,9 @@ MeshView view(const swe_ctx *c)
     return m;
 }
 
+// the edge items cover the first nblocks blocks (0: every block)
+bool items_cover(const swe_ctx *c, int64_t nblocks);
+
 template <typename Real>
 StageArgs<Real> make_args(const swe_ctx *c)
 {
@@ -268,7 +272,7 @@ hipError_t enqueue_stage(Lanes &L, int mode, int in, int out, double tstage, dou
     a.Uout = out >= 0 ? static_cast<Real *>(c->d_U[out]) : nullptr;
     a.Lout = static_cast<Real *>(Lout);
     L.time(a, mode == MODE_STAGE2 ? 1 : 0, tstage, dt);
-    if (c->d_items && !a.mixed)
+    if (items_cover(c, 0) && !a.mixed)
         return launch_stage_sh(c->cfg.p_max, c->fp32, mode, &a, c->d_items, c->d_item_off, L.a);
     return launch_stage(c->cfg.p_max, c->fp32, mode, false, &a, L.a);
 }
@@ -291,7 +295,7 @@ hipError_t launch_base(Lanes &L, int mode, StageArgs<Real> &a)
 {
     swe_ctx *c = L.c;
     const int b = c->cfg.p_base;
-    if (c->d_items && stage_sh_supported(b, c->fp32))
+    if (items_cover(c, a.blocks) && stage_sh_supported(b, c->fp32))
         return launch_stage_sh(b, c->fp32, mode, &a, c->d_items, c->d_item_off, L.a);
     return launch_stage(b, c->fp32, mode, true, &a, L.a);
 }
@@ -610,14 +614,18 @@ hipError_t enqueue_rhs_split(swe_ctx *c, double t)
 #define SWE_SHARED_FLUX 1
 #endif
 // Edge items of the shared-flux stage kernel for the current numbering
-// (replacing any built before); none when a block would hold more than the
-// kernel takes.
+// (replacing any built before), for every block; or, when some block would
+// hold more than the kernel takes, for the blocks of unlisted elements of a
+// grouped numbering (the base pass of the partitioned scheme needs no more:
+// listed elements of one order are seldom neighbours of each other, so their
+// blocks hold many edges to outside); else none.
 swe_status build_items(swe_ctx *c)
 {
     if (c->d_items) (void)hipFree(c->d_items);
     if (c->d_item_off) (void)hipFree(c->d_item_off);
     c->d_items = nullptr;
     c->d_item_off = nullptr;
+    c->item_blocks = 0;
     if (SWE_SHARED_FLUX && stage_sh_supported(c->cfg.p_max, c->fp32)) {
         const int64_t ne = c->ne;
         const int S = c->stride;
@@ -658,16 +666,31 @@ swe_status build_items(swe_ctx *c)
         // the kernel takes at most two items per lane; a block with more
         // (a mesh ordering with long block boundaries) leaves the mesh to
         // the element-gather kernel
-        int most = 0;
-        for (int64_t bi = 0; bi < nblk; ++bi) most = std::max(most, ioff[(size_t)bi + 1] - ioff[(size_t)bi]);
-        if (most <= 2 * BLOCK) {
+        int64_t cover = 0;
+        while (cover < nblk && ioff[(size_t)cover + 1] - ioff[(size_t)cover] <= 2 * BLOCK) ++cover;
+        if (cover < nblk && c->grouped && cover >= (c->n_unlisted + BLOCK - 1) / BLOCK) {
+            cover = (c->n_unlisted + BLOCK - 1) / BLOCK;
+            items.resize((size_t)ioff[(size_t)cover]);
+            for (int64_t bi = cover + 1; bi <= nblk; ++bi) ioff[(size_t)bi] = (int)items.size();
+        } else if (cover < nblk) {
+            cover = 0;
+        }
+        if (cover > 0) {
             HIP_TRY(c, hipMalloc(&c->d_items, sizeof(unsigned) * std::max<size_t>(items.size(), 1)));
             HIP_TRY(c, hipMalloc(&c->d_item_off, sizeof(int) * ioff.size()));
             if (!items.empty()) HIP_TRY(c, h2d(c, c->d_items, items.data(), sizeof(unsigned) * items.size()));
             HIP_TRY(c, h2d(c, c->d_item_off, ioff.data(), sizeof(int) * ioff.size()));
+            c->item_blocks = cover;
         }
     }
     return SWE_OK;
+}
+
+// The edge items cover the first nblocks blocks (0: every block).
+bool items_cover(const swe_ctx *c, int64_t nblocks)
+{
+    const int64_t all = (c->ne + BLOCK - 1) / BLOCK;
+    return c->d_items && c->item_blocks >= (nblocks > 0 ? std::min(nblocks, all) : all);
 }
 
 // Renumber the elements: new internal index i is the element at old index
@@ -1822,8 +1845,8 @@ swe_status swe_batch_admit(swe_batch *b, swe_ctx *c, int64_t nsteps, double dt, 
                                  w * c->ne, 2 * K, hipMemcpyDeviceToDevice, b->s));
     BHIP_TRY(b, hipMemcpyAsync(b->d_vtx + vbase, c->d_vtx, sizeof(double4) * c->nv, hipMemcpyDeviceToDevice, b->s));
     BHIP_TRY(b, launch_relocate(c->d_ev, c->d_nb, c->d_nbk, (int)c->ne, c->stride, P.v, (int)first, (int)vbase, b->s));
-    const bool no_items = P.v.items != nullptr && c->d_items == nullptr;
-    if (P.v.items && c->d_items)
+    const bool no_items = P.v.items != nullptr && !items_cover(c, 0);
+    if (P.v.items && items_cover(c, 0))
         BHIP_TRY(b, launch_place_items(c->d_items, c->d_item_off, (int)((c->ne + BLOCK - 1) / BLOCK), P.v, (int)first,
                                        b->s));
     InstDesc &d = b->h_inst[i];

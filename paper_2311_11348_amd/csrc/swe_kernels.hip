@@ -1259,7 +1259,7 @@ k_batch_stage(BatchArgs b)
     const int lo = (int)(((long long)ntiles * x) >> 3), hi = (int)(((long long)ntiles * (x + 1)) >> 3);
     const int t = lo + i;
     if (t >= hi) return;
-    StageArgs<Real> a;
+    StageArgs<Real> a{};   // every field not set below is zero / null (no lists, no skipping)
     a.m.ne = 0;
     a.m.stride = b.pool.cap;
     a.m.KS = K;
@@ -1305,7 +1305,7 @@ k_batch_stage_sh(BatchArgs b)
     const int2 tile = b.tiles[t];
     const InstDesc &I = b.inst[tile.x];
     if (!I.run) return;
-    StageArgs<Real> a;
+    StageArgs<Real> a{};   // every field not set below is zero / null (no lists, no skipping)
     a.m.ne = 0;
     a.m.stride = b.pool.cap;
     a.m.KS = Ord<P>::K;
