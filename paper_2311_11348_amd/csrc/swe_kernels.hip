@@ -1140,12 +1140,13 @@ template <int P, typename Real, int MODE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sh_waves<P, Real>(), 8)))
 k_stage_sh(StageArgs<Real> a, const unsigned *items, const int *item_off)
 {
-    if (a.inst && !a.inst->run) return;   // the step's clock stopped (failure): the whole block leaves
     __shared__ ShLds<P, Real> S;
     load_trace_lds<P, Real>(S);
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     double xihat = a.xihat, dt = a.dt;
     if (a.inst) {
+        // the step's clock stopped (failure): the whole block leaves before its first barrier
+        if (!a.inst->run) return;
         xihat = MODE == MODE_STAGE2 ? a.inst->xh[1] : a.inst->xh[0];
         dt = a.inst->dt;
     }
@@ -1415,7 +1416,6 @@ template <int PN, typename Real, int MODE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<PN, Real>(), 8)))
 k_full_all(StageArgs<Real> a, int lo, int nblk, int lcap)
 {
-    if (a.inst && !a.inst->run) return;   // the step's clock stopped (failure)
     // beside the base kernel over all elements, these end the stage: their
     // waves issue first on a shared SIMD
     __builtin_amdgcn_s_setprio(2);
@@ -1428,6 +1428,7 @@ k_full_all(StageArgs<Real> a, int lo, int nblk, int lcap)
     const unsigned e = (unsigned)a.list[(size_t)p * (size_t)lcap + (size_t)i];
     double xihat = a.xihat, dt = a.dt;
     if (a.inst) {
+        if (!a.inst->run) return;   // the step's clock stopped (failure)
         xihat = MODE == MODE_STAGE2 ? a.inst->xh[1] : a.inst->xh[0];
         dt = a.inst->dt;
     }
@@ -1490,7 +1491,6 @@ template <int B, int PN, typename Real>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<PN, Real>(), 8)))
 k_corr_all(StageArgs<Real> a, double dt, int nblk, int lcap)
 {
-    if (a.inst && !a.inst->run) return;   // the step's clock stopped (failure)
     __builtin_amdgcn_s_setprio(2);   // as in k_full_all
     constexpr int KB = Ord<B>::K, NTB = Ord<B>::NT;
     constexpr int KN = Ord<PN>::K, NX = PN + 1;
@@ -1505,6 +1505,7 @@ k_corr_all(StageArgs<Real> a, double dt, int nblk, int lcap)
     double xihat = a.xihat;
     if (a.inst) {
         // the clock of a replayed step lives on the device
+        if (!a.inst->run) return;   // the step's clock stopped (failure)
         xihat = a.inst->xh[a.stage];
         dt = a.inst->dt;
     }
@@ -1545,10 +1546,10 @@ template <int PN, typename Real, int MODE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
 k_epi_all(StageArgs<Real> a, int KB, int lo, int nblk, int lcap)
 {
-    if (a.inst && !a.inst->run) return;   // the step's clock stopped (failure)
     const int p = list_order(lo, nblk), i = list_entry(nblk);
     if (p > PN || i >= a.count[p]) return;
     const unsigned e = (unsigned)a.list[(size_t)p * (size_t)lcap + (size_t)i];
+    if (a.inst && !a.inst->run) return;   // the step's clock stopped (failure)
     switch (p) {
     case 0: epi_element<0, Real, MODE>(a, e, KB); break;
     case 1: if constexpr (PN >= 1) epi_element<1, Real, MODE>(a, e, KB); break;
