@@ -353,7 +353,21 @@ hipError_t enqueue_separated(Lanes &L, int mode, int in, int out, double tstage,
     a.Lc = static_cast<Real *>(c->d_Lc);
     hipError_t e = L.fork();
     if (e != hipSuccess) return e;
-    e = launch_base<Real>(L, mode, a);
+    const int64_t nbu = (c->n_unlisted + BLOCK - 1) / BLOCK, off = nbu * BLOCK;
+    if (c->grouped && nbu > 0 && off < c->ne && stage_sh_supported(b, c->fp32) && items_cover(c, nbu)) {
+        // grouped numbering whose listed blocks the shared-flux kernel cannot
+        // take: the unlisted blocks on it, the listed range on the gather kernel
+        a.blocks = (int)nbu;
+        e = launch_base<Real>(L, mode, a);
+        a.blocks = 0;
+        if (e != hipSuccess) return e;
+        StageArgs<Real> r = a;
+        r.e_off = (int)off;
+        r.m.ne = (int)(c->ne - off);
+        e = launch_stage(b, c->fp32, mode, true, &r, L.a);
+    } else {
+        e = launch_base<Real>(L, mode, a);
+    }
     if (e != hipSuccess) return e;
     // the corrections of every order in one launch on branch B, then (after
     // the join) the epilogues of every order in one launch
