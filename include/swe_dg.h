@@ -111,7 +111,13 @@ swe_status swe_set_bathymetry(swe_ctx *ctx, const double *hb_vertex);
 
 /* Per-element polynomial order p[ne] in [p_base, p_max].  Modes above the new
  * K(p_e) are dropped from the state (the L2 projection, the basis being
- * hierarchical and orthonormal); new modes start at zero. */
+ * hierarchical and orthonormal); new modes start at zero.  In a separated,
+ * non-adaptive context (a static order map) the library also renumbers its
+ * device storage of the elements (elements without a correction first, then
+ * those with one, by order) so that each order's list is contiguous; this
+ * costs host time linear in ne and a rebuild of the step graphs, keeps the
+ * source term of swe_set_source, and changes nothing at the interface (every
+ * array in and out stays in the caller's element order). */
 swe_status swe_set_order(swe_ctx *ctx, const int8_t *p);
 swe_status swe_get_order(swe_ctx *ctx, int8_t *p_out);
 
