@@ -287,17 +287,32 @@ hipError_t enqueue_stage(swe_ctx *c, int mode, int in, int out, double tstage, d
 
 bool separated(const swe_ctx *c) { return c->cfg.separate && c->cfg.p_base < c->cfg.p_max; }
 
-// Base pass of the order-separated and order-partitioned schemes: the
-// shared-flux kernel at the base order where there is one (edge items built,
-// base order 1..3), else the element-gather kernel.
+// Base pass of the order-separated and order-partitioned schemes over the
+// elements [0, end): the shared-flux kernel at the base order (orders 1..3)
+// on the leading blocks that have edge items, the element-gather kernel on
+// the rest of the range (all of it without items).
 template <typename Real>
-hipError_t launch_base(Lanes &L, int mode, StageArgs<Real> &a)
+hipError_t launch_base(Lanes &L, int mode, StageArgs<Real> &a, int64_t end)
 {
     swe_ctx *c = L.c;
     const int b = c->cfg.p_base;
-    if (items_cover(c, a.blocks) && stage_sh_supported(b, c->fp32))
-        return launch_stage_sh(b, c->fp32, mode, &a, c->d_items, c->d_item_off, L.a);
-    return launch_stage(b, c->fp32, mode, true, &a, L.a);
+    const int64_t all = (c->ne + BLOCK - 1) / BLOCK, nb_end = (end + BLOCK - 1) / BLOCK;
+    const int64_t cov = (c->d_items && stage_sh_supported(b, c->fp32)) ? std::min(c->item_blocks, nb_end) : 0;
+    hipError_t e = hipSuccess;
+    if (cov > 0) {
+        a.blocks = cov < all ? (int)cov : 0;
+        e = launch_stage_sh(b, c->fp32, mode, &a, c->d_items, c->d_item_off, L.a);
+        a.blocks = 0;
+        if (e != hipSuccess) return e;
+    }
+    const int64_t off = cov * BLOCK;
+    if (off < end) {
+        StageArgs<Real> r = a;
+        r.e_off = (int)off;
+        r.m.ne = (int)(end - off);
+        e = launch_stage(b, c->fp32, mode, true, &r, L.a);
+    }
+    return e;
 }
 
 // Blocks per order of a one-launch list kernel (every order's list fits):
@@ -353,21 +368,8 @@ hipError_t enqueue_separated(Lanes &L, int mode, int in, int out, double tstage,
     a.Lc = static_cast<Real *>(c->d_Lc);
     hipError_t e = L.fork();
     if (e != hipSuccess) return e;
-    const int64_t nbu = (c->n_unlisted + BLOCK - 1) / BLOCK, off = nbu * BLOCK;
-    if (c->grouped && nbu > 0 && off < c->ne && stage_sh_supported(b, c->fp32) && items_cover(c, nbu)) {
-        // grouped numbering whose listed blocks the shared-flux kernel cannot
-        // take: the unlisted blocks on it, the listed range on the gather kernel
-        a.blocks = (int)nbu;
-        e = launch_base<Real>(L, mode, a);
-        a.blocks = 0;
-        if (e != hipSuccess) return e;
-        StageArgs<Real> r = a;
-        r.e_off = (int)off;
-        r.m.ne = (int)(c->ne - off);
-        e = launch_stage(b, c->fp32, mode, true, &r, L.a);
-    } else {
-        e = launch_base<Real>(L, mode, a);
-    }
+    // every element: a listed one leaves its base part in Lb for the epilogue
+    e = launch_base<Real>(L, mode, a, c->ne);
     if (e != hipSuccess) return e;
     // the corrections of every order in one launch on branch B, then (after
     // the join) the epilogues of every order in one launch
@@ -403,13 +405,9 @@ hipError_t enqueue_partitioned(Lanes &L, int mode, int in, int out, double tstag
     hipError_t e = L.fork();
     if (e != hipSuccess) return e;
     // with the elements grouped (static order map) the unlisted ones are the
-    // first n_unlisted: the base kernel covers their blocks only
-    if (!c->grouped || c->n_unlisted > 0) {
-        a.blocks = c->grouped ? (int)((c->n_unlisted + BLOCK - 1) / BLOCK) : 0;
-        e = launch_base<Real>(L, mode, a);
-        if (e != hipSuccess) return e;
-        a.blocks = 0;
-    }
+    // first n_unlisted: the base pass covers them only
+    e = launch_base<Real>(L, mode, a, c->grouped ? c->n_unlisted : c->ne);
+    if (e != hipSuccess) return e;
     // the listed elements of every order in one launch on branch B
     a.skip_listed = 0;
     a.list = c->d_list;
@@ -680,14 +678,15 @@ swe_status build_items(swe_ctx *c)
         // the kernel takes at most two items per lane; a block with more
         // (a mesh ordering with long block boundaries) leaves the mesh to
         // the element-gather kernel
+        // the leading blocks that fit; of a grouped numbering only those of
+        // unlisted elements are worth keeping (the base pass takes the rest
+        // of its range on the gather kernel), else all blocks or none
         int64_t cover = 0;
         while (cover < nblk && ioff[(size_t)cover + 1] - ioff[(size_t)cover] <= 2 * BLOCK) ++cover;
-        if (cover < nblk && c->grouped && cover >= (c->n_unlisted + BLOCK - 1) / BLOCK) {
-            cover = (c->n_unlisted + BLOCK - 1) / BLOCK;
+        if (cover < nblk) {
+            cover = c->grouped ? std::min<int64_t>(cover, (c->n_unlisted + BLOCK - 1) / BLOCK) : 0;
             items.resize((size_t)ioff[(size_t)cover]);
             for (int64_t bi = cover + 1; bi <= nblk; ++bi) ioff[(size_t)bi] = (int)items.size();
-        } else if (cover < nblk) {
-            cover = 0;
         }
         if (cover > 0) {
             HIP_TRY(c, hipMalloc(&c->d_items, sizeof(unsigned) * std::max<size_t>(items.size(), 1)));
@@ -762,19 +761,40 @@ swe_status group_by_lists(swe_ctx *c)
 {
     const int b = c->cfg.p_base, S = c->stride;
     const int64_t ne = c->ne;
-    std::vector<std::vector<int>> grp(5);
+    std::vector<unsigned char> listed(ne, 0);
     for (int64_t i = 0; i < ne; ++i) {
-        bool listed = c->p[i] > b;
-        for (int k = 0; k < 3 && !listed; ++k) {
+        bool l = c->p[i] > b;
+        for (int k = 0; k < 3 && !l; ++k) {
             const int n = c->nb_host[(size_t)k * S + i];
-            if (n >= 0 && c->p[n] > b) listed = true;
+            if (n >= 0 && c->p[n] > b) l = true;
         }
-        grp[listed ? 1 + c->p[i] : 0].push_back((int)i);
+        listed[i] = l ? 1 : 0;
+    }
+    // groups: unlisted elements, then the listed elements of each order.
+    // For the order-separated scheme the unlisted neighbours of listed
+    // elements (which its corrections gather) form a group of their own just
+    // before the lists, in the lists' order, so that consecutive lanes share
+    // cache lines; its base pass takes that group on the gather kernel.  The
+    // partitioned scheme keeps them in the first group (measured faster: its
+    // base pass then stays one shared-flux launch).
+    const bool halo_group = c->cfg.separate == 1;
+    std::vector<std::vector<int>> grp(6);
+    for (int64_t i = 0; i < ne; ++i) {
+        if (listed[i]) {
+            grp[2 + c->p[i]].push_back((int)i);
+            continue;
+        }
+        bool halo = false;
+        for (int k = 0; k < 3 && halo_group && !halo; ++k) {
+            const int n = c->nb_host[(size_t)k * S + i];
+            if (n >= 0 && listed[n]) halo = true;
+        }
+        grp[halo ? 1 : 0].push_back((int)i);
     }
     std::vector<int> order;
     order.reserve(ne);
     for (const auto &g : grp) order.insert(order.end(), g.begin(), g.end());
-    c->n_unlisted = (int64_t)grp[0].size();
+    c->n_unlisted = (int64_t)(grp[0].size() + grp[1].size());
     c->grouped = true;
     for (int64_t i = 0; i < ne; ++i)
         if (order[i] != (int)i) return relayout(c, order);
