@@ -79,3 +79,29 @@ def test_dambreak_full_size_static32_p12():
     err, err_inc = rel(got, ref), rel(got - before, ref - c0)
     say(f"  rel L2 {err:.2e}, increment {err_inc:.2e} (increment / state {rel(ref, c0):.1e})")
     assert err < 1e-12 and err_inc < 1e-9
+
+
+@pytest.mark.parametrize("separate", [1, 2])
+@pytest.mark.parametrize("precision", [swe.SWE_FP64, swe.SWE_FP32_WB])
+def test_dambreak_full_size_mass(precision, separate):
+    """Walls on every side: the FP64 mass of the full dam break (static 1/32
+    p1-2, renumbered for its order map) is conserved by 20 steps of the CFL
+    step, to a few roundings of each element's mean elevation per stage in
+    the working precision (4 units of 2^-52 FP64, 2^-23 FP32, per element
+    and stage)."""
+    prob = I.config_dambreak(n=1024, p_lo=1, p_hi=2, every=32, dt_fixed=None)
+    sa = np.sqrt(prob.mesh.areas())
+    steps = 20
+    with swe.context_for(prob, precision=precision, separate=separate) as ctx:
+        ctx.set_state_fn(prob.ic)
+        m0 = ctx.mass()
+        c0, _ = ctx.state()
+        ctx.step(steps, prob.dt())
+        ctx.sync()
+        m1 = ctx.mass()
+    eps = 2.0 ** -52 if precision == swe.SWE_FP64 else 2.0 ** -23
+    scale = float(np.sum(np.abs(c0[:, 0, 0]) * sa))
+    bound = 4 * eps * 2 * steps * scale
+    say(f"dambreak mass precision={precision} separate={separate}: |dM| {abs(m1 - m0):.3e}, bound {bound:.3e} "
+        f"(relative {abs(m1 - m0) / abs(m0):.2e})")
+    assert abs(m1 - m0) <= bound
