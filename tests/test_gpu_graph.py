@@ -74,3 +74,21 @@ def test_graph_equals_launches(name, precision):
     err = np.linalg.norm(cg - cl) / np.linalg.norm(cl)
     say(f"{name} precision={precision}: graph vs launches rel L2 {err:.2e}, equal={np.array_equal(cg, cl)}")
     assert err < (1e-13 if precision == swe.SWE_FP64 else 1e-6)
+
+
+@pytest.mark.parametrize("name", ["tsunami", "static-partitioned", "tsunami-open"])
+def test_long_call_equals_launches(name):
+    """A long call (many replays of the multi-step graph and a remainder of
+    single-step replays): 76 steps in calls of 1, 70 and 5 against launches
+    (FP64)."""
+    prob, separate = cases()[name]
+    orc = Oracle.from_problem(prob)
+    c0 = orc.project(prob.ic)
+    dt = prob.dt()
+    cg, tg, pg = run(prob, c0, 76, dt, swe.SWE_FP64, separate, 2, chunks=(1, 70))
+    cl, tl, pl = run(prob, c0, 76, dt, swe.SWE_FP64, separate, 0, chunks=(1, 70))
+    assert tg == tl
+    assert np.array_equal(pg, pl)
+    err = np.linalg.norm(cg - cl) / np.linalg.norm(cl)
+    say(f"{name} long call, graph vs launches rel L2 {err:.2e}")
+    assert err < 1e-13
