@@ -20,9 +20,10 @@ dambreak: the paper's radial dam break on 1024x1024x2 = 2,097,152 jittered
   triangles of [0,5]^2 (g = 1, h_b = 0.5 m, walls, linear friction), 100
   steps of 1e-5 s as in its static runs: uniform p0, p1, p2 (fused kernel)
   and every 32nd element at the higher order (p0-1, p1-2; order-partitioned
-  and order-separated), FP64 and FP32, each beside the paper's own time per
-  stage on its hardware (context).  The value is static 1/32 p1-2,
-  order-partitioned, FP64.
+  and order-separated), then dynamic orders (this library's indicator,
+  threshold 1e-2 m, the CFL step, 400 steps), FP64 and FP32, each beside the
+  paper's own time per stage on its hardware (context).  The value is static
+  1/32 p1-2, order-partitioned, FP64.
 batched: 64 independent instances (seeds 4000+i), log-uniform 16k-500k
   elements, p in {1,2,3}, tidal or hump, random smooth bathymetry, 300 steps
   each; FP32 and FP64 batched against the plain FP64 solver run one instance
@@ -236,7 +237,17 @@ DAMBREAK_PAPER_MS = {
     "p1-2 1/32": {"ARM-AGX CPU unseparated": 517.70, "ARM-AGX GPU separated": 714.25,
                   "ARM-AGX CPU+GPU separated": 460.01, "AMD-RTX CPU separated": 68.05,
                   "AMD-RTX GPU separated": 72.39, "AMD-RTX CPU+GPU separated": 222.2},
+    # dynamic runs: averaged over 12,500 steps, with the paper's own indicator
+    # (about 1/482 and 1/172 of the elements at the higher order)
+    "p0-1 dynamic": {"ARM-AGX GPU unseparated": 59.80, "ARM-AGX GPU separated": 74.44,
+                     "ARM-AGX CPU+GPU separated": 88.1, "ARM-AGX CPU unseparated": 110.92,
+                     "ARM-AGX CPU separated": 123.94},
+    "p1-2 dynamic": {"ARM-AGX GPU unseparated": 270.92, "ARM-AGX GPU separated": 310.16,
+                     "ARM-AGX CPU+GPU separated": 292.7, "ARM-AGX CPU unseparated": 416.16,
+                     "ARM-AGX CPU separated": 432.64},
 }
+DAMBREAK_TAU = 1e-2     # indicator threshold (m) of the dynamic setups
+DAMBREAK_DYN_STEPS = 400
 
 
 def run_dambreak(steps, warmup, n=1024):
@@ -262,6 +273,20 @@ def run_dambreak(steps, warmup, n=1024):
                 for sep, scheme in ((2, "partitioned"), (1, "separated")):
                     r = run_separated(prob, prec, steps, warmup, separate=sep)
                     row[f"{tag}_{scheme}"] = {"ms_per_stage": r["ms_per_step"] / 2, "value": r["value"]}
+        row["paper_ms_per_stage"] = DAMBREAK_PAPER_MS[name]
+        out[name] = row
+    # dynamic orders: this library's indicator (threshold DAMBREAK_TAU), the
+    # CFL step, DAMBREAK_DYN_STEPS timed steps from the start of the run
+    for name, lo, hi in (("p0-1 dynamic", 0, 1), ("p1-2 dynamic", 1, 2)):
+        prob = I.config_dambreak(n=n, p_lo=lo, p_hi=hi, dt_fixed=None, adapt_tau=DAMBREAK_TAU)
+        row = {"tau_m": DAMBREAK_TAU, "dt_s": prob.dt(), "timed_steps": DAMBREAK_DYN_STEPS}
+        for prec, tag in ((swe.SWE_FP64, "fp64"), (swe.SWE_FP32_WB, "fp32")):
+            for sep, scheme in ((2, "partitioned"), (1, "separated")):
+                print(f"bench: dambreak {name} {tag} {scheme} ({prob.mesh.ne} elements)", file=sys.stderr,
+                      flush=True)
+                r = run_separated(prob, prec, DAMBREAK_DYN_STEPS, warmup, separate=sep)
+                row[f"{tag}_{scheme}"] = {"ms_per_stage": r["ms_per_step"] / 2, "value": r["value"],
+                                         "order_fractions": r["order_fractions"]}
         row["paper_ms_per_stage"] = DAMBREAK_PAPER_MS[name]
         out[name] = row
     return out

@@ -295,7 +295,7 @@ DAMBREAK_DT = 1.0e-5
 
 
 def config_dambreak(n: int = 1024, p_lo: int = 1, p_hi: int = 2, every: int = 32, seed: int = 6,
-                    dt_fixed: Optional[float] = DAMBREAK_DT) -> Problem:
+                    dt_fixed: Optional[float] = DAMBREAK_DT, adapt_tau: Optional[float] = None) -> Problem:
     """Radial dam break of Sec. "Radial dam break" with the physical values of
     its table of physical quantities: [0,5]^2, g = 1, constant bathymetry
     0.5 m, walls on every side, Coriolis 1e-5 1/s, linear friction
@@ -306,15 +306,18 @@ def config_dambreak(n: int = 1024, p_lo: int = 1, p_hi: int = 2, every: int = 32
     ``every``-th element in mesh order (the statically adaptive setups;
     every = 1 gives uniform p_hi, every = 0 uniform p_lo), base order p_lo.
     Time step: the static runs' 1e-5 s unless ``dt_fixed`` is None (then the
-    CFL rule)."""
+    CFL rule).  With ``adapt_tau`` the orders are dynamic instead (the
+    dynamic runs): every element starts at p_lo and the order update before
+    each step sets p_lo..p_hi from the indicator with threshold adapt_tau."""
     mesh = structured_mesh(n, length=DAMBREAK_LENGTH, jitter=0.2, seed=seed)
     p = np.full(mesh.ne, p_lo, np.int8)
-    if every > 0:
+    if adapt_tau is None and every > 0:
         p[::every] = p_hi
-    p_max = int(p.max())
+    p_max = int(p.max()) if adapt_tau is None else p_hi
     return _problem(f"dambreak{n}", mesh, bathy_flat(0.5), ic_dambreak(), p, min(p_lo, p_max), p_max, g=1.0,
                     f_coriolis=1.0e-5, friction=FRICTION_LINEAR, friction_coef=1.0e-4, steps=100,
-                    dt_fixed=dt_fixed)
+                    dt_fixed=dt_fixed, adapt=0 if adapt_tau is None else 1,
+                    adapt_tau=1e-3 if adapt_tau is None else adapt_tau)
 
 
 def instance_mesh_n(n_elements: float) -> int:

@@ -105,3 +105,36 @@ def test_dambreak_full_size_mass(precision, separate):
     say(f"dambreak mass precision={precision} separate={separate}: |dM| {abs(m1 - m0):.3e}, bound {bound:.3e} "
         f"(relative {abs(m1 - m0) / abs(m0):.2e})")
     assert abs(m1 - m0) <= bound
+
+
+@pytest.mark.parametrize("lo,hi", [(0, 1), (1, 2)])
+@pytest.mark.parametrize("separate", [1, 2])
+def test_dambreak_dynamic_small_matches_oracle(lo, hi, separate):
+    """Dynamic orders (the indicator with threshold 1e-2 m before every step)
+    on 32x32x2: order maps identical to the oracle's adaptive run, state
+    within 1e-12 after 12 steps (FP64)."""
+    tau = 1e-2
+    prob = I.config_dambreak(n=32, p_lo=lo, p_hi=hi, dt_fixed=None, adapt_tau=tau)
+    orc = Oracle.from_problem(prob)
+    c0 = orc.project(prob.ic)
+    dt, steps = prob.dt(), 12
+    ref = c0
+    for s in range(steps):
+        ind = orc.indicator(s * dt, ref)
+        for k in range(hi - lo):
+            thr = tau / 10 ** k
+            assert np.min(np.abs(ind - thr)) / thr > 1e-9   # no decision within rounding of a threshold
+        ref = orc.step(ref, 1, dt, t0=s * dt, adapt=True, tau=tau, p_lo=lo, p_hi=hi)
+    pref = orc.order()
+    with swe.context_for(prob, separate=separate) as ctx:
+        ctx.set_state(c0)
+        ctx.step(steps, dt)
+        ctx.sync()
+        got, _ = ctx.state()
+        pgot = ctx.order()
+    err = rel(got, ref)
+    say(f"dambreak dynamic p{lo}-{hi} separate={separate}: {int((pref == hi).sum())} of {prob.mesh.ne} at p{hi}, "
+        f"maps equal {np.array_equal(pgot, pref)}, rel L2 {err:.2e}")
+    assert (pref == hi).sum() > 0
+    assert np.array_equal(pgot, pref)
+    assert err < 1e-12
