@@ -126,7 +126,10 @@ swe_status swe_set_open_boundary(swe_ctx *ctx, int ncon, const double *amp,
                                  const double *omega, const double *phase);
 
 /* State at time t0 from host coefficients coef[ne][3][K(p_max)] (physical
- * orthonormal basis, caller's element order). */
+ * orthonormal basis, caller's element order).  Modes above each element's
+ * current order are ignored; the current order is the one set by
+ * swe_set_order or, in an adaptive context, the one the last order update on
+ * the device chose (read back by this call, as by swe_get_order). */
 swe_status swe_set_state(swe_ctx *ctx, double t0, const double *coef);
 
 /* Input preparation: xy_out[ne][SWE_NQP][2] receives the physical points of

@@ -531,9 +531,22 @@ hipError_t usolve_buf(swe_ctx *c, int buf)
     return c->fp32 ? enqueue_usolve<float>(c, buf) : enqueue_usolve<double>(c, buf);
 }
 
-// host [elem][3][K] physical -> device SoA reference-scaled (buffer buf)
+// The host copy of the element orders.  An adaptive context changes its
+// orders on the device every step; whatever truncates or projects a state
+// to each element's order reads them back first.
+swe_status refresh_orders(swe_ctx *c)
+{
+    if (!c->cfg.adapt || !c->d_p) return SWE_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    HIP_TRY(c, d2h(c, c->p.data(), c->d_p, c->ne));
+    return SWE_OK;
+}
+
+// host [elem][3][K] physical -> device SoA reference-scaled (buffer buf);
+// modes above each element's current order are dropped
 swe_status upload_state(swe_ctx *c, const double *coef, void *dst)
 {
+    if (swe_status st = refresh_orders(c)) return st;
     const int K = c->K, S = c->stride;
     const size_t n = (size_t)3 * K * S;
     std::vector<double> h(n, 0.0);
@@ -1124,11 +1137,7 @@ swe_status swe_get_order(swe_ctx *c, int8_t *p)
 {
     if (!c || !p) return SWE_EINVAL;
     if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
-    if (c->cfg.adapt) {
-        // orders change on the device every step
-        HIP_TRY(c, hipStreamSynchronize(c->s_base));
-        HIP_TRY(c, d2h(c, c->p.data(), c->d_p, c->ne));
-    }
+    if (swe_status st = refresh_orders(c)) return st;   // orders change on the device every step
     for (int64_t i = 0; i < c->ne; ++i) p[c->e_perm[i]] = c->p[i];
     return SWE_OK;
 }
@@ -1187,6 +1196,7 @@ swe_status swe_set_state_points(swe_ctx *c, double t0, const double *vals)
 {
     if (!c || !vals) return SWE_EINVAL;
     if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    if (swe_status st = refresh_orders(c)) return st;
     const int K = c->K;
     std::vector<double> coef((size_t)c->ne * 3 * K, 0.0);
     for (int64_t i = 0; i < c->ne; ++i) {

@@ -1390,6 +1390,19 @@ __global__ void __launch_bounds__(BLOCK) k_batch_clock(InstDesc *inst, const int
 __device__ __forceinline__ int list_order(int lo, int nblk) { return lo + (int)blockIdx.x / nblk; }
 __device__ __forceinline__ int list_entry(int nblk) { return ((int)blockIdx.x % nblk) * BLOCK + (int)threadIdx.x; }
 
+// Element of entry i of order p's list, or -1 past the list's end.  The
+// count is capped at the list's capacity and an entry outside the mesh is
+// skipped, so a list is only ever read within its allocation and an entry is
+// only ever followed into the element arrays.
+template <typename Real>
+__device__ __forceinline__ int list_element(const StageArgs<Real> &a, int p, int i, int lcap)
+{
+    const int n = a.count[p];
+    if (i >= (n < lcap ? n : lcap)) return -1;
+    const int e = a.list[(size_t)p * (size_t)lcap + (size_t)i];
+    return (e >= 0 && e < a.m.ne) ? e : -1;
+}
+
 // full stage of listed element e of order P (order-partitioned scheme)
 template <int P, int PN, typename Real, int MODE>
 __device__ __forceinline__ void full_element(const StageArgs<Real> &a, unsigned e,
@@ -1423,9 +1436,11 @@ k_full_all(StageArgs<Real> a, int lo, int nblk, int lcap)
     __shared__ Real sR[3][KN][NX];
     load_trace_table<KN, NX, Real>(sR);
     __syncthreads();
-    const int p = list_order(lo, nblk), i = list_entry(nblk);
-    if (p > PN || i >= a.count[p]) return;
-    const unsigned e = (unsigned)a.list[(size_t)p * (size_t)lcap + (size_t)i];
+    const int p = list_order(lo, nblk);
+    if (p > PN) return;
+    const int le = list_element(a, p, list_entry(nblk), lcap);
+    if (le < 0) return;
+    const unsigned e = (unsigned)le;
     double xihat = a.xihat, dt = a.dt;
     if (a.inst) {
         if (!a.inst->run) return;   // the step's clock stopped (failure)
@@ -1499,9 +1514,11 @@ k_corr_all(StageArgs<Real> a, double dt, int nblk, int lcap)
     load_trace_table<KN, NX, Real>(sR);
     load_trace_table<KB, NTB, Real>(sRb);
     __syncthreads();
-    const int p = list_order(B, nblk), i = list_entry(nblk);
-    if (p > PN || i >= a.count[p]) return;
-    const unsigned e = (unsigned)a.list[(size_t)p * (size_t)lcap + (size_t)i];
+    const int p = list_order(B, nblk);
+    if (p > PN) return;
+    const int le = list_element(a, p, list_entry(nblk), lcap);
+    if (le < 0) return;
+    const unsigned e = (unsigned)le;
     double xihat = a.xihat;
     if (a.inst) {
         // the clock of a replayed step lives on the device
@@ -1546,9 +1563,11 @@ template <int PN, typename Real, int MODE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
 k_epi_all(StageArgs<Real> a, int KB, int lo, int nblk, int lcap)
 {
-    const int p = list_order(lo, nblk), i = list_entry(nblk);
-    if (p > PN || i >= a.count[p]) return;
-    const unsigned e = (unsigned)a.list[(size_t)p * (size_t)lcap + (size_t)i];
+    const int p = list_order(lo, nblk);
+    if (p > PN) return;
+    const int le = list_element(a, p, list_entry(nblk), lcap);
+    if (le < 0) return;
+    const unsigned e = (unsigned)le;
     if (a.inst && !a.inst->run) return;   // the step's clock stopped (failure)
     switch (p) {
     case 0: epi_element<0, Real, MODE>(a, e, KB); break;
@@ -1678,8 +1697,9 @@ __global__ void __launch_bounds__(BLOCK) k_apply_order(StageArgs<Real> a, const 
         if (lane == leader) base = atomicAdd(&a.cntw[p], __popcll(mask));
         base = __shfl(base, leader);
         if (mine) {
+            // base + rank < lcap: each element is appended at most once per update
             const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-            a.listw[p * lcap + base + rank] = (int)e;
+            if (base + rank < lcap) a.listw[(size_t)p * (size_t)lcap + (size_t)(base + rank)] = (int)e;
         }
     }
 }

@@ -78,9 +78,23 @@ class Executor:
     def discard(self, handle) -> None: ...        # a prepared request that is never admitted
 
 
+def _initial_state(ctx, prob, req, init_state):
+    """Set a request's initial state: its analytic initial condition projected
+    on the device, or the coefficients init_state(problem) returns (callers
+    that bring their own projection), or a dry state for a poisoned request."""
+    if req.poisoned:
+        c = np.zeros((prob.mesh.ne, 3, I.K_OF_P[req.spec.p]))
+        c[:, 0, 0] = -5000.0 * np.sqrt(prob.mesh.areas())   # every element dry
+        ctx.set_state(c)
+    elif init_state is not None:
+        ctx.set_state(init_state(prob))
+    else:
+        ctx.set_state_fn(prob.ic)
+
+
 class GpuExecutor(Executor):
     def __init__(self, precision: int, budget_bytes: int, max_instances: int = 1024, stream=None,
-                 keep_state: bool = True):
+                 keep_state: bool = True, init_state: Optional[Callable] = None):
         from . import swe
         self.swe = swe
         self.precision = precision
@@ -88,6 +102,7 @@ class GpuExecutor(Executor):
                                stream=stream)
         self._budget = budget_bytes
         self.keep_state = keep_state
+        self.init_state = init_state
         self.slots: Dict[int, tuple] = {}
 
     def footprint(self, req):
@@ -99,14 +114,8 @@ class GpuExecutor(Executor):
     def prepare(self, req):
         prob = I.request_problem(req.spec)
         ctx = self.swe.context_for(prob, precision=self.precision)
-        p = req.spec.p
-        if req.poisoned:
-            c = np.zeros((prob.mesh.ne, 3, I.K_OF_P[p]))
-            c[:, 0, 0] = -5000.0 * np.sqrt(prob.mesh.areas())   # every element dry
-            ctx.set_state(c)
-        else:
-            ctx.set_state_fn(prob.ic)
-        return ctx, prob.dt(), req.spec.steps, 3 * I.K_OF_P[p] * prob.mesh.ne
+        _initial_state(ctx, prob, req, self.init_state)
+        return ctx, prob.dt(), req.spec.steps, 3 * I.K_OF_P[req.spec.p] * prob.mesh.ne
 
     def admit(self, handle):
         ctx, dt, steps, dof = handle
@@ -140,12 +149,14 @@ class PlainExecutor(Executor):
     """The plain solver: one request on the GPU at a time, unbatched, each
     stage one ordinary launch over that request's mesh (FIFO queue)."""
 
-    def __init__(self, precision: int, stream=None, keep_state: bool = True):
+    def __init__(self, precision: int, stream=None, keep_state: bool = True,
+                 init_state: Optional[Callable] = None):
         from . import swe
         self.swe = swe
         self.precision = precision
         self.stream = stream
         self.keep_state = keep_state
+        self.init_state = init_state
         self.cur: Dict[int, list] = {}
         self.next_slot = 0
 
@@ -158,14 +169,8 @@ class PlainExecutor(Executor):
     def prepare(self, req):
         prob = I.request_problem(req.spec)
         ctx = self.swe.context_for(prob, precision=self.precision, stream_base=self.stream)
-        p = req.spec.p
-        if req.poisoned:
-            c = np.zeros((prob.mesh.ne, 3, I.K_OF_P[p]))
-            c[:, 0, 0] = -5000.0 * np.sqrt(prob.mesh.areas())
-            ctx.set_state(c)
-        else:
-            ctx.set_state_fn(prob.ic)
-        return ctx, prob.dt(), req.spec.steps, 3 * I.K_OF_P[p] * prob.mesh.ne
+        _initial_state(ctx, prob, req, self.init_state)
+        return ctx, prob.dt(), req.spec.steps, 3 * I.K_OF_P[req.spec.p] * prob.mesh.ne
 
     def admit(self, handle):
         if self.cur:

@@ -84,3 +84,42 @@ def test_adaptive_run_fp32():
     say(f"adaptive fp32: order-map agreement {agree:.4f}, xi rel L2 {err:.2e}")
     assert agree > 0.99
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("separate", [0, 1, 2])
+def test_set_state_after_adaptive_steps(separate):
+    """A state set after adaptive steps (without reading the orders first) is
+    truncated to the orders the device chose: the caller's modes above each
+    element's current order are ignored, the ones below kept.  The oracle's
+    state after 12 adaptive steps, with noise added above each element's
+    order, is set and both continue for 10 more steps (FP64, 1e-12); fused,
+    order-separated and order-partitioned stepping."""
+    prob = c3_small()
+    orc = Oracle.from_problem(prob)
+    c0 = orc.project(prob.ic)
+    dt = prob.dt()
+    n1, n2 = 12, 10
+    mid = orc.step(c0, n1, dt, adapt=True, tau=prob.adapt_tau, p_lo=1, p_hi=3)
+    pmid = orc.order()
+    ref = orc.step(mid, n2, dt, t0=n1 * dt, adapt=True, tau=prob.adapt_tau, p_lo=1, p_hi=3)
+    pref = orc.order()
+    dirty = mid.copy()
+    above = np.arange(10)[None, :] >= np.asarray(I.K_OF_P)[pmid][:, None]
+    noise = np.random.default_rng(77).standard_normal(dirty.shape) * np.abs(mid).max()
+    dirty += noise * above[:, None, :]
+    assert np.count_nonzero(pmid > 1) > 0
+    with swe.context_for(prob, separate=separate) as ctx:
+        ctx.set_state(c0)
+        ctx.step(n1, dt)
+        ctx.set_state(dirty, t0=n1 * dt)
+        back, _ = ctx.state()
+        ctx.step(n2, dt)
+        ctx.sync()
+        got, _ = ctx.state()
+        pgot = ctx.order()
+    assert np.max(np.abs(back - mid)) <= 1e-14 * np.max(np.abs(mid)), np.max(np.abs(back - mid))
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    say(f"set_state after adaptive steps, separate={separate}: maps equal {np.array_equal(pgot, pref)}, "
+        f"rel L2 {err:.2e}")
+    assert np.array_equal(pgot, pref)
+    assert err < 1e-12

@@ -1,12 +1,16 @@
 """Batched instances: each instance's result inside a batch (persistent
 launches over all resident instances, captured step replayed, membership
-changing between ticks, autotuned tiles) is bitwise the result of the same
-instance run on its own; admission respects the footprint budget."""
+changing between ticks, autotuned tiles) matches the oracle run of the same
+instance (FP64 within 1e-12 relative L2, FP32 elevation within 1e-5) and is
+bitwise the result of the same instance run on its own; admission respects
+the footprint budget."""
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
 
+from oracle.oracle import Oracle
 from paper_2311_11348_amd import inputs as I
 from paper_2311_11348_amd import swe
 
@@ -26,25 +30,54 @@ def make_instances(count, seed, n_lo=200, n_hi=6000):
     return probs
 
 
-def ctx_for(prob, precision):
+def ctx_for(prob, precision, c0=None):
     ctx = swe.context_for(prob, precision=precision)
-    ctx.set_state_fn(prob.ic)
+    if c0 is None:
+        ctx.set_state_fn(prob.ic)
+    else:
+        ctx.set_state(c0)
     return ctx
 
 
+class OracleRuns:
+    """The mixed-size instances of the batch test, their initial states
+    projected by the oracle and the oracle's runs of each (computed once, one
+    thread per instance: the oracle releases the interpreter lock)."""
+
+    def __init__(self):
+        self.probs = make_instances(6, seed=7)
+        self.steps = [30, 17, 25, 40, 9, 33]
+        self.c0, self.ref = [], []
+
+        def one(args):
+            prob, n = args
+            orc = Oracle.from_problem(prob)
+            c0 = orc.project(prob.ic)
+            return c0, orc.step(c0, n, prob.dt())
+        with ThreadPoolExecutor(max_workers=6) as pool:
+            for c0, ref in pool.map(one, zip(self.probs, self.steps)):
+                self.c0.append(c0)
+                self.ref.append(ref)
+
+
+@pytest.fixture(scope="module")
+def oracle_runs():
+    say("oracle runs of the batch instances")
+    return OracleRuns()
+
+
 @pytest.mark.parametrize("precision", [swe.SWE_FP64, swe.SWE_FP32_WB])
-def test_batch_equals_alone(precision):
-    probs = make_instances(6, seed=7)
-    steps = [30, 17, 25, 40, 9, 33]
+def test_batch_equals_alone(precision, oracle_runs):
+    probs, steps, c0s = oracle_runs.probs, oracle_runs.steps, oracle_runs.c0
     dts = [p.dt() for p in probs]
     alone = []
-    for prob, n, dt in zip(probs, steps, dts):
-        ctx = ctx_for(prob, precision)
+    for prob, n, dt, c0 in zip(probs, steps, dts, c0s):
+        ctx = ctx_for(prob, precision, c0)
         ctx.step(n, dt)
         ctx.sync()
         alone.append(ctx.state())
         ctx.close()
-    ctxs = [ctx_for(p, precision) for p in probs]
+    ctxs = [ctx_for(p, precision, c0) for p, c0 in zip(probs, c0s)]
     with swe.Batch(precision=precision, budget_bytes=8 << 30, max_instances=16) as b:
         slots = [b.admit(c, n, dt) for c, n, dt in zip(ctxs[:4], steps[:4], dts[:4])]
         b.tick(5)
@@ -61,9 +94,17 @@ def test_batch_equals_alone(precision):
         assert b.resident() == 0
     for i, (ctx, (ref, tref)) in enumerate(zip(ctxs, alone)):
         got, t = ctx.state()
-        say(f"instance {i}: ne={ctx.ne} p={probs[i].p_max} equal={np.array_equal(got, ref)} t={t:.3f}/{tref:.3f}")
+        orc = oracle_runs.ref[i]
+        err = np.linalg.norm(got - orc) / np.linalg.norm(orc)
+        exi = np.linalg.norm((got - orc)[:, 0]) / np.linalg.norm(orc[:, 0])
+        say(f"instance {i}: ne={ctx.ne} p={probs[i].p_max} equal={np.array_equal(got, ref)} t={t:.3f}/{tref:.3f} "
+            f"vs oracle rel L2 {err:.2e}, xi {exi:.2e}")
         assert np.array_equal(got, ref), i
         assert t == tref
+        if precision == swe.SWE_FP64:
+            assert err < 1e-12, i
+        else:
+            assert exi < 1e-5, i
         ctx.close()
 
 

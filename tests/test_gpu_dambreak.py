@@ -109,10 +109,13 @@ def test_dambreak_full_size_mass(precision, separate):
 
 @pytest.mark.parametrize("lo,hi", [(0, 1), (1, 2)])
 @pytest.mark.parametrize("separate", [1, 2])
-def test_dambreak_dynamic_small_matches_oracle(lo, hi, separate):
+@pytest.mark.parametrize("precision", [swe.SWE_FP64, swe.SWE_FP32_WB])
+def test_dambreak_dynamic_small_matches_oracle(lo, hi, separate, precision):
     """Dynamic orders (the indicator with threshold 1e-2 m before every step)
-    on 32x32x2: order maps identical to the oracle's adaptive run, state
-    within 1e-12 after 12 steps (FP64)."""
+    on 32x32x2 against the oracle's adaptive run after 12 steps: FP64 order
+    maps identical and state within 1e-12; FP32 (the configuration the
+    benchmark's FP32 dynamic rows time) order maps agreeing on at least 99 %
+    of the elements and the elevation within 1e-5 relative L2."""
     tau = 1e-2
     prob = I.config_dambreak(n=32, p_lo=lo, p_hi=hi, dt_fixed=None, adapt_tau=tau)
     orc = Oracle.from_problem(prob)
@@ -126,15 +129,21 @@ def test_dambreak_dynamic_small_matches_oracle(lo, hi, separate):
             assert np.min(np.abs(ind - thr)) / thr > 1e-9   # no decision within rounding of a threshold
         ref = orc.step(ref, 1, dt, t0=s * dt, adapt=True, tau=tau, p_lo=lo, p_hi=hi)
     pref = orc.order()
-    with swe.context_for(prob, separate=separate) as ctx:
+    with swe.context_for(prob, precision=precision, separate=separate) as ctx:
         ctx.set_state(c0)
         ctx.step(steps, dt)
         ctx.sync()
         got, _ = ctx.state()
         pgot = ctx.order()
     err = rel(got, ref)
-    say(f"dambreak dynamic p{lo}-{hi} separate={separate}: {int((pref == hi).sum())} of {prob.mesh.ne} at p{hi}, "
-        f"maps equal {np.array_equal(pgot, pref)}, rel L2 {err:.2e}")
+    exi = rel(got[:, 0], ref[:, 0])
+    agree = float(np.mean(pgot == pref))
+    say(f"dambreak dynamic p{lo}-{hi} separate={separate} precision={precision}: {int((pref == hi).sum())} of "
+        f"{prob.mesh.ne} at p{hi}, map agreement {agree:.4f}, rel L2 {err:.2e}, xi {exi:.2e}")
     assert (pref == hi).sum() > 0
-    assert np.array_equal(pgot, pref)
-    assert err < 1e-12
+    if precision == swe.SWE_FP64:
+        assert np.array_equal(pgot, pref)
+        assert err < 1e-12
+    else:
+        assert agree >= 0.99
+        assert exi < 1e-5
