@@ -1,9 +1,14 @@
 """Throughput of the DG shallow-water hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload tidal|tsunami|static32|dambreak|batched|served]
+                    [--workload default|tidal|tsunami|static32|dambreak|batched|served]
 
-tidal (default): 512x512x2 triangulation of a 100 km square, nodes jittered
+default: the tidal headline below (value, roofline, compute roofline, the
+  FP64 path beside it, the oracle on the host), with the tsunami, batched and
+  served workloads as extra keys of the same line (tsunami timed over at
+  least 200 steps, batched over at least 20 steps of every instance, served
+  on a 30 s trace); each extra leg that fails records its error instead.
+tidal: the headline alone: 512x512x2 triangulation of a 100 km square, nodes jittered
   by U(-0.2h, 0.2h) (seed 2), uniform order p = 2, bathymetry
   10 m + 3990 m (1 + sin(2 pi x/L) cos(2 pi y/L))/2, lake at rest, west edge
   open and forced by a 0.5 m tide of period 44712 s, Coriolis 3.19e-5 1/s,
@@ -38,6 +43,16 @@ A step is one SSP-RK2 step (two stages) of the whole hot path: volume +
 source + edge fluxes + stage update + u H = q (+ order update when adaptive).
 Metric: DOF-updates per second per RK stage, DOF = 3 * sum_e K(p_e).  Inputs
 are resident in HBM before the timed region.  Prints one JSON line.
+
+roofline: the headline kernel's algorithmic bytes per launch (11.5 K words +
+100 B per element and stage) over its average launch time in the timed
+region (HIP events on the library stream; every launch there is that
+kernel), against 8 TB/s; traffic: the HBM bytes its counters read per launch
+(a committed counter summary of the same kernel sources), over the same
+time.  compute: the method's floating-point operations per launch over the
+same time, against the vector peaks.  cpu_baseline: the FP64 oracle on the
+host's cores (one process per usable core, up to 16), with a single-process
+figure beside it.
 """
 from __future__ import annotations
 
@@ -55,17 +70,78 @@ HBM_PEAK_GBS = 8000.0
 K_OF_P = (1, 3, 6, 10)
 
 
-def stage_bytes_per_element(p: int, word: int, nv: int, ne: int) -> float:
-    """Algorithmic HBM bytes one element moves in one fused stage kernel
-    (average of the two SSP-RK2 stages): read c (3K) and u (2K), read c^n (3K)
-    in the second stage only, write c (3K) and u (2K); geometry: 3 vertex ids,
-    3 neighbour ids, 1 packed neighbour-edge byte and the element's share of
-    the 32-byte vertex records.  Neighbour coefficients are counted once, as
-    their owner's read (they are served from cache)."""
+def stage_bytes_per_element(p: int, word: int) -> float:
+    """Algorithmic HBM bytes one element moves in one RK stage, the practical
+    figure of the scope table's measurement row: read c (3K), read c^n (3K)
+    in the second stage only (1.5K on average), write c (3K), and the stored
+    velocity u (write 2K, read 2K): 11.5 K words, plus G = 100 B of geometry
+    (about 80 B of FP64 geometry and 16 B of neighbour ids and codes)."""
+    return 11.5 * K_OF_P[p] * word + 100.0
+
+
+def kernel_bytes_per_element(p: int, word: int, nv: int, ne: int) -> float:
+    """The same stage as this library's fused kernel moves it: read c (3K) and
+    u (2K), c^n (3K) in stage 2, write c (3K) and u (2K); 3 vertex ids, 3
+    neighbour ids, 1 packed neighbour-edge byte and the element's share of
+    the 32-byte vertex records (geometry is rebuilt from the vertices, not
+    stored).  Neighbour coefficients are counted once, as their owner's read."""
     K = K_OF_P[p]
     state = (3 * K + 2 * K + 0.5 * 3 * K + 3 * K + 2 * K) * word
     geo = 3 * 4 + 3 * 4 + 1 + 32.0 * nv / ne
     return state + geo
+
+
+# Vector peaks of the MI355X (256 CUs at 2.4 GHz): FP32 157.3 TFLOP/s with
+# packed FP32 FMAs, which this library's kernels are built without (half that
+# rate per issued instruction), FP64 78.6 TFLOP/s.
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def compute_roofline(p: int, fp32: bool, ne: int, launch_s: float) -> dict:
+    """Operations of one stage launch (the method's contractions with the
+    reference tensors' exact zero patterns, each edge flux once, see
+    paper_2311_11348_amd/flops.py) over the launch time, against the vector
+    peak of the bulk precision; the FP64 part of the FP32 path is priced at
+    the FP64 rate."""
+    from paper_2311_11348_amd import flops as F
+    f = F.stage_flops(p)
+    bulk = f["total"] * ne
+    f64 = f["fp64"] * ne
+
+    def mixed_peak(fp32_rate):
+        # the rate at which the launch's work completes at peak: the bulk at
+        # the bulk precision's rate, the FP64 part at the FP64 rate
+        if not fp32:
+            return FP64_PEAK_TFLOPS
+        return (bulk + f64) / (bulk / fp32_rate + f64 / FP64_PEAK_TFLOPS)
+    peak = mixed_peak(FP32_PEAK_TFLOPS)
+    unpacked = mixed_peak(FP32_PEAK_TFLOPS / 2)
+    achieved = (bulk + f64) / launch_s / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "frac_of_unpacked_peak": achieved / unpacked,
+            "flop_per_element": f["total"] + f["fp64"], "fp64_flop_per_element": f["fp64"],
+            "flop_per_launch": bulk + f64,
+            "peak_note": "vector peaks (FP32 157.3 TFLOP/s with packed FMAs, 78.6 without, which is how "
+                         "the kernels are built; FP64 78.6), mixed by the FP64 share of the work on the "
+                         "FP32 path"}
+
+
+def host_description() -> dict:
+    """The host the oracle legs run on: logical CPUs, the ones this process
+    may use, and the CPU model and socket count from /proc/cpuinfo."""
+    model, sockets = None, set()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name") and model is None:
+                    model = line.split(":", 1)[1].strip()
+                elif line.startswith("physical id"):
+                    sockets.add(line.split(":", 1)[1].strip())
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable": len(os.sched_getaffinity(0)), "model": model,
+            "sockets": len(sockets) or None}
 
 
 KERNEL_SOURCES = ("paper_2311_11348_amd/csrc/swe_kernels.hip", "paper_2311_11348_amd/csrc/swe_internal.h",
@@ -121,15 +197,41 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 3) -> None:
     del src, dst
 
 
-def cpu_baseline(p: int, budget_s: float = 15.0):
-    """The FP64 oracle (single thread) on a bounded sample of the same workload:
-    the same problem family on a 64x64x2 mesh, timed over whole SSP-RK2 steps."""
+ORACLE_SAMPLE_N = 64
+
+
+def _oracle_sample(p: int):
     from oracle.oracle import Oracle
     from paper_2311_11348_amd import inputs as I
-    n = 64
-    prob = I.config_c2(n=n, p=p)
+    prob = I.config_c2(n=ORACLE_SAMPLE_N, p=p)
     orc = Oracle.from_problem(prob)
     c0 = orc.project(prob.ic)
+    return prob, orc, c0
+
+
+def _oracle_worker(p, steps, start, results):
+    """One oracle process of the all-core leg: set up, wait at the start
+    barrier, run `steps` SSP-RK2 steps, report the elapsed time."""
+    prob, orc, c0 = _oracle_sample(p)
+    dt = prob.dt()
+    start.wait()
+    t0 = time.perf_counter()
+    orc.step(c0, steps, dt)
+    results.put(time.perf_counter() - t0)
+
+
+def cpu_baseline(p: int, budget_s: float = 10.0) -> dict:
+    """The FP64 oracle on the host, on a bounded sample of the headline
+    workload: the tidal problem family on a 64x64x2 mesh (8192 elements, the
+    same order, bathymetry, forcing and physics), whole SSP-RK2 steps, scaled
+    to DOF-updates per second per stage.  First one process on one core
+    (about budget_s seconds), then one independent oracle process per usable
+    core, started together, each running the same number of steps (the
+    oracle is single-threaded and unchanged; its elements are computed one
+    after another).  Runs before the GPU is initialised: the worker processes
+    are forked from this one."""
+    import multiprocessing as mp
+    prob, orc, c0 = _oracle_sample(p)
     dt = prob.dt()
     t0 = time.perf_counter()
     c = orc.step(c0, 1, dt)
@@ -139,9 +241,26 @@ def cpu_baseline(p: int, budget_s: float = 15.0):
     orc.step(c, steps, dt, t0=dt)
     el = time.perf_counter() - t0
     dof = 3 * K_OF_P[p] * prob.mesh.ne
-    return {"value": dof * 2 * steps / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n}x{n}x2 mesh of the tidal workload family ({prob.mesh.ne} elements, p={p}), "
-                      f"{steps} SSP-RK2 steps, FP64, single thread, {el:.1f} s"}
+    single = dof * 2 * steps / el
+    host = host_description()
+    nproc = min(16, host["usable"] or 1)
+    ctx = mp.get_context("fork")
+    start, results = ctx.Barrier(nproc + 1), ctx.Queue()
+    procs = [ctx.Process(target=_oracle_worker, args=(p, steps, start, results)) for _ in range(nproc)]
+    for pr in procs:
+        pr.start()
+    start.wait()              # every worker has set up: they start together
+    times = [results.get() for _ in procs]
+    for pr in procs:
+        pr.join()
+    allcore = nproc * dof * 2 * steps / max(times)
+    return {"value": allcore, "unit": "DOF-updates/s", "cores": nproc, "kind": "oracle",
+            "sample": f"{ORACLE_SAMPLE_N}x{ORACLE_SAMPLE_N}x2 mesh of the tidal workload family "
+                      f"({prob.mesh.ne} elements, p={p}), {steps} SSP-RK2 steps per process, FP64; "
+                      f"{nproc} independent oracle processes at once (slowest {max(times):.1f} s); "
+                      f"single process {el:.1f} s",
+            "single_thread": {"value": single, "cores": 1, "seconds": el},
+            "host": host}
 
 
 def timed_steps(ctx, stream, steps, dt):
@@ -173,8 +292,12 @@ def run_uniform(prob, precision, steps, warmup):
     ne, nv = prob.mesh.ne, prob.mesh.nv
     word = 8 if precision == swe.SWE_FP64 else 4
     dof = 3 * K_OF_P[p] * ne
+    # every launch of the timed region is this kernel (two per step, back to back
+    # on the library stream), so the event-timed region / launches is its
+    # average launch duration, launch gaps included
     launch_s = ms * 1e-3 / (2 * steps)
-    bpe = stage_bytes_per_element(p, word, nv, ne)
+    bpe = stage_bytes_per_element(p, word)
+    kbpe = kernel_bytes_per_element(p, word, nv, ne)
     achieved = bpe * ne / launch_s / 1e9
     real = "double" if word == 8 else "float"
     traffic = measured_traffic([f"k_stage_sh<{p}, {real}, {m}>" for m in (1, 2)]) if p == 2 and ne == 524288 else None
@@ -185,7 +308,13 @@ def run_uniform(prob, precision, steps, warmup):
                          "traffic_bytes_per_launch": traffic,
                          "kernel": f"k_stage_sh<{p},{real}> (fused stage, edge fluxes shared within a block)"
                                    if p >= 1 else f"k_stage<{p},{real}> (fused stage, element gather)",
-                         "bytes_per_launch": bpe * ne, "avg_launch_us": launch_s * 1e6}}
+                         "bytes_per_element": bpe, "bytes_per_launch": bpe * ne,
+                         "bytes_note": "11.5 K words + 100 B per element and stage (stored velocity, "
+                                       "c^n read in the second stage only)",
+                         "kernel_bytes_per_launch": kbpe * ne,
+                         "frac_kernel_bytes": kbpe * ne / launch_s / 1e9 / HBM_PEAK_GBS,
+                         "avg_launch_us": launch_s * 1e6, "launches_timed": 2 * steps},
+            "compute": compute_roofline(p, word == 4, ne, launch_s)}
 
 
 def run_separated(prob, precision, steps, warmup, separate=1, chunk=50):
@@ -292,12 +421,17 @@ def run_dambreak(steps, warmup, n=1024):
     return out
 
 
+BATCH_SOLVE_STEPS = 300      # steps of one batched solve in the batched workload
+
+
 def run_batched(count, steps, warmup):
     """Many independent instances: FP32 and FP64 batched (tile-per-block
     kernels, step graph, autotuned tiles) and the plain FP64 solver (one
-    instance at a time, one ordinary launch per stage).  Every instance runs
-    warmup + steps steps; the timed region holds the last ``steps`` of all of
-    them.  Inputs are resident before timing."""
+    instance at a time, one ordinary launch per stage, on the same FP64
+    contexts once they have left the batch).  Each leg runs warmup steps,
+    then `steps` timed steps of every instance; solves per second are for
+    the workload's 300-step solves at the timed rate.  Inputs are resident
+    before timing."""
     import numpy as np
     import torch
     from paper_2311_11348_amd import inputs as I
@@ -319,14 +453,17 @@ def run_batched(count, steps, warmup):
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1)
 
-    def batched(prec):
-        t0 = time.perf_counter()
-        ctxs = []
+    def contexts(prec):
+        out = []
         for p in probs:
-            c = swe.context_for(p, precision=prec)
+            c = swe.context_for(p, precision=prec, stream_base=stream.cuda_stream)
             c.set_state_fn(p.ic)
-            ctxs.append(c)
-        budget = sum(swe.swe_footprint_bytes(c.ne, p.p_max, prec) for c, p in zip(ctxs, probs)) + (1 << 30)
+            out.append(c)
+        return out
+
+    def batched(prec, ctxs):
+        t0 = time.perf_counter()
+        budget = sum(swe.swe_footprint_bytes(c.ne, p.p_max, prec) for c, p in zip(ctxs, probs)) + (8 << 30)
         b = swe.Batch(precision=prec, budget_bytes=budget, max_instances=count, stream=stream.cuda_stream)
         slots = [b.admit(c, steps + warmup, dt) for c, dt in zip(ctxs, dts)]
         b.tune(reps=3)
@@ -335,62 +472,62 @@ def run_batched(count, steps, warmup):
         b.sync()
         print(f"bench: batched precision {prec} ready after {time.perf_counter() - t0:.1f} s",
               file=sys.stderr, flush=True)
-
-        def run():
-            b.tick(steps)
-        ms = elapsed(run)
+        ms = elapsed(lambda: b.tick(steps))
         done = b.poll()
         assert len(done) == count and not any(f for _, f in done), done
         out = []
-        for s, c in zip(slots, ctxs):
-            b.retire(s)
+        for s_, c in zip(slots, ctxs):
+            b.retire(s_)
             out.append(c.state()[0][:, 0].copy())
-            c.close()
         b.close()
         return ms, out, tiles
 
-    def plain_fp64():
+    def plain_fp64(ctxs):
         ms, out = 0.0, []
-        for p, dt in zip(probs, dts):
-            c = swe.context_for(p, precision=swe.SWE_FP64, stream_base=stream.cuda_stream)
+        for p, dt, c in zip(probs, dts, ctxs):
             c.set_state_fn(p.ic)
             c.step(warmup, dt)
             c.sync()
             torch.cuda.synchronize()
-
-            def run():
-                c.step(steps, dt)
-            ms += elapsed(run)
+            ms += elapsed(lambda: c.step(steps, dt))
             c.sync()
             out.append(c.state()[0][:, 0].copy())
-            c.close()
         return ms, out
 
-    ms32, xi32, tiles = batched(swe.SWE_FP32_WB)
-    ms64, xi64, _ = batched(swe.SWE_FP64)
-    msp, xip = plain_fp64()
+    c32 = contexts(swe.SWE_FP32_WB)
+    ms32, xi32, tiles = batched(swe.SWE_FP32_WB, c32)
+    for c in c32:
+        c.close()
+    c64 = contexts(swe.SWE_FP64)
+    ms64, xi64, _ = batched(swe.SWE_FP64, c64)
+    print("bench: plain FP64 solver, one instance at a time", file=sys.stderr, flush=True)
+    msp, xip = plain_fp64(c64)
+    for c in c64:
+        c.close()
     d64 = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(xi64, xip))
     err = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(xi32, xi64))
     upd = dofs.sum() * 2 * steps
-    word_bytes = {4: 0.0, 8: 0.0}
-    for w in word_bytes:
-        word_bytes[w] = sum(p.mesh.ne * stage_bytes_per_element(p.p_max, w, p.mesh.nv, p.mesh.ne)
-                            for p in probs) * 2 * steps
+    k = np.bincount([p.p_max for p in probs], minlength=4)
+    word_bytes = {w: sum(p.mesh.ne * stage_bytes_per_element(p.p_max, w) for p in probs) * 2 * steps for w in (4, 8)}
     ach = word_bytes[4] / (ms32 * 1e-3) / 1e9
 
     def leg(ms, word):
-        return {"solves_per_s": count / (ms * 1e-3), "value": upd / (ms * 1e-3), "ms_total": ms,
-                "hbm_gbs": word_bytes[word] / (ms * 1e-3) / 1e9}
-    k = np.bincount([p.p_max for p in probs], minlength=4)
+        return {"solves_per_s": count / (ms / steps * BATCH_SOLVE_STEPS * 1e-3), "value": upd / (ms * 1e-3),
+                "ms_per_step": ms / steps, "hbm_gbs": word_bytes[word] / (ms * 1e-3) / 1e9}
+    kinds = {p: ("shared edge fluxes, 256-element tiles" if t[2] else f"element gather, {t[0]}-element tiles")
+             for p, t in tiles.items() if k[p] > 0}
+    kernel = "; ".join(f"p{p}: k_batch_stage{'_sh' if tiles[p][2] else ''}<{p},float> ({kinds[p]})"
+                       for p in sorted(kinds))
     return {"value": upd / (ms32 * 1e-3), "ms_per_step": ms32 / steps,
-            "solves_per_s": count / (ms32 * 1e-3),
+            "solves_per_s": leg(ms32, 4)["solves_per_s"],
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": "k_batch_stage<P,float> over all orders + k_batch_clock (whole step)"},
-            "fp64_batched": leg(ms64, 8), "plain_fp64": leg(msp, 8),
+                         "kernel": kernel + " + k_batch_clock, whole step (one launch per order class and stage)"},
+            "fp32_batched": leg(ms32, 4), "fp64_batched": leg(ms64, 8), "plain_fp64": leg(msp, 8),
             "speedup_solves_vs_plain_fp64": msp / ms32,
             "fp32_xi_rel_l2_vs_fp64_max": err, "fp64_batched_vs_plain_xi_rel_l2_max": d64,
-            "tiles": {f"p{p}": {"tile": t[0], "grid": t[1], "kernel": "shared edge fluxes" if t[2] else "element gather"}
+            "solve_steps": BATCH_SOLVE_STEPS, "timed_steps": steps,
+            "tiles": {f"p{p}": {"tile": t[0], "grid": t[1], "kernel": kinds[p]}
                       for p, t in tiles.items() if k[p] > 0},
             "elements": int(sum(p.mesh.ne for p in probs)),
             "orders": {f"p{p}": int(k[p]) for p in range(4) if k[p] > 0}}
@@ -429,7 +566,7 @@ def run_served(duration, rate, capacity_requests, tick_steps):
             s2 = serve(sub, e, tick_steps=tick_steps, on_tick=progress)
             e.close()
         else:
-            e = PlainExecutor(swe.SWE_FP64, stream=stream.cuda_stream, keep_state=False)
+            e = PlainExecutor(swe.SWE_FP64, budget_bytes=budget, keep_state=False)
             s2 = serve(sub, e, tick_steps=1 << 30, on_tick=progress)
         sm = s2.summary()
         print(f"bench: capacity {mk} {sm}", file=sys.stderr, flush=True)
@@ -437,13 +574,73 @@ def run_served(duration, rate, capacity_requests, tick_steps):
     return main, dict(cap)
 
 
+def tidal_leg(args, I, swe):
+    """The headline: the tidal workload, FP32 path with the FP64 path beside it."""
+    n = args.n or 512
+    prob = I.config_c2(n=n, p=args.p)
+    print(f"bench: tidal {prob.mesh.ne} elements p={args.p}", file=sys.stderr, flush=True)
+    r32 = run_uniform(prob, swe.SWE_FP32_WB, args.steps, args.warmup)
+    r64 = run_uniform(prob, swe.SWE_FP64, args.steps, args.warmup)
+    return dict(value=r32["value"], ms_per_step=r32["ms_per_step"], dtype="f32 (f64 bathymetry terms)",
+                config={"workload": f"tidal: {n}x{n}x2 jittered triangulation, {prob.mesh.ne} elements, "
+                                    f"p={args.p} uniform, sin*cos bathymetry 10-4000 m, west tide",
+                        "elements": prob.mesh.ne, "order": args.p, "dof": 3 * K_OF_P[args.p] * prob.mesh.ne},
+                roofline=r32["roofline"], compute=r32["compute"],
+                fp64={"value": r64["value"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
+                      "roofline": r64["roofline"], "compute": r64["compute"]})
+
+
+def tsunami_leg(n, steps, warmup, I, swe):
+    """The p-adaptive workload: order-partitioned FP64 and order-separated FP32."""
+    prob = I.config_c3(n=n)
+    print(f"bench: tsunami {prob.mesh.ne} elements adaptive", file=sys.stderr, flush=True)
+    # FP32 order-partitioned stepping with orders up to 3 is switched off (see
+    # the library's configuration checks): the partitioned scheme runs in FP64
+    r = run_separated(prob, swe.SWE_FP64, steps, warmup, separate=2)
+    rs = run_separated(I.config_c3(n=n), swe.SWE_FP32_WB, steps, warmup, separate=1)
+    return {"value": r["value"], "ms_per_step": r["ms_per_step"], "dtype": "f64", "timed_steps": steps,
+            "scheme": "order-partitioned (base elements and each order's listed elements on parallel branches)",
+            "order_fractions": r["order_fractions"],
+            "separated_fp32": {"value": rs["value"], "ms_per_step": rs["ms_per_step"],
+                               "dtype": "f32 (f64 bathymetry terms)", "order_fractions": rs["order_fractions"],
+                               "scheme": "base + corrections on a second stream, joined by epilogues"},
+            "config": f"tsunami: {n}x{n}x2 jittered, shelf 4000-50 m, 2 m hump, p in {{1,2,3}} by the "
+                      "indicator (1e-3 m) before every step, base p=1"}
+
+
+def served_leg(duration, rate, capacity, tick_steps, swe):
+    main_s, cap = run_served(duration, rate, capacity, tick_steps)
+    return {"solves_per_s": main_s["solves_per_s"], "p50_latency_s": main_s["p50_latency_s"],
+            "p99_latency_s": main_s["p99_latency_s"], "served": main_s, "capacity": cap,
+            "speedup_solves_vs_plain_fp64": cap["batched_fp32"]["solves_per_s"]
+            / max(cap["plain_fp64"]["solves_per_s"], 1e-30),
+            "config": f"served: Poisson {rate:g} req/s for {duration:g} s, 8k-260k elements log-uniform, "
+                      "p in {1,2,3}, 200-2000 steps, tidal or hump; FP32 with FP64 bathymetry terms; "
+                      f"admission by resident footprint (64 GiB); {tick_steps} steps per tick; capacity "
+                      f"legs: the first {capacity} requests offered at once"}
+
+
+def guarded(name, fn):
+    """Run one extra leg of the default line; a failure is recorded, not raised."""
+    t0 = time.perf_counter()
+    try:
+        r = fn()
+    except Exception as e:   # noqa: BLE001 - the headline line must still print
+        print(f"bench: {name} leg failed: {e!r}", file=sys.stderr, flush=True)
+        r = {"error": repr(e)}
+    r["wall_s"] = time.perf_counter() - t0
+    return r
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", choices=["tidal", "tsunami", "static32", "dambreak", "batched", "served"],
-                    default="tidal")
+    ap.add_argument("--workload", choices=["default", "tidal", "tsunami", "static32", "dambreak", "batched",
+                                           "served"], default="default",
+                    help="default: the tidal headline with the tsunami, batched and (shortened) served "
+                         "workloads as extra keys; tidal: the headline alone")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--duration", type=float, default=120.0)
     ap.add_argument("--rate", type=float, default=20.0)
@@ -451,7 +648,10 @@ def main() -> int:
     ap.add_argument("--tick-steps", type=int, default=50)
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--p", type=int, default=2)
+    ap.add_argument("--served-duration", type=float, default=30.0,
+                    help="length of the request trace of the default line's served leg (s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="default workload without the extra legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB elementwise copy first (scales PMC byte counters)")
     args = ap.parse_args()
@@ -461,6 +661,13 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
+    t_wall0 = time.perf_counter()
+    cpu = None
+    if args.workload in ("default", "tidal") and not args.no_cpu_baseline:
+        # the oracle legs fork worker processes: before anything initialises the GPU
+        print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(args.p)
+
     import numpy as np
     import torch
     from paper_2311_11348_amd import inputs as I
@@ -468,46 +675,28 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    t_wall0 = time.perf_counter()
     out = {"metric": "DOF-updates/s per RK stage", "unit": "DOF-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic"}
     if args.copy_calibration:
         copy_calibration()
-    if args.workload == "tidal":
-        n = args.n or 512
-        prob = I.config_c2(n=n, p=args.p)
-        print(f"bench: tidal {prob.mesh.ne} elements p={args.p}", file=sys.stderr, flush=True)
-        r32 = run_uniform(prob, swe.SWE_FP32_WB, args.steps, args.warmup)
-        r64 = run_uniform(prob, swe.SWE_FP64, args.steps, args.warmup)
-        out.update(value=r32["value"], ms_per_step=r32["ms_per_step"], dtype="f32 (f64 bathymetry terms)",
-                   config={"workload": f"tidal: {n}x{n}x2 jittered triangulation, {prob.mesh.ne} elements, "
-                                       f"p={args.p} uniform, sin*cos bathymetry 10-4000 m, west tide",
-                           "elements": prob.mesh.ne, "order": args.p, "dof": 3 * K_OF_P[args.p] * prob.mesh.ne},
-                   roofline=r32["roofline"],
-                   fp64={"value": r64["value"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
-                         "roofline": r64["roofline"]})
-        if not args.no_cpu_baseline:
-            print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
-            out["cpu_baseline"] = cpu_baseline(args.p)
+    if args.workload in ("default", "tidal"):
+        out.update(tidal_leg(args, I, swe))
+        if cpu is not None:
+            out["cpu_baseline"] = cpu
+        if args.workload == "default" and not args.no_extras:
+            # the other workloads of the method's measurement plan, at the
+            # driver's step counts where they are timed per step
+            out["tsunami"] = guarded("tsunami", lambda: tsunami_leg(256, max(args.steps, 200), max(args.warmup, 5),
+                                                                    I, swe))
+            out["batched"] = guarded("batched", lambda: run_batched(args.instances, max(args.steps, 20), 2))
+            out["served"] = guarded("served", lambda: served_leg(args.served_duration, args.rate,
+                                                                 args.capacity_requests, args.tick_steps, swe))
     elif args.workload == "tsunami":
         n = args.n or 256
-        prob = I.config_c3(n=n)
-        print(f"bench: tsunami {prob.mesh.ne} elements adaptive", file=sys.stderr, flush=True)
-        # FP32 order-partitioned stepping with orders up to 3 is switched off
-        # (see the library's configuration checks): the partitioned scheme
-        # runs in FP64 (the faster of the two here), the order-separated
-        # scheme in FP32 beside it
-        r = run_separated(prob, swe.SWE_FP64, args.steps, args.warmup, separate=2)
-        rs = run_separated(I.config_c3(n=n), swe.SWE_FP32_WB, args.steps, args.warmup, separate=1)
-        out.update(value=r["value"], ms_per_step=r["ms_per_step"], dtype="f64",
-                   config={"workload": f"tsunami: {n}x{n}x2 jittered, shelf 4000-50 m, 2 m hump, "
-                                       "p in {1,2,3} by indicator (1e-3 m), base p=1; order-partitioned "
-                                       "(base elements and each order's listed elements on parallel branches)",
-                           "elements": prob.mesh.ne, "order_fractions": r["order_fractions"]},
-                   separated_fp32={"value": rs["value"], "ms_per_step": rs["ms_per_step"],
-                                   "dtype": "f32 (f64 bathymetry terms)",
-                                   "scheme": "base + corrections on a second stream, joined by epilogues"})
+        r = tsunami_leg(n, args.steps, args.warmup, I, swe)
+        out.update(value=r.pop("value"), ms_per_step=r.pop("ms_per_step"), dtype=r.pop("dtype"),
+                   config={"workload": r.pop("config"), "elements": 2 * n * n}, **r)
     elif args.workload == "dambreak":
         steps = args.steps if args.steps != 500 else 100
         n = args.n or 1024

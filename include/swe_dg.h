@@ -181,8 +181,12 @@ swe_status swe_indicator(swe_ctx *ctx, double t, const double *coef, double *I_o
 /* Last error message of the context (never NULL; empty if none). */
 const char *swe_last_error(const swe_ctx *ctx);
 
-/* Device bytes a context with ne elements, order p_max and precision holds
- * after swe_set_mesh (state, velocity, geometry, order map, scratch). */
+/* Upper bound of the device bytes a batch-ready context (uniform order
+ * p_max, not separated, not adaptive) with ne elements holds on its own
+ * after swe_set_mesh (state, velocity, geometry, order map, scratch, edge
+ * items), and of what it takes resident in an empty batch (its share of the
+ * pools plus the arrays it keeps); the vertex count is bounded by that of a
+ * triangulated polygon with a few holes. */
 int64_t swe_footprint_bytes(int64_t ne, int p_max, int precision);
 
 /* Free everything the context holds; NULL is accepted. */
@@ -200,8 +204,15 @@ void swe_destroy(swe_ctx *ctx);
  * swe_set_mesh / swe_set_bathymetry / swe_set_open_boundary (at most 4
  * constituents) / swe_set_state.  While resident, a member refuses
  * swe_step, swe_set_* and the test hooks; swe_get_state and swe_mass wait
- * for the batch.  Admission is by device footprint (swe_footprint_bytes)
- * against the budget given at creation.
+ * for the batch.  The budget given at creation bounds the device memory the
+ * batch holds: its per-order pools (capacity doubling while the budget
+ * allows, exact growth otherwise; old and new arrays are counted together
+ * while a pool grows), tile lists, vertex pool, and the arrays a member
+ * keeps while resident (vertex and neighbour ids, vertices, flag).  A
+ * member's state buffers are released at admission (the pool holds its
+ * state) and re-created when it is retired; swe_get_state and swe_mass of a
+ * resident member re-create them for the call only.  A pool whose order has
+ * no member left is released.
  * ------------------------------------------------------------------------ */
 typedef struct swe_batch swe_batch;
 
@@ -212,8 +223,9 @@ swe_status swe_batch_create(const swe_config *cfg, int64_t hbm_budget_bytes, int
                             swe_batch **out);
 
 /* Make ctx resident for nsteps steps of size dt from its current state and
- * time.  SWE_ENOMEM if its footprint exceeds the free budget or no slot is
- * free; SWE_EINVAL if ctx does not qualify.  *slot receives the slot. */
+ * time.  SWE_ENOMEM if the pool growth it needs would take the batch beyond
+ * its budget (nothing changes then) or no slot is free; SWE_EINVAL if ctx
+ * does not qualify.  *slot receives the slot. */
 swe_status swe_batch_admit(swe_batch *b, swe_ctx *ctx, int64_t nsteps, double dt, int32_t *slot);
 
 /* Enqueue nsteps steps of every resident instance (each stops at its own
@@ -253,6 +265,7 @@ swe_status swe_batch_set_tile(swe_batch *b, int p, int tile, int shared);
  * any pointer may be NULL. */
 swe_status swe_batch_tile_config(const swe_batch *b, int p, int *tile, int *grid, int *shared);
 
+/* Budget minus the device bytes the batch holds now. */
 int64_t swe_batch_free_bytes(const swe_batch *b);
 int swe_batch_resident(const swe_batch *b);
 const char *swe_batch_last_error(const swe_batch *b);

@@ -159,6 +159,37 @@ void free_mesh(swe_ctx *c)
     c->have_mesh = false;
 }
 
+// A batch member's state buffers (C0, C1, U0, U1, the right-hand-side
+// scratch, edge items) are released while it is resident: its state lives in
+// the batch's pool.  They are re-created (zero-filled) when the state comes
+// back; the edge items when the member leaves the batch.
+void release_state_buffers(swe_ctx *c)
+{
+    drop_step_graph(c);
+    void *q[] = {c->d_C[0], c->d_C[1], c->d_U[0], c->d_U[1], c->d_L, c->d_items, c->d_item_off};
+    for (void *x : q)
+        if (x) (void)hipFree(x);
+    c->d_C[0] = c->d_C[1] = c->d_U[0] = c->d_U[1] = c->d_L = nullptr;
+    c->d_items = nullptr;
+    c->d_item_off = nullptr;
+    c->item_blocks = 0;
+}
+
+swe_status restore_state_buffers(swe_ctx *c)
+{
+    if (c->d_C[0]) return SWE_OK;
+    const size_t w = c->rsz, K = c->K, S = c->stride;
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(c, hipMalloc(&c->d_C[b], w * 3 * K * S));
+        HIP_TRY(c, hipMalloc(&c->d_U[b], w * 2 * K * S));
+        HIP_TRY(c, dzero(c, c->d_C[b], w * 3 * K * S));
+        HIP_TRY(c, dzero(c, c->d_U[b], w * 2 * K * S));
+    }
+    HIP_TRY(c, hipMalloc(&c->d_L, w * 3 * K * S));
+    HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    return SWE_OK;
+}
+
 double xi_hat(const swe_ctx *c, double t)
 {
     double s = 0.0;
@@ -814,6 +845,38 @@ swe_status group_by_lists(swe_ctx *c)
     return SWE_OK;
 }
 
+// Device bytes of the arrays a context keeps as long as it has a mesh: vertex
+// and neighbour ids, neighbour edges, orders, vertices, flag, clock, mass
+// reduction scratch.
+int64_t kept_bytes(int64_t ne, int64_t nv)
+{
+    const int64_t S = (ne + BLOCK - 1) / BLOCK * BLOCK;
+    return 2 * 3 * 4 * S + 2 * S + 32 * nv + 4 + (int64_t)sizeof(InstDesc) + 8 * (S / BLOCK + 2);
+}
+
+// Device bytes of a context's state: C0, C1, U0, U1, the right-hand-side
+// scratch and the shared-flux kernel's edge items (at most 3 per element).
+int64_t state_bytes(int64_t ne, int p, bool fp32)
+{
+    const int64_t S = (ne + BLOCK - 1) / BLOCK * BLOCK;
+    const int64_t K = K_OF[p], w = fp32 ? 4 : 8;
+    int64_t b = (2 * 3 * K + 2 * 2 * K + 3 * K) * S * w;
+    if (stage_sh_supported(p, fp32)) b += 3 * 4 * S + 4 * (S / BLOCK + 1);
+    return b;
+}
+
+// Device bytes of a batch's pool of order p at capacity nc (elements):
+// state and velocity ping-pong buffers, vertex and neighbour ids, neighbour
+// edges, edge items and their block counts, tile list.
+int64_t pool_bytes(int p, bool fp32, int64_t nc)
+{
+    if (nc <= 0) return 0;
+    const int64_t K = K_OF[p], w = fp32 ? 4 : 8;
+    int64_t b = (2 * 3 * K + 2 * 2 * K) * nc * w + 2 * 3 * 4 * nc + nc;
+    if (stage_sh_supported(p, fp32)) b += 3 * 4 * nc + 4 * (nc / BLOCK);
+    return b + (int64_t)sizeof(int2) * (nc / 64 + 1);
+}
+
 }  // namespace
 
 extern "C" {
@@ -905,20 +968,16 @@ int swe_num_modes(const swe_ctx *c) { return c ? c->K : 0; }
 int64_t swe_footprint_bytes(int64_t ne, int p_max, int precision)
 {
     if (ne <= 0 || p_max < 0 || p_max > 3) return -1;
+    const bool fp32 = precision == SWE_FP32_WB;
     const int64_t S = (ne + BLOCK - 1) / BLOCK * BLOCK;
-    const int64_t K = K_OF[p_max], w = precision == SWE_FP32_WB ? 4 : 8;
-    const int64_t nv_est = ne + 2 * (int64_t)std::sqrt((double)ne) + 2;   // structured-like bound
-    int64_t b = 0;
-    b += 2 * 3 * K * S * w;          // C0, C1
-    b += 2 * 2 * K * S * w;          // U0, U1
-    b += 3 * K * S * w;              // rhs scratch
-    b += 3 * S * 4 * 2;              // ev, nb
-    b += S * 2;                      // nbk, p
-    b += nv_est * 32;                // vertices
-    b += (S / BLOCK + 1) * 8 + 64;   // reduction scratch, flag
-    if (stage_sh_supported(p_max, precision == SWE_FP32_WB))
-        b += S * 3 * 4 + (S / BLOCK + 1) * 4;   // edge items of the shared-flux kernel (at most 3 per element)
-    return b;
+    // vertices of a triangulated polygon: nv <= ne + 2; the margin covers a few holes
+    const int64_t nv_est = ne + 2 * (int64_t)std::sqrt((double)ne) + 2;
+    const int64_t kept = kept_bytes(ne, nv_est);
+    // on its own: every array of the context; resident in an empty batch: its
+    // share of the pool of its order, of the vertex pool, and what it keeps
+    const int64_t alone = kept + state_bytes(ne, p_max, fp32);
+    const int64_t resident = kept + pool_bytes(p_max, fp32, S) + 32 * nv_est;
+    return std::max(alone, resident);
 }
 
 swe_status swe_set_mesh(swe_ctx *c, int64_t nv, const double *vxy, int64_t ne, const int32_t *tri,
@@ -1307,12 +1366,14 @@ swe_status swe_get_state(swe_ctx *c, double *coef, double *t_out)
     if (c->batch) {
         swe_status st = swe_batch_sync(c->batch);
         if (st != SWE_OK && st != SWE_ESTATE) return fail(c, st, "batch sync failed");
-        c->t = batch_member_time(c->batch, c->slot);
+        c->t = batch_member_time(c->batch, c->slot);   // re-creates the state buffers for the copy
+        if (!c->d_C[0]) return fail(c, SWE_EDEVICE, "state of the resident member could not be read");
     }
     HIP_TRY(c, hipStreamSynchronize(c->s_base));
     HIP_TRY(c, hipStreamSynchronize(c->s_corr));
     swe_status st = download(c, c->d_C[0], 3, coef, false);
     if (t_out) *t_out = c->t;
+    if (c->batch) release_state_buffers(c);   // while resident the pool holds the state
     return st;
 }
 
@@ -1324,10 +1385,12 @@ swe_status swe_mass(swe_ctx *c, double *out)
         swe_status st = swe_batch_sync(c->batch);
         if (st != SWE_OK && st != SWE_ESTATE) return fail(c, st, "batch sync failed");
         c->t = batch_member_time(c->batch, c->slot);   // also brings the state over from the pool
+        if (!c->d_C[0]) return fail(c, SWE_EDEVICE, "state of the resident member could not be read");
     }
     HIP_TRY(c, launch_mass(view(c), c->fp32, c->d_C[0], c->d_part, c->d_mass, c->s_base));
     HIP_TRY(c, hipMemcpyAsync(out, c->d_mass, sizeof(double), hipMemcpyDeviceToHost, c->s_base));
     HIP_TRY(c, hipStreamSynchronize(c->s_base));
+    if (c->batch) release_state_buffers(c);
     return SWE_OK;
 }
 
@@ -1419,6 +1482,18 @@ swe_status swe_indicator(swe_ctx *c, double t, const double *coef, double *I_out
 struct RangeAlloc {
     std::vector<std::pair<int64_t, int64_t>> free;   // (start, length), sorted by start
     int64_t cap = 0;
+    // where take(n) would place n elements, or -1 (nothing changes)
+    int64_t find(int64_t n) const
+    {
+        for (const auto &r : free)
+            if (r.second >= n) return r.first;
+        return -1;
+    }
+    void clear()
+    {
+        free.clear();
+        cap = 0;
+    }
     int64_t take(int64_t n)
     {
         for (size_t k = 0; k < free.size(); ++k)
@@ -1453,13 +1528,18 @@ struct swe_batch {
     swe_config cfg{};
     bool fp32 = false;
     size_t w = 8;
-    int64_t budget = 0, used = 0;
+    int64_t budget = 0;
+    // device bytes the batch holds: its pools (with growth slack), tile
+    // lists, vertex pool and the arrays its members keep while resident;
+    // never above budget, also while a pool grows (old and new arrays
+    // coexist during the copy)
+    int64_t alloc = 0;
     int cap = 0;
     hipStream_t s = nullptr;
     bool own_s = false;
     struct Member {
         swe_ctx *ctx = nullptr;
-        int64_t bytes = 0;
+        int64_t kept = 0;              // device bytes the member context keeps while resident
         int order = 0;
         int64_t first = 0, span = 0, vbase = 0, nv = 0;
         bool no_items = false;         // the context has no edge items (shared-flux kernel unusable)
@@ -1514,13 +1594,23 @@ void drop_graph(swe_batch *b)
     b->graph_orders = -1;
 }
 
-// Grow the pool of order p to hold at least need elements (capacity doubles).
-swe_status grow_pool(swe_batch *b, int p, int64_t need)
+// Capacity of a pool that has to hold need elements: twice the current one
+// when the budget allows it, else need itself; 0 when even that does not
+// fit.  room is what the pool's arrays may take (the old arrays stay
+// allocated while they are copied, so the whole new size counts).
+template <typename F>
+int64_t grown_capacity(int64_t cap, int64_t need, int64_t room, F bytes)
+{
+    const int64_t twice = std::max(need, 2 * cap);
+    if (bytes(twice) <= room) return twice;
+    return bytes(need) <= room ? need : 0;
+}
+
+// Grow the pool of order p to capacity nc (a multiple of POOL_ALIGN).
+swe_status grow_pool(swe_batch *b, int p, int64_t nc)
 {
     swe_batch::Pool &P = b->pool[p];
-    int64_t nc = std::max<int64_t>(P.ra.cap ? P.ra.cap : 65536, 65536);
-    while (nc < need) nc *= 2;
-    if (nc == P.ra.cap) return SWE_OK;
+    if (nc <= P.ra.cap) return SWE_OK;
     const int64_t K = K_OF[p];
     if ((int64_t)3 * K * nc * (int64_t)b->w > (int64_t)INT32_MAX)
         return bfail(b, SWE_EUNSUPPORTED, "pool of one order would exceed 2 GiB per array");
@@ -1555,6 +1645,7 @@ swe_status grow_pool(swe_batch *b, int p, int64_t need)
         void *old[] = {P.v.C0, P.v.C1, P.v.U0, P.v.U1, P.v.ev, P.v.nb, P.v.nbk, P.v.items, P.v.nitems};
         for (void *q : old) (void)hipFree(q);
     }
+    b->alloc += pool_bytes(p, b->fp32, nc) - pool_bytes(p, b->fp32, oc);
     P.v = v;
     P.ra.grow(nc);
     // tile list capacity follows the pool: at most one tile per 64 elements
@@ -1568,11 +1659,10 @@ swe_status grow_pool(swe_batch *b, int p, int64_t need)
     return SWE_OK;
 }
 
-swe_status grow_vertices(swe_batch *b, int64_t need)
+// Grow the vertex pool to capacity nc.
+swe_status grow_vertices(swe_batch *b, int64_t nc)
 {
-    int64_t nc = std::max<int64_t>(b->vra.cap ? b->vra.cap : 65536, 65536);
-    while (nc < need) nc *= 2;
-    if (nc == b->vra.cap) return SWE_OK;
+    if (nc <= b->vra.cap) return SWE_OK;
     double4 *v = nullptr;
     BHIP_TRY(b, hipMalloc(&v, sizeof(double4) * nc));
     if (b->vra.cap) {
@@ -1580,10 +1670,37 @@ swe_status grow_vertices(swe_batch *b, int64_t need)
         BHIP_TRY(b, hipStreamSynchronize(b->s));
         (void)hipFree(b->d_vtx);
     }
+    b->alloc += (int64_t)sizeof(double4) * (nc - b->vra.cap);
     b->d_vtx = v;
     b->vra.grow(nc);
     drop_graph(b);
     return SWE_OK;
+}
+
+// Free the pool of order p (no member of that order is resident).
+void release_pool(swe_batch *b, int p)
+{
+    swe_batch::Pool &P = b->pool[p];
+    if (P.ra.cap == 0) return;
+    void *q[] = {P.v.C0, P.v.C1, P.v.U0, P.v.U1, P.v.ev, P.v.nb, P.v.nbk, P.v.items, P.v.nitems, b->d_tiles[p]};
+    for (void *x : q)
+        if (x) (void)hipFree(x);
+    b->alloc -= pool_bytes(p, b->fp32, P.ra.cap);
+    P.v = PoolView{};
+    P.ra.clear();
+    b->d_tiles[p] = nullptr;
+    b->tile_cap[p] = 0;
+    drop_graph(b);
+}
+
+void release_vertices(swe_batch *b)
+{
+    if (b->vra.cap == 0) return;
+    (void)hipFree(b->d_vtx);
+    b->alloc -= (int64_t)sizeof(double4) * b->vra.cap;
+    b->d_vtx = nullptr;
+    b->vra.clear();
+    drop_graph(b);
 }
 
 // Order p runs the shared-flux batch kernel: chosen for it, and every resident
@@ -1740,13 +1857,15 @@ swe_status get_desc(swe_batch *b, int i)
     return SWE_OK;
 }
 
-// copy a resident instance's state and velocity from the pool into its context
+// copy a resident instance's state and velocity from the pool into its
+// context (whose state buffers are re-created for it)
 swe_status pull_state(swe_batch *b, int i)
 {
     const swe_batch::Member &m = b->mem[i];
     swe_ctx *c = m.ctx;
     const swe_batch::Pool &P = b->pool[m.order];
     const size_t w = b->w, K = c->K;
+    if (swe_status st = restore_state_buffers(c)) return bfail(b, st, c->err);
     BHIP_TRY(b, hipMemcpy2DAsync(c->d_C[0], w * c->stride, static_cast<char *>(P.v.C0) + w * m.first, w * P.v.cap,
                                  w * c->ne, 3 * K, hipMemcpyDeviceToDevice, b->s));
     BHIP_TRY(b, hipMemcpy2DAsync(c->d_U[0], w * c->stride, static_cast<char *>(P.v.U0) + w * m.first, w * P.v.cap,
@@ -1818,11 +1937,13 @@ void swe_batch_destroy(swe_batch *b)
     if (b->s) (void)hipStreamSynchronize(b->s);
     for (int i = 0; i < b->cap; ++i)
         if (b->mem[i].ctx) {
+            swe_ctx *c = b->mem[i].ctx;
             (void)pull_state(b, i);
             (void)get_desc(b, i);
-            b->mem[i].ctx->t = b->h_inst[i].t;
-            b->mem[i].ctx->batch = nullptr;
-            b->mem[i].ctx->slot = -1;
+            c->t = b->h_inst[i].t;
+            c->batch = nullptr;
+            c->slot = -1;
+            (void)build_items(c);
         }
     drop_graph(b);
     std::vector<void *> ptrs = {b->d_inst, b->d_flags, b->d_ntiles, b->d_vtx};
@@ -1839,7 +1960,7 @@ void swe_batch_destroy(swe_batch *b)
 }
 
 const char *swe_batch_last_error(const swe_batch *b) { return b ? b->err.c_str() : "null batch"; }
-int64_t swe_batch_free_bytes(const swe_batch *b) { return b ? b->budget - b->used : 0; }
+int64_t swe_batch_free_bytes(const swe_batch *b) { return b ? b->budget - b->alloc : 0; }
 
 int swe_batch_resident(const swe_batch *b)
 {
@@ -1858,29 +1979,50 @@ swe_status swe_batch_admit(swe_batch *b, swe_ctx *c, int64_t nsteps, double dt, 
     if (c->cfg.separate || c->cfg.adapt || !c->uniform || c->d_src || c->failed)
         return bfail(b, SWE_EINVAL, "batch members need one uniform order, no separation, adaptivity or source");
     if (c->ncon > 4) return bfail(b, SWE_EINVAL, "batch members support at most 4 forcing constituents");
-    const int64_t bytes = swe_footprint_bytes(c->ne, c->cfg.p_max, c->cfg.precision);
-    if (bytes > b->budget - b->used) return bfail(b, SWE_ENOMEM, "footprint exceeds the free budget");
     int i = 0;
     while (i < b->cap && b->mem[i].ctx) ++i;
     if (i == b->cap) return bfail(b, SWE_ENOMEM, "no free slot");
     BHIP_TRY(b, hipStreamSynchronize(c->s_base));
     BHIP_TRY(b, hipStreamSynchronize(c->s_corr));
     BHIP_TRY(b, hipStreamSynchronize(b->s));
+    // what admission takes from the budget, decided before anything changes:
+    // the arrays the member keeps, growth of its order's pool and of the
+    // vertex pool (each counted whole while its old arrays are copied)
     const int p = c->cfg.p_max;
     swe_batch::Pool &P = b->pool[p];
+    const int64_t kept = kept_bytes(c->ne, c->nv);
     const int64_t span = (c->ne + POOL_ALIGN - 1) / POOL_ALIGN * POOL_ALIGN;
-    int64_t first = P.ra.take(span);
-    if (first < 0) {
-        swe_status st = grow_pool(b, p, P.ra.cap + span);
-        if (st) return st;
-        first = P.ra.take(span);
-        if (first < 0) return bfail(b, SWE_ENOMEM, "pool allocation failed");
+    int64_t alloc = b->alloc + kept;
+    int64_t pool_cap = 0, vtx_cap = 0;
+    if (P.ra.find(span) < 0) {
+        const int64_t old = pool_bytes(p, b->fp32, P.ra.cap);
+        // (a capacity whose coefficient arrays pass 2 GiB is never chosen)
+        const int64_t max_cap = (int64_t)INT32_MAX / (3 * K_OF[p] * (int64_t)b->w);
+        pool_cap = grown_capacity(P.ra.cap, P.ra.cap + span, b->budget - alloc, [&](int64_t nc) {
+            return nc <= max_cap ? pool_bytes(p, b->fp32, nc) : INT64_MAX;
+        });
+        if (pool_cap == 0) return bfail(b, SWE_ENOMEM, "the member does not fit the budget");
+        alloc += pool_bytes(p, b->fp32, pool_cap) - old;
     }
-    int64_t vbase = b->vra.take(c->nv);
-    if (vbase < 0) {
-        swe_status st = grow_vertices(b, b->vra.cap + c->nv);
-        if (st) { P.ra.give(first, span); return st; }
-        vbase = b->vra.take(c->nv);
+    if (b->vra.find(c->nv) < 0) {
+        vtx_cap = grown_capacity(b->vra.cap, b->vra.cap + c->nv, b->budget - alloc,
+                                 [](int64_t nc) { return 32 * nc; });
+        if (vtx_cap == 0) return bfail(b, SWE_ENOMEM, "the member does not fit the budget");
+    }
+    if (pool_cap) {
+        swe_status st = grow_pool(b, p, pool_cap);
+        if (st) return st;
+    }
+    if (vtx_cap) {
+        swe_status st = grow_vertices(b, vtx_cap);
+        if (st) return st;
+    }
+    const int64_t first = P.ra.take(span);
+    const int64_t vbase = b->vra.take(c->nv);
+    if (first < 0 || vbase < 0) {
+        if (first >= 0) P.ra.give(first, span);
+        if (vbase >= 0) b->vra.give(vbase, c->nv);
+        return bfail(b, SWE_ENOMEM, "pool allocation failed");
     }
     const size_t w = b->w, K = c->K;
     BHIP_TRY(b, hipMemcpy2DAsync(static_cast<char *>(P.v.C0) + w * first, w * P.v.cap, c->d_C[0], w * c->stride,
@@ -1916,7 +2058,7 @@ swe_status swe_batch_admit(swe_batch *b, swe_ctx *c, int64_t nsteps, double dt, 
     if (st) return st;
     swe_batch::Member &m = b->mem[i];
     m.ctx = c;
-    m.bytes = bytes;
+    m.kept = kept;
     m.order = p;
     m.first = first;
     m.span = span;
@@ -1924,7 +2066,9 @@ swe_status swe_batch_admit(swe_batch *b, swe_ctx *c, int64_t nsteps, double dt, 
     m.nv = c->nv;
     m.no_items = no_items;
     if (no_items && b->no_items[p]++ == 0) drop_graph(b);   // the order falls back to the gather kernel
-    b->used += bytes;
+    BHIP_TRY(b, hipStreamSynchronize(b->s));   // the copies out of the member's buffers are done
+    release_state_buffers(c);
+    b->alloc += kept;
     c->batch = b;
     c->slot = i;
     if (per_instance(b, p)) drop_graph(b);   // the step graph launches each such instance
@@ -2008,12 +2152,23 @@ swe_status swe_batch_retire(swe_batch *b, int32_t slot)
     if (st) return st;
     if (per_instance(b, m.order)) drop_graph(b);
     if (m.no_items && --b->no_items[m.order] == 0) drop_graph(b);
-    b->pool[m.order].ra.give(m.first, m.span);
+    const int order = m.order;
+    b->pool[order].ra.give(m.first, m.span);
     b->vra.give(m.vbase, m.nv);
-    b->used -= m.bytes;
+    b->alloc -= m.kept;
     m = swe_batch::Member();
     c->batch = nullptr;
     c->slot = -1;
+    st = build_items(c);   // the context can step on its own again
+    if (st) return bfail(b, st, c->err);
+    // an order (or the whole batch) without members holds no pool
+    bool any = false, any_order = false;
+    for (const auto &q : b->mem) {
+        any = any || q.ctx;
+        any_order = any_order || (q.ctx && q.order == order);
+    }
+    if (!any_order) release_pool(b, order);
+    if (!any) release_vertices(b);
     return upload_tiles(b);
 }
 

@@ -2,9 +2,12 @@
 
 Requests arrive over time (each: a mesh size, an order, a step count and a
 forcing kind).  Host threads prepare each request's context (mesh upload,
-bathymetry, initial state) as soon as it arrives; the scheduler admits
-prepared requests into the resident batch while their device footprint fits
-the budget, advances every resident instance together (one step graph per
+bathymetry, initial state) once it has arrived and the prepared contexts'
+footprints fit the staging budget (a prepared context holds device memory
+until it is admitted); the scheduler admits prepared requests into the
+resident batch while their device footprint fits the budget (the batch
+itself refuses any admission that would take its own device memory beyond
+the budget), advances every resident instance together (one step graph per
 tick, each instance at its own time step and step budget), retires finished
 instances (state copied back to the host) and admits the next ones at every
 tick boundary.  Latency is measured from arrival to the completed copy of the
@@ -18,6 +21,7 @@ tested without a GPU.
 """
 from __future__ import annotations
 
+import threading
 import time
 from collections import deque
 from concurrent.futures import ThreadPoolExecutor
@@ -147,14 +151,16 @@ class GpuExecutor(Executor):
 
 class PlainExecutor(Executor):
     """The plain solver: one request on the GPU at a time, unbatched, each
-    stage one ordinary launch over that request's mesh (FIFO queue)."""
+    stage one ordinary launch over that request's mesh (FIFO queue).  Each
+    context runs on its own streams, so preparing the next requests does not
+    queue behind (or ahead of) the running one."""
 
-    def __init__(self, precision: int, stream=None, keep_state: bool = True,
+    def __init__(self, precision: int, budget_bytes: int = 64 << 30, keep_state: bool = True,
                  init_state: Optional[Callable] = None):
         from . import swe
         self.swe = swe
         self.precision = precision
-        self.stream = stream
+        self._budget = budget_bytes
         self.keep_state = keep_state
         self.init_state = init_state
         self.cur: Dict[int, list] = {}
@@ -164,11 +170,11 @@ class PlainExecutor(Executor):
         return self.swe.swe_footprint_bytes(req.elements, req.spec.p, self.precision)
 
     def budget(self):
-        return 1 << 62
+        return self._budget
 
     def prepare(self, req):
         prob = I.request_problem(req.spec)
-        ctx = self.swe.context_for(prob, precision=self.precision, stream_base=self.stream)
+        ctx = self.swe.context_for(prob, precision=self.precision)
         _initial_state(ctx, prob, req, self.init_state)
         return ctx, prob.dt(), req.spec.steps, 3 * I.K_OF_P[req.spec.p] * prob.mesh.ne
 
@@ -214,6 +220,7 @@ class ServeStats:
     results: List[Result] = field(default_factory=list)
     wall: float = 0.0
     max_used: int = 0
+    max_staged: int = 0
     ticks: int = 0
 
     def summary(self) -> dict:
@@ -225,54 +232,69 @@ class ServeStats:
                 "solves_per_s": len(ok) / self.wall if self.wall > 0 else 0.0,
                 "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
                 "dof_updates_per_s": dof / self.wall if self.wall > 0 else 0.0,
-                "wall_s": self.wall, "max_resident_bytes": self.max_used, "ticks": self.ticks}
+                "wall_s": self.wall, "max_resident_bytes": self.max_used, "max_staged_bytes": self.max_staged,
+                "ticks": self.ticks}
 
 
 def serve(requests: List[Request], ex: Executor, tick_steps: int = 50, prep_threads: int = 8,
           clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
-          on_tick: Optional[Callable[[float, int], None]] = None) -> ServeStats:
-    """Run the request trace to completion and return per-request results."""
+          on_tick: Optional[Callable[[float, int], None]] = None,
+          stage_budget: Optional[int] = None) -> ServeStats:
+    """Run the request trace to completion and return per-request results.
+
+    stage_budget bounds the summed footprints of the requests being prepared
+    or prepared and waiting for admission (their contexts hold device memory
+    beside the resident batch); default a quarter of the executor's budget.
+    One request is always let through, so any request can make progress."""
     stats = ServeStats()
     pending = deque(sorted(requests, key=lambda r: r.arrival))
-    preparing: deque = deque()                 # (request, future) in arrival order
+    preparing: deque = deque()                 # (request, future, footprint) in arrival order
     resident: Dict[int, tuple] = {}            # slot -> (request, admitted time, footprint)
-    used = 0
+    used = staged = 0
+    stage_cap = ex.budget() // 4 if stage_budget is None else stage_budget
     t0 = clock()
     pool = ThreadPoolExecutor(max_workers=prep_threads)
     try:
         while pending or preparing or resident:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
+                fp = ex.footprint(pending[0])
+                if preparing and staged + fp > stage_cap:
+                    break                       # wait until admissions free staging room
                 r = pending.popleft()
-                preparing.append((r, pool.submit(ex.prepare, r)))
+                preparing.append((r, pool.submit(ex.prepare, r), fp))
+                staged += fp
+                stats.max_staged = max(stats.max_staged, staged)
             # admission at the tick boundary, FIFO: the head waits until it fits
             while preparing and preparing[0][1].done():
-                r, fut = preparing[0]
-                fp = ex.footprint(r)
+                r, fut, fp = preparing[0]
                 err = fut.exception()
                 if err is not None:
                     preparing.popleft()
+                    staged -= fp
                     stats.results.append(Result(r.rid, False, r.arrival, now, clock() - t0, 0.0, error=str(err)))
                     continue
                 if used + fp > ex.budget():
                     if not resident:          # can never fit
                         preparing.popleft()
+                        staged -= fp
                         ex.discard(fut.result())
                         stats.results.append(Result(r.rid, False, r.arrival, now, clock() - t0, 0.0,
                                                     error="footprint exceeds the budget"))
                         continue
                     break
-                preparing.popleft()
                 try:
                     slot = ex.admit(fut.result())
-                except Exception as e:          # e.g. no free slot: retry after the next retirement
-                    preparing.appendleft((r, fut))
+                except Exception as e:          # no free slot or no room in the pools: retry after a retirement
                     if not resident:
                         preparing.popleft()
+                        staged -= fp
                         ex.discard(fut.result())
                         stats.results.append(Result(r.rid, False, r.arrival, now, clock() - t0, 0.0, error=str(e)))
                         continue
                     break
+                preparing.popleft()
+                staged -= fp
                 resident[slot] = (r, clock() - t0, fp)
                 used += fp
                 stats.max_used = max(stats.max_used, used)
@@ -316,6 +338,9 @@ class FakeExecutor(Executor):
         self.used = 0
         self.sizes: Dict[int, int] = {}
         self.discarded: List[int] = []
+        self.prepared = 0              # footprints of prepared requests not yet admitted or discarded
+        self.max_prepared = 0
+        self._lock = threading.Lock()
 
     def footprint(self, req):
         return req.elements * self.bpe
@@ -326,11 +351,16 @@ class FakeExecutor(Executor):
     def prepare(self, req):
         if req.spec.steps <= 0:
             raise ValueError("no steps requested")
+        with self._lock:
+            self.prepared += self.footprint(req)
+            self.max_prepared = max(self.max_prepared, self.prepared)
         return req
 
     def admit(self, req):
         fp = self.footprint(req)
         assert self.used + fp <= self._budget, "admitted beyond the budget"
+        with self._lock:
+            self.prepared -= fp
         s = self.next_slot
         self.next_slot += 1
         self.left[s] = req.spec.steps
@@ -358,3 +388,5 @@ class FakeExecutor(Executor):
 
     def discard(self, handle):
         self.discarded.append(handle.rid)
+        with self._lock:
+            self.prepared -= self.footprint(handle)

@@ -59,3 +59,25 @@ def test_tick_granularity():
     ex = FakeExecutor(10**9)
     st = serve([Request(0, spec)], ex, tick_steps=5)
     assert st.ticks == 5 and st.results[0].ok
+
+
+def test_staging_budget_bounds_prepared_requests():
+    """Prepared requests hold device memory until admitted: their summed
+    footprints stay within the staging budget (one request is always let
+    through), and every request still completes."""
+    reqs = small_trace(60, seed=3, steps=(20, 60))
+    for r in reqs:
+        r.spec.arrival = 0.0                         # all at once: preparation would run far ahead
+    budget = 100 * 15000
+    stage = 100 * 6000
+    ex = FakeExecutor(budget, bytes_per_element=100, step_time=2e-5)
+    st = serve(reqs, ex, tick_steps=5, prep_threads=8, stage_budget=stage)
+    assert all(r.ok for r in st.results)
+    biggest = max(ex.footprint(r) for r in reqs)
+    assert ex.max_prepared <= max(stage, biggest)
+    assert st.max_staged <= max(stage, biggest)
+    assert ex.prepared == 0 and ex.used == 0
+    # without the bound, preparation runs ahead of admission
+    ex2 = FakeExecutor(budget, bytes_per_element=100, step_time=2e-5)
+    serve(reqs, ex2, tick_steps=5, prep_threads=8, stage_budget=1 << 60)
+    assert ex2.max_prepared > stage
