@@ -454,11 +454,14 @@ def run_batched(count, steps, warmup):
         return ev0.elapsed_time(ev1)
 
     def contexts(prec):
-        out = []
-        for p in probs:
+        out, t0 = [], time.perf_counter()
+        for i, p in enumerate(probs):
             c = swe.context_for(p, precision=prec, stream_base=stream.cuda_stream)
             c.set_state_fn(p.ic)
             out.append(c)
+            if i % 16 == 15:
+                print(f"bench: {i + 1} contexts (precision {prec}) in {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
         return out
 
     def batched(prec, ctxs):
