@@ -162,6 +162,20 @@ swe_status swe_get_state(swe_ctx *ctx, double *coef_out, double *t_out);
  * in a fixed order (deterministic). */
 swe_status swe_mass(swe_ctx *ctx, double *out);
 
+/* swe_mass for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same deterministic FP64 reduction over the current state, enqueued on the
+ * context's base stream without allocating, copying, filling memory or
+ * synchronising; the result (one double, the same bits as swe_mass) is
+ * written to the device pointer d_out once the stream reaches it.  The
+ * reduction's partial sums live in one fixed device array of 16384 doubles
+ * per GPU (128 KiB, held until the process ends), so the mesh may have at
+ * most 4,194,304 elements (SWE_EINVAL beyond, before anything is enqueued).
+ * Calls that overlap on one GPU (other contexts' streams included) share
+ * that array and race; serialise them.  SWE_EINVAL for a context resident in
+ * a batch. */
+swe_status swe_mass_noalloc(swe_ctx *ctx, double *d_out);
+
 /* Test hooks: the semi-discrete right-hand side L(c, t) of (variational_disc_1)
  * (the time derivative of the coefficients) and the velocity coefficients
  * u_out[ne][2][K] of (variational_disc_2) for the given host state.  They do

@@ -911,6 +911,8 @@ swe_status swe_create(const swe_config *cfg, swe_ctx **out)
         return SWE_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SWE_EDEVICE;
+    // the fixed array of swe_mass_noalloc: its address on this device, taken at set-up
+    if (mass_scratch(nullptr) != hipSuccess) return SWE_EDEVICE;
     swe_ctx *c = new (std::nothrow) swe_ctx();
     if (!c) return SWE_ENOMEM;
     c->cfg = *cfg;
@@ -1391,6 +1393,18 @@ swe_status swe_mass(swe_ctx *c, double *out)
     HIP_TRY(c, hipMemcpyAsync(out, c->d_mass, sizeof(double), hipMemcpyDeviceToHost, c->s_base));
     HIP_TRY(c, hipStreamSynchronize(c->s_base));
     if (c->batch) release_state_buffers(c);
+    return SWE_OK;
+}
+
+swe_status swe_mass_noalloc(swe_ctx *c, double *d_out)
+{
+    if (!c || !d_out) return SWE_EINVAL;
+    if (c->batch) return fail(c, SWE_EINVAL, "context is resident in a batch (its state lives in the batch's pool)");
+    if (!c->have_mesh) return fail(c, SWE_EINVAL, "set_mesh first");
+    if (mass_partials((int)c->ne) > MASS_SCRATCH_PARTIALS)
+        return fail(c, SWE_EINVAL, "swe_mass_noalloc takes at most " + std::to_string((int64_t)MASS_SCRATCH_PARTIALS * BLOCK) +
+                                       " elements; this mesh has " + std::to_string(c->ne));
+    HIP_TRY(c, launch_mass_noalloc(view(c), c->fp32, c->d_C[0], d_out, c->s_base));
     return SWE_OK;
 }
 

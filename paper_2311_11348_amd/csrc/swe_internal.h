@@ -159,6 +159,14 @@ hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, i
                             signed char *p_new, hipStream_t s);
 hipError_t launch_mass(const MeshView &m, bool fp32, const void *C, double *partial,
                        double *out, hipStream_t s);
+// The same reduction with its partial sums in a fixed device array of
+// MASS_SCRATCH_PARTIALS doubles (ne <= MASS_SCRATCH_PARTIALS * BLOCK), no
+// allocation; the result goes to the device pointer out.
+constexpr int MASS_SCRATCH_PARTIALS = 16384;
+hipError_t launch_mass_noalloc(const MeshView &m, bool fp32, const void *C, double *out, hipStream_t s);
+// Device address of that array on the current device (resolved once per
+// device, kept for the process); out may be null.
+hipError_t mass_scratch(double **out);
 int mass_partials(int ne);
 hipError_t launch_batch_stage(int p, bool fp32, int mode, int tile, const BatchArgs &b, int grid, Sink &k);
 hipError_t launch_batch_clock(InstDesc *inst, const int *flags, int n, Sink &k);

@@ -24,6 +24,7 @@
 #include "swe_internal.h"
 #include "swe_tables.h"
 
+#include <mutex>
 #include <type_traits>
 
 namespace swe {
@@ -2129,6 +2130,54 @@ __global__ void k_inst_set(InstDesc *inst, InstDesc v)
 hipError_t launch_inst_set(InstDesc *inst, const InstDesc &v, hipStream_t s)
 {
     hipLaunchKernelGGL(k_inst_set, dim3(1), dim3(64), 0, s, inst, v);
+    return hipGetLastError();
+}
+
+// Partial sums of the mass reduction for callers that cannot allocate: a
+// fixed array on each device (the library holds it until the process ends),
+// enough for MASS_SCRATCH_PARTIALS blocks of 256 elements.  Host code never
+// passes the array's name to a kernel (on the host it only stands in for the
+// symbol): it takes the device address once per device with that device
+// current and uses that.
+static __device__ __align__(256) double scratch[MASS_SCRATCH_PARTIALS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+double *scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t mass_scratch(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    if (out) *out = scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_mass_noalloc(const MeshView &m, bool fp32, const void *C, double *out, hipStream_t s)
+{
+    const int nb = mass_partials(m.ne);
+    if (nb <= 0 || nb > MASS_SCRATCH_PARTIALS) return hipErrorInvalidValue;
+    double *part = nullptr;
+    hipError_t e = mass_scratch(&part);
+    if (e != hipSuccess) return e;
+    // every partial the final pass reads is written by the first pass: nothing to clear
+    if (fp32)
+        hipLaunchKernelGGL(k_mass_partial<float>, dim3(nb), dim3(BLOCK), 0, s, m, static_cast<const float *>(C), part);
+    else
+        hipLaunchKernelGGL(k_mass_partial<double>, dim3(nb), dim3(BLOCK), 0, s, m, static_cast<const double *>(C),
+                           part);
+    hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(BLOCK), 0, s, part, nb, out);
     return hipGetLastError();
 }
 

@@ -67,6 +67,7 @@ def lib() -> C.CDLL:
         "swe_sync": (C.c_int, [vp]),
         "swe_get_state": (C.c_int, [vp, dp, dp]),
         "swe_mass": (C.c_int, [vp, dp]),
+        "swe_mass_noalloc": (C.c_int, [vp, vp]),
         "swe_rhs": (C.c_int, [vp, C.c_double, dp, dp]),
         "swe_usolve": (C.c_int, [vp, dp, dp]),
         "swe_rhs_split": (C.c_int, [vp, C.c_double, dp, dp, dp]),
@@ -242,6 +243,11 @@ class Context:
         m = C.c_double()
         self._check(self.L.swe_mass(self.h, C.byref(m)))
         return m.value
+
+    def mass_noalloc(self, d_out: int):
+        """Enqueue the mass reduction without allocating; the result lands in
+        the device double at address d_out once the context's stream gets there."""
+        self._check(self.L.swe_mass_noalloc(self.h, C.c_void_p(int(d_out))))
 
     # -- test hooks
     def rhs(self, t, coef):
