@@ -213,10 +213,16 @@ void swe_destroy(swe_ctx *ctx);
  * the device, so one step graph (built from kernel nodes, no stream capture,
  * and replayed) serves any resident set.  Other host threads may create and
  * fill contexts while a batch runs.
- * Members are ordinary contexts (precision equal to the batch's, one uniform
- * order p_max, not separated, not adaptive, no extra source) prepared with
- * swe_set_mesh / swe_set_bathymetry / swe_set_open_boundary (at most 4
- * constituents) / swe_set_state.  While resident, a member refuses
+ * Members are ordinary contexts (precision equal to the batch's, the fused
+ * scheme separate = 0, no extra source) prepared with swe_set_mesh /
+ * swe_set_bathymetry / swe_set_open_boundary (at most 4 constituents) /
+ * swe_set_order / swe_set_state: one uniform order, a static per-element
+ * order map, or orders the indicator re-chooses before every step (adapt).
+ * A member lives in the pool of its p_max; a member with per-element orders
+ * is stepped by the element-gather kernel with each element's modes masked
+ * by its order (its order class then uses that kernel for every member),
+ * and an indicator-driven member's order update runs over all such members
+ * of the class in one launch before the stages.  While resident, a member refuses
  * swe_step, swe_set_* and the test hooks; swe_get_state and swe_mass wait
  * for the batch.  The budget given at creation bounds the device memory the
  * batch holds: its per-order pools (capacity doubling while the budget

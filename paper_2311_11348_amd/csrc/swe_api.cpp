@@ -872,9 +872,9 @@ int64_t pool_bytes(int p, bool fp32, int64_t nc)
 {
     if (nc <= 0) return 0;
     const int64_t K = K_OF[p], w = fp32 ? 4 : 8;
-    int64_t b = (2 * 3 * K + 2 * 2 * K) * nc * w + 2 * 3 * 4 * nc + nc;
+    int64_t b = (2 * 3 * K + 2 * 2 * K) * nc * w + 2 * 3 * 4 * nc + 3 * nc;
     if (stage_sh_supported(p, fp32)) b += 3 * 4 * nc + 4 * (nc / BLOCK);
-    return b + (int64_t)sizeof(int2) * (nc / 64 + 1);
+    return b + (int64_t)sizeof(int2) * (nc / 64 + 1 + nc / BLOCK + 1);
 }
 
 }  // namespace
@@ -1553,6 +1553,8 @@ struct swe_batch {
     bool own_s = false;
     struct Member {
         swe_ctx *ctx = nullptr;
+        bool mixed = false;            // per-element orders: a static order map or indicator-driven
+        bool adapt = false;            // indicator-driven orders
         int64_t kept = 0;              // device bytes the member context keeps while resident
         int order = 0;
         int64_t first = 0, span = 0, vbase = 0, nv = 0;
@@ -1569,6 +1571,12 @@ struct swe_batch {
     int2 *d_tiles[4] = {nullptr, nullptr, nullptr, nullptr};
     int tile_cap[4] = {0, 0, 0, 0};
     int *d_ntiles = nullptr;
+    // 256-element tiles of the indicator-driven members of each order class
+    int2 *d_atiles[4] = {nullptr, nullptr, nullptr, nullptr};
+    int atile_cap[4] = {0, 0, 0, 0};
+    int natiles[4] = {0, 0, 0, 0};
+    int *d_natiles = nullptr;
+    int mixed_members[4] = {0, 0, 0, 0};   // resident members of the order with per-element orders
     int tile[4] = {256, 256, 256, 256};
     bool shared[4] = {false, true, true, true};     // shared-flux kernel (256-element tiles) chosen for the order
     int no_items[4] = {0, 0, 0, 0};    // resident members of the order without edge items
@@ -1637,6 +1645,8 @@ swe_status grow_pool(swe_batch *b, int p, int64_t nc)
     BHIP_TRY(b, hipMalloc(&v.ev, sizeof(int) * 3 * nc));
     BHIP_TRY(b, hipMalloc(&v.nb, sizeof(int) * 3 * nc));
     BHIP_TRY(b, hipMalloc(&v.nbk, nc));
+    BHIP_TRY(b, hipMalloc(&v.ep, nc));
+    BHIP_TRY(b, hipMalloc(&v.pnew, nc));
     if (stage_sh_supported(p, b->fp32)) {
         BHIP_TRY(b, hipMalloc(&v.items, sizeof(unsigned) * 3 * nc));
         BHIP_TRY(b, hipMalloc(&v.nitems, sizeof(int) * (nc / BLOCK)));
@@ -1651,12 +1661,14 @@ swe_status grow_pool(swe_batch *b, int p, int64_t nc)
         BHIP_TRY(b, hipMemcpy2DAsync(v.ev, 4 * nc, P.v.ev, 4 * oc, 4 * oc, 3, hipMemcpyDeviceToDevice, b->s));
         BHIP_TRY(b, hipMemcpy2DAsync(v.nb, 4 * nc, P.v.nb, 4 * oc, 4 * oc, 3, hipMemcpyDeviceToDevice, b->s));
         BHIP_TRY(b, hipMemcpyAsync(v.nbk, P.v.nbk, oc, hipMemcpyDeviceToDevice, b->s));
+        BHIP_TRY(b, hipMemcpyAsync(v.ep, P.v.ep, oc, hipMemcpyDeviceToDevice, b->s));
         if (v.items) {
             BHIP_TRY(b, hipMemcpyAsync(v.items, P.v.items, sizeof(unsigned) * 3 * oc, hipMemcpyDeviceToDevice, b->s));
             BHIP_TRY(b, hipMemcpyAsync(v.nitems, P.v.nitems, sizeof(int) * (oc / BLOCK), hipMemcpyDeviceToDevice, b->s));
         }
         BHIP_TRY(b, hipStreamSynchronize(b->s));
-        void *old[] = {P.v.C0, P.v.C1, P.v.U0, P.v.U1, P.v.ev, P.v.nb, P.v.nbk, P.v.items, P.v.nitems};
+        void *old[] = {P.v.C0, P.v.C1, P.v.U0, P.v.U1, P.v.ev, P.v.nb, P.v.nbk, P.v.ep, P.v.pnew, P.v.items,
+                       P.v.nitems};
         for (void *q : old) (void)hipFree(q);
     }
     b->alloc += pool_bytes(p, b->fp32, nc) - pool_bytes(p, b->fp32, oc);
@@ -1669,6 +1681,12 @@ swe_status grow_pool(swe_batch *b, int p, int64_t nc)
     if (b->d_tiles[p]) (void)hipFree(b->d_tiles[p]);
     b->d_tiles[p] = nt;
     b->tile_cap[p] = tc;
+    const int ac = (int)(nc / BLOCK + 1);
+    int2 *na = nullptr;
+    BHIP_TRY(b, hipMalloc(&na, sizeof(int2) * ac));
+    if (b->d_atiles[p]) (void)hipFree(b->d_atiles[p]);
+    b->d_atiles[p] = na;
+    b->atile_cap[p] = ac;
     drop_graph(b);
     return SWE_OK;
 }
@@ -1696,7 +1714,8 @@ void release_pool(swe_batch *b, int p)
 {
     swe_batch::Pool &P = b->pool[p];
     if (P.ra.cap == 0) return;
-    void *q[] = {P.v.C0, P.v.C1, P.v.U0, P.v.U1, P.v.ev, P.v.nb, P.v.nbk, P.v.items, P.v.nitems, b->d_tiles[p]};
+    void *q[] = {P.v.C0, P.v.C1, P.v.U0, P.v.U1, P.v.ev, P.v.nb, P.v.nbk, P.v.ep, P.v.pnew, P.v.items, P.v.nitems,
+                 b->d_tiles[p], b->d_atiles[p]};
     for (void *x : q)
         if (x) (void)hipFree(x);
     b->alloc -= pool_bytes(p, b->fp32, P.ra.cap);
@@ -1704,6 +1723,8 @@ void release_pool(swe_batch *b, int p)
     P.ra.clear();
     b->d_tiles[p] = nullptr;
     b->tile_cap[p] = 0;
+    b->d_atiles[p] = nullptr;
+    b->atile_cap[p] = 0;
     drop_graph(b);
 }
 
@@ -1721,7 +1742,8 @@ void release_vertices(swe_batch *b)
 // member of that order brought its edge items.
 bool use_shared(const swe_batch *b, int p)
 {
-    return b->shared[p] && b->no_items[p] == 0 && b->pool[p].v.items != nullptr;
+    // the shared-flux kernel takes uniform-order members only
+    return b->shared[p] && b->no_items[p] == 0 && b->mixed_members[p] == 0 && b->pool[p].v.items != nullptr;
 }
 
 // Tile size of order p: 256 for the shared-flux kernel (tiles are its blocks).
@@ -1742,11 +1764,24 @@ swe_status upload_tiles(swe_batch *b)
         if (!t.empty())
             BHIP_TRY(b, hipMemcpyAsync(b->d_tiles[p], t.data(), sizeof(int2) * t.size(), hipMemcpyHostToDevice, b->s));
         if (b->grid[p] <= 0) b->grid[p] = 2 * b->ncu;
+        // the order update's tiles: 256 elements of an indicator-driven member
+        std::vector<int2> at;
+        for (int i = 0; i < b->cap; ++i) {
+            const swe_batch::Member &m = b->mem[i];
+            if (!m.ctx || m.order != p || !m.adapt) continue;
+            for (int64_t f = 0; f < m.ctx->ne; f += BLOCK) at.push_back(make_int2(i, (int)(m.first + f)));
+        }
+        if ((int)at.size() > b->atile_cap[p]) return bfail(b, SWE_ENOMEM, "tile list capacity exceeded");
+        b->natiles[p] = (int)at.size();
+        if (!at.empty())
+            BHIP_TRY(b, hipMemcpyAsync(b->d_atiles[p], at.data(), sizeof(int2) * at.size(), hipMemcpyHostToDevice,
+                                       b->s));
     }
     BHIP_TRY(b, hipMemcpyAsync(b->d_ntiles, b->ntiles, sizeof(int) * 4, hipMemcpyHostToDevice, b->s));
+    BHIP_TRY(b, hipMemcpyAsync(b->d_natiles, b->natiles, sizeof(int) * 4, hipMemcpyHostToDevice, b->s));
     BHIP_TRY(b, hipStreamSynchronize(b->s));
     int present = 0;
-    for (int p = 0; p < 4; ++p) present |= b->ntiles[p] ? 1 << p : 0;
+    for (int p = 0; p < 4; ++p) present |= (b->ntiles[p] ? 1 << p : 0) | (b->natiles[p] ? 1 << (4 + p) : 0);
     if (present != b->graph_orders) drop_graph(b);   // the step graph launches other orders
     return SWE_OK;
 }
@@ -1767,6 +1802,8 @@ BatchArgs batch_args(const swe_batch *b, int p)
     a.inst = b->d_inst;
     a.tiles = b->d_tiles[p];
     a.ntiles = b->d_ntiles + p;
+    a.atiles = b->d_atiles[p];
+    a.natiles = b->d_natiles + p;
     a.flags = b->d_flags;
     return a;
 }
@@ -1817,6 +1854,12 @@ hipError_t enqueue_instance_stage(swe_batch *b, int i, int mode, Sink &k)
 hipError_t enqueue_batch_step(swe_batch *b, Sink &k)
 {
     hipError_t e = launch_batch_clock(b->d_inst, b->d_flags, b->cap, k);
+    // order update of the indicator-driven members: every indicator before
+    // any order is applied (an element's list flag reads its neighbours' new orders)
+    for (int p = 1; p < 4 && e == hipSuccess; ++p)
+        if (b->natiles[p]) e = launch_batch_indicator(b->fp32, batch_args(b, p), tile_grid(b, p, BLOCK), k);
+    for (int p = 1; p < 4 && e == hipSuccess; ++p)
+        if (b->natiles[p]) e = launch_batch_apply(p, b->fp32, batch_args(b, p), tile_grid(b, p, BLOCK), k);
     for (int mode = MODE_STAGE1; mode <= MODE_STAGE2 && e == hipSuccess; ++mode)
         for (int p = 0; p < 4 && e == hipSuccess; ++p) {
             if (b->ntiles[p] == 0) continue;
@@ -1853,7 +1896,7 @@ swe_status build_step_graph(swe_batch *b)
     b->graph = g;
     BHIP_TRY(b, hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
     b->graph_orders = 0;
-    for (int p = 0; p < 4; ++p) b->graph_orders |= b->ntiles[p] ? 1 << p : 0;
+    for (int p = 0; p < 4; ++p) b->graph_orders |= (b->ntiles[p] ? 1 << p : 0) | (b->natiles[p] ? 1 << (4 + p) : 0);
     return SWE_OK;
 }
 
@@ -1884,6 +1927,8 @@ swe_status pull_state(swe_batch *b, int i)
                                  w * c->ne, 3 * K, hipMemcpyDeviceToDevice, b->s));
     BHIP_TRY(b, hipMemcpy2DAsync(c->d_U[0], w * c->stride, static_cast<char *>(P.v.U0) + w * m.first, w * P.v.cap,
                                  w * c->ne, 2 * K, hipMemcpyDeviceToDevice, b->s));
+    if (m.adapt)   // the orders the indicator chose while resident
+        BHIP_TRY(b, hipMemcpyAsync(c->d_p, P.v.ep + m.first, c->ne, hipMemcpyDeviceToDevice, b->s));
     BHIP_TRY(b, hipStreamSynchronize(b->s));
     return SWE_OK;
 }
@@ -1929,7 +1974,8 @@ swe_status swe_batch_create(const swe_config *cfg, int64_t budget, int max_insta
     }
     if (hipMalloc(&b->d_inst, sizeof(InstDesc) * max_instances) != hipSuccess ||
         hipMalloc(&b->d_flags, sizeof(int) * max_instances) != hipSuccess ||
-        hipMalloc(&b->d_ntiles, sizeof(int) * 4) != hipSuccess) {
+        hipMalloc(&b->d_ntiles, sizeof(int) * 4) != hipSuccess ||
+        hipMalloc(&b->d_natiles, sizeof(int) * 4) != hipSuccess) {
         swe_batch_destroy(b);
         return SWE_ENOMEM;
     }
@@ -1937,6 +1983,7 @@ swe_status swe_batch_create(const swe_config *cfg, int64_t budget, int max_insta
                        b->s) != hipSuccess ||
         hipMemsetAsync(b->d_flags, 0, sizeof(int) * max_instances, b->s) != hipSuccess ||
         hipMemsetAsync(b->d_ntiles, 0, sizeof(int) * 4, b->s) != hipSuccess ||
+        hipMemsetAsync(b->d_natiles, 0, sizeof(int) * 4, b->s) != hipSuccess ||
         hipStreamSynchronize(b->s) != hipSuccess) {
         swe_batch_destroy(b);
         return SWE_EDEVICE;
@@ -1960,11 +2007,12 @@ void swe_batch_destroy(swe_batch *b)
             (void)build_items(c);
         }
     drop_graph(b);
-    std::vector<void *> ptrs = {b->d_inst, b->d_flags, b->d_ntiles, b->d_vtx};
+    std::vector<void *> ptrs = {b->d_inst, b->d_flags, b->d_ntiles, b->d_natiles, b->d_vtx};
     for (int p = 0; p < 4; ++p) {
         const PoolView &v = b->pool[p].v;
-        for (void *q : {v.C0, v.C1, v.U0, v.U1, (void *)v.ev, (void *)v.nb, (void *)v.nbk, (void *)v.items,
-                        (void *)v.nitems, (void *)b->d_tiles[p]})
+        for (void *q : {v.C0, v.C1, v.U0, v.U1, (void *)v.ev, (void *)v.nb, (void *)v.nbk, (void *)v.ep,
+                        (void *)v.pnew, (void *)v.items, (void *)v.nitems, (void *)b->d_tiles[p],
+                        (void *)b->d_atiles[p]})
             ptrs.push_back(q);
     }
     for (void *q : ptrs)
@@ -1990,8 +2038,8 @@ swe_status swe_batch_admit(swe_batch *b, swe_ctx *c, int64_t nsteps, double dt, 
     if (!c->have_mesh) return bfail(b, SWE_EINVAL, "context has no mesh");
     if (c->batch) return bfail(b, SWE_EINVAL, "context is already resident in a batch");
     if (c->fp32 != b->fp32) return bfail(b, SWE_EINVAL, "context precision differs from the batch");
-    if (c->cfg.separate || c->cfg.adapt || !c->uniform || c->d_src || c->failed)
-        return bfail(b, SWE_EINVAL, "batch members need one uniform order, no separation, adaptivity or source");
+    if (c->cfg.separate || c->d_src || c->failed)
+        return bfail(b, SWE_EINVAL, "batch members run the fused scheme (separate = 0) and take no extra source");
     if (c->ncon > 4) return bfail(b, SWE_EINVAL, "batch members support at most 4 forcing constituents");
     int i = 0;
     while (i < b->cap && b->mem[i].ctx) ++i;
@@ -2044,7 +2092,8 @@ swe_status swe_batch_admit(swe_batch *b, swe_ctx *c, int64_t nsteps, double dt, 
     BHIP_TRY(b, hipMemcpy2DAsync(static_cast<char *>(P.v.U0) + w * first, w * P.v.cap, c->d_U[0], w * c->stride,
                                  w * c->ne, 2 * K, hipMemcpyDeviceToDevice, b->s));
     BHIP_TRY(b, hipMemcpyAsync(b->d_vtx + vbase, c->d_vtx, sizeof(double4) * c->nv, hipMemcpyDeviceToDevice, b->s));
-    BHIP_TRY(b, launch_relocate(c->d_ev, c->d_nb, c->d_nbk, (int)c->ne, c->stride, P.v, (int)first, (int)vbase, b->s));
+    BHIP_TRY(b, launch_relocate(c->d_ev, c->d_nb, c->d_nbk, c->d_p, (int)c->ne, c->stride, P.v, (int)first, (int)vbase,
+                                b->s));
     const bool no_items = P.v.items != nullptr && !items_cover(c, 0);
     if (P.v.items && items_cover(c, 0))
         BHIP_TRY(b, launch_place_items(c->d_items, c->d_item_off, (int)((c->ne + BLOCK - 1) / BLOCK), P.v, (int)first,
@@ -2067,6 +2116,11 @@ swe_status swe_batch_admit(swe_batch *b, swe_ctx *c, int64_t nsteps, double dt, 
     d.active = 1;
     d.ncon = c->ncon;
     for (int k = 0; k < c->ncon; ++k) { d.amp[k] = c->amp[k]; d.omega[k] = c->omega[k]; d.phase[k] = c->phase[k]; }
+    const bool mixed = !c->uniform || c->cfg.adapt;
+    d.mixed = mixed ? 1 : 0;
+    d.adapt = c->cfg.adapt ? 1 : 0;
+    d.tau = c->cfg.adapt_tau;
+    d.p_lo = c->cfg.p_base;
     BHIP_TRY(b, hipMemsetAsync(b->d_flags + i, 0, sizeof(int), b->s));
     swe_status st = put_desc(b, i);
     if (st) return st;
@@ -2079,7 +2133,10 @@ swe_status swe_batch_admit(swe_batch *b, swe_ctx *c, int64_t nsteps, double dt, 
     m.vbase = vbase;
     m.nv = c->nv;
     m.no_items = no_items;
+    m.mixed = mixed;
+    m.adapt = c->cfg.adapt != 0;
     if (no_items && b->no_items[p]++ == 0) drop_graph(b);   // the order falls back to the gather kernel
+    if (mixed && b->mixed_members[p]++ == 0) drop_graph(b);
     BHIP_TRY(b, hipStreamSynchronize(b->s));   // the copies out of the member's buffers are done
     release_state_buffers(c);
     b->alloc += kept;
@@ -2166,6 +2223,7 @@ swe_status swe_batch_retire(swe_batch *b, int32_t slot)
     if (st) return st;
     if (per_instance(b, m.order)) drop_graph(b);
     if (m.no_items && --b->no_items[m.order] == 0) drop_graph(b);
+    if (m.mixed && --b->mixed_members[m.order] == 0) drop_graph(b);
     const int order = m.order;
     b->pool[order].ra.give(m.first, m.span);
     b->vra.give(m.vbase, m.nv);

@@ -84,7 +84,11 @@ struct InstDesc {
     int active, run;             // resident / advancing in the current step
     int steps_done, steps_left;
     int ncon;
+    int mixed;                   // per-element orders (pool ep) mask the stage
+    int adapt;                   // orders re-chosen by the indicator before every step
+    int p_lo;                    // lowest order of an indicator-driven member (its base order)
     Physics ph;
+    double tau;                  // indicator threshold of an indicator-driven member
     double t0, t, dt;            // start time, current time, step
     double xh[2];                // open-sea elevation at the two stage times of this step
     double amp[4], omega[4], phase[4];
@@ -98,6 +102,8 @@ struct PoolView {
     unsigned *items;             // edge items of the shared-flux kernel, 3 slots per element:
                                  // the block at element f (f a multiple of 256) keeps its items from 3 f
     int *nitems;                 // [cap / 256] item count of each 256-element block
+    signed char *ep;             // [cap] element orders (uniform members: their order)
+    signed char *pnew;           // [cap] orders chosen by the indicator, before they are applied
     int cap;
 };
 
@@ -107,6 +113,8 @@ struct BatchArgs {
     const InstDesc *inst;
     const int2 *tiles;           // [tile_cap] (instance, first element) of the launched order
     const int *ntiles;           // device-side tile count of the launched order
+    const int2 *atiles;          // 256-element tiles of the launched order's indicator-driven members
+    const int *natiles;          // their device-side count
     int *flags;                  // [instances]
 };
 
@@ -178,7 +186,11 @@ hipError_t launch_inst_set(InstDesc *inst, const InstDesc &v, hipStream_t s);
 hipError_t launch_batch_stage_sh(int p, bool fp32, int mode, const BatchArgs &b, int grid, Sink &k);
 hipError_t launch_place_items(const unsigned *items, const int *item_off, int nblk, const PoolView &pool, int first,
                               hipStream_t s);
-hipError_t launch_relocate(const int *ev, const int *nb, const unsigned char *nbk, int ne, int stride,
-                           const PoolView &pool, int first, int vbase, hipStream_t s);
+hipError_t launch_relocate(const int *ev, const int *nb, const unsigned char *nbk, const signed char *ep, int ne,
+                           int stride, const PoolView &pool, int first, int vbase, hipStream_t s);
+// order update of a batch's indicator-driven members of one order class:
+// indicator into pool.pnew, then the new orders applied (fused scheme, no lists)
+hipError_t launch_batch_indicator(bool fp32, const BatchArgs &b, int grid, Sink &k);
+hipError_t launch_batch_apply(int pm, bool fp32, const BatchArgs &b, int grid, Sink &k);
 
 }  // namespace swe

@@ -1277,10 +1277,13 @@ k_batch_stage(BatchArgs b)
     a.Uout = static_cast<Real *>(MODE == MODE_STAGE1 ? b.pool.U1 : b.pool.U0);
     a.Lout = nullptr;
     a.src = nullptr;
-    a.mixed = 0;
     const int2 tile = b.tiles[t];
     const InstDesc &I = b.inst[tile.x];
     if (!I.run) return;
+    // a member with per-element orders (a static order map or indicator-driven
+    // orders) masks each element's modes by its order, as on its own
+    a.m.ep = b.pool.ep;
+    a.mixed = I.mixed;
     a.ph = I.ph;
     const unsigned e = (unsigned)tile.y + threadIdx.x;
     if (e < (unsigned)(I.first + I.ne))
@@ -1344,8 +1347,9 @@ __global__ void __launch_bounds__(BLOCK) k_place_items(const unsigned *items, co
     if (threadIdx.x == 0) pool.nitems[f / BLOCK] = n;
 }
 
-__global__ void __launch_bounds__(BLOCK) k_relocate(const int *ev, const int *nb, const unsigned char *nbk, int ne,
-                                                    int stride, PoolView pool, int first, int vbase)
+__global__ void __launch_bounds__(BLOCK) k_relocate(const int *ev, const int *nb, const unsigned char *nbk,
+                                                    const signed char *ep, int ne, int stride, PoolView pool,
+                                                    int first, int vbase)
 {
     const int e = blockIdx.x * BLOCK + threadIdx.x;
     if (e >= ne) return;
@@ -1356,6 +1360,7 @@ __global__ void __launch_bounds__(BLOCK) k_relocate(const int *ev, const int *nb
         pool.nb[k * pool.cap + first + e] = n >= 0 ? n + first : n;
     }
     pool.nbk[first + e] = nbk[e];
+    pool.ep[first + e] = ep[e];
 }
 
 // Per-step clock of every resident instance: open-sea elevation at the two
@@ -1584,16 +1589,10 @@ k_epi_all(StageArgs<Real> a, int KB, int lo, int nblk, int lcap)
 // edges contribute 0, open edges compare with xi_hat(t).  New order: p_hi if
 // I >= tau, one less for each further factor 10 below tau, never below p_lo.
 template <typename Real>
-__global__ void __launch_bounds__(BLOCK) k_indicator(StageArgs<Real> a, double tau, int p_lo, int p_hi,
-                                                     double *I_out, signed char *p_new)
+__device__ __forceinline__ void indicator_element(const MeshView &m, const Buf<Real> &bC, unsigned e, double xihat,
+                                                  double tau, int p_lo, int p_hi, double *I_out, signed char *p_new)
 {
-    const MeshView &m = a.m;
-    const int KS = m.KS, stride = m.stride;
-    if (a.cntw && blockIdx.x == 0 && threadIdx.x < 4) a.cntw[threadIdx.x] = 0;   // list counts of the next pass
-    const unsigned e = blockIdx.x * BLOCK + threadIdx.x;
-    if (e >= (unsigned)m.ne) return;
-    const Buf<Real> bC(a.Cin, 3 * KS, stride);
-    const Buf<int> bNb(m.enb, 3, stride);
+    const Buf<int> bNb(m.enb, 3, m.stride);
     const unsigned off = e * (unsigned)sizeof(Real);
     const double x0 = bC.ld(0, off), x1 = bC.ld(1, off), x2 = bC.ld(2, off);
     const unsigned nbk_all = m.enbk[e];
@@ -1609,7 +1608,7 @@ __global__ void __launch_bounds__(BLOCK) k_indicator(StageArgs<Real> a, double t
             const double y0 = bC.ld(0, on), y1 = bC.ld(1, on), y2 = bC.ld(2, on);
             other = TPMID[kk][0] * y0 + TPMID[kk][1] * y1 + TPMID[kk][2] * y2;
         } else if (nb == NB_OPEN) {
-            other = a.inst ? a.inst->xh[0] : a.xihat;
+            other = xihat;
         }
         const double j = fabs(own - other);
         I = j > I ? j : I;
@@ -1626,65 +1625,89 @@ __global__ void __launch_bounds__(BLOCK) k_indicator(StageArgs<Real> a, double t
     }
 }
 
-// Apply the new orders: drop modes above K(p_new) from every state buffer,
-// re-solve u of changed elements, flag elements that need a correction and
-// append them to the list of their order (one atomic per wave and order).
+template <typename Real>
+__global__ void __launch_bounds__(BLOCK) k_indicator(StageArgs<Real> a, double tau, int p_lo, int p_hi,
+                                                     double *I_out, signed char *p_new)
+{
+    const MeshView &m = a.m;
+    if (a.cntw && blockIdx.x == 0 && threadIdx.x < 4) a.cntw[threadIdx.x] = 0;   // list counts of the next pass
+    const unsigned e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= (unsigned)m.ne) return;
+    const Buf<Real> bC(a.Cin, 3 * m.KS, m.stride);
+    indicator_element<Real>(m, bC, e, a.inst ? a.inst->xh[0] : a.xihat, tau, p_lo, p_hi, I_out, p_new);
+}
+
+// Apply the new order of element e: drop modes above K(p_new) from every state
+// buffer and re-solve u if the order changed; whether the element is listed
+// (its order or a neighbour's above p_base) goes to *listed.
 template <int PM, typename Real>
-__global__ void __launch_bounds__(BLOCK) k_apply_order(StageArgs<Real> a, const signed char *p_new,
-                                                       signed char *p_cur, int p_base, int lcap)
+__device__ __forceinline__ int apply_element(const StageArgs<Real> &a, unsigned e, const signed char *p_new,
+                                             signed char *p_cur, int p_base, bool *listed)
 {
     constexpr int K = Ord<PM>::K;
     const MeshView &m = a.m;
     const int KS = m.KS, stride = m.stride;
+    const unsigned off = e * (unsigned)sizeof(Real);
+    const int pn = p_new[e];
+    const int po = p_cur[e];
+    const Buf<int> bNb(m.enb, 3, stride);
+    bool l = pn > p_base;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int nb = bNb.ld(k, e * 4u);
+        if (nb >= 0 && p_new[nb] > p_base) l = true;
+    }
+    *listed = l;
+    if (pn != po) {
+        const int Kn = KOFP[pn];
+        Buf<Real> b0(a.Cout, 3 * KS, stride), b1(a.Calt, 3 * KS, stride);
+        Buf<Real> u1(a.Ualt, 2 * KS, stride);
+        Real xi[K], U[K], V[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const bool keep = q < Kn;
+            xi[q] = keep ? b0.ld(0 * KS + q, off) : Real(0);
+            U[q] = keep ? b0.ld(1 * KS + q, off) : Real(0);
+            V[q] = keep ? b0.ld(2 * KS + q, off) : Real(0);
+            if (!keep) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) { b0.st(j * KS + q, off, Real(0)); b1.st(j * KS + q, off, Real(0)); }
+                u1.st(0 * KS + q, off, Real(0));
+                u1.st(1 * KS + q, off, Real(0));
+            }
+        }
+        Geo G;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) G.h[v] = m.vtx[(unsigned)Buf<int>(m.ev, 3, stride).ld(v, e * 4u)].z;
+        double hbh[3];
+        hb_modes(G, hbh);
+        Real u[K], v[K];
+        solve_u<PM, Real>(xi, U, V, hbh, Kn, u, v);
+        Buf<Real> bu(a.Uout, 2 * KS, stride);
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            bu.st(0 * KS + q, off, u[q]);
+            bu.st(1 * KS + q, off, v[q]);
+        }
+        p_cur[e] = (signed char)pn;
+    }
+    return pn;
+}
+
+// Apply the new orders of a context's elements, flag elements that need a
+// correction and append them to the list of their order (one atomic per
+// wave and order).
+template <int PM, typename Real>
+__global__ void __launch_bounds__(BLOCK) k_apply_order(StageArgs<Real> a, const signed char *p_new,
+                                                       signed char *p_cur, int p_base, int lcap)
+{
     const unsigned e = blockIdx.x * BLOCK + threadIdx.x;
-    const bool live = e < (unsigned)m.ne;
+    const bool live = e < (unsigned)a.m.ne;
     int pn = 0;
     bool listed = false;
     if (live) {
-        const unsigned off = e * (unsigned)sizeof(Real);
-        pn = p_new[e];
-        const int po = p_cur[e];
-        const Buf<int> bNb(m.enb, 3, stride);
-        listed = pn > p_base;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int nb = bNb.ld(k, e * 4u);
-            if (nb >= 0 && p_new[nb] > p_base) listed = true;
-        }
+        pn = apply_element<PM, Real>(a, e, p_new, p_cur, p_base, &listed);
         a.inlist[e] = listed ? 1 : 0;
-        if (pn != po) {
-            const int Kn = KOFP[pn];
-            Buf<Real> b0(a.Cout, 3 * KS, stride), b1(a.Calt, 3 * KS, stride);
-            Buf<Real> u1(a.Ualt, 2 * KS, stride);
-            Real xi[K], U[K], V[K];
-#pragma unroll
-            for (int q = 0; q < K; ++q) {
-                const bool keep = q < Kn;
-                xi[q] = keep ? b0.ld(0 * KS + q, off) : Real(0);
-                U[q] = keep ? b0.ld(1 * KS + q, off) : Real(0);
-                V[q] = keep ? b0.ld(2 * KS + q, off) : Real(0);
-                if (!keep) {
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) { b0.st(j * KS + q, off, Real(0)); b1.st(j * KS + q, off, Real(0)); }
-                    u1.st(0 * KS + q, off, Real(0));
-                    u1.st(1 * KS + q, off, Real(0));
-                }
-            }
-            Geo G;
-#pragma unroll
-            for (int v = 0; v < 3; ++v) G.h[v] = m.vtx[(unsigned)Buf<int>(m.ev, 3, stride).ld(v, e * 4u)].z;
-            double hbh[3];
-            hb_modes(G, hbh);
-            Real u[K], v[K];
-            solve_u<PM, Real>(xi, U, V, hbh, Kn, u, v);
-            Buf<Real> bu(a.Uout, 2 * KS, stride);
-#pragma unroll
-            for (int q = 0; q < K; ++q) {
-                bu.st(0 * KS + q, off, u[q]);
-                bu.st(1 * KS + q, off, v[q]);
-            }
-            p_cur[e] = (signed char)pn;
-        }
     }
     // wave-aggregated append to the list of order pn
     const int lane = threadIdx.x & 63;
@@ -1703,6 +1726,62 @@ __global__ void __launch_bounds__(BLOCK) k_apply_order(StageArgs<Real> a, const 
             if (base + rank < lcap) a.listw[(size_t)p * (size_t)lcap + (size_t)(base + rank)] = (int)e;
         }
     }
+}
+
+// The order update of the indicator-driven members of a batch, over 256-element
+// tiles of their pool (every such member runs the fused scheme: its elements'
+// own orders mask the stage, no lists).  Tile lists and instance scalars as
+// for the batch stage kernels; instances whose clock stopped are skipped.
+template <typename Real>
+__global__ void __launch_bounds__(BLOCK) k_batch_indicator(BatchArgs b)
+{
+    const int nt = b.natiles[0];
+    const int x = (int)(blockIdx.x & 7u), i = (int)(blockIdx.x >> 3);
+    const int lo = (int)(((long long)nt * x) >> 3), hi = (int)(((long long)nt * (x + 1)) >> 3);
+    const int t = lo + i;
+    if (t >= hi) return;
+    const int2 tile = b.atiles[t];
+    const InstDesc &I = b.inst[tile.x];
+    if (!I.run) return;
+    const unsigned e = (unsigned)tile.y + threadIdx.x;
+    if (e >= (unsigned)(I.first + I.ne)) return;
+    MeshView m{};
+    m.stride = b.pool.cap;
+    m.KS = (I.order + 1) * (I.order + 2) / 2;
+    m.vtx = b.vtx;
+    m.ev = b.pool.ev;
+    m.enb = b.pool.nb;
+    m.enbk = b.pool.nbk;
+    const Buf<Real> bC(static_cast<const Real *>(b.pool.C0), 3 * m.KS, m.stride);
+    indicator_element<Real>(m, bC, e, I.xh[0], I.tau, I.p_lo, I.order, nullptr, b.pool.pnew);
+}
+
+template <int PM, typename Real>
+__global__ void __launch_bounds__(BLOCK) k_batch_apply(BatchArgs b)
+{
+    const int nt = b.natiles[0];
+    const int x = (int)(blockIdx.x & 7u), i = (int)(blockIdx.x >> 3);
+    const int lo = (int)(((long long)nt * x) >> 3), hi = (int)(((long long)nt * (x + 1)) >> 3);
+    const int t = lo + i;
+    if (t >= hi) return;
+    const int2 tile = b.atiles[t];
+    const InstDesc &I = b.inst[tile.x];
+    if (!I.run) return;
+    const unsigned e = (unsigned)tile.y + threadIdx.x;
+    if (e >= (unsigned)(I.first + I.ne)) return;
+    StageArgs<Real> a{};   // no lists: the fused scheme masks by the elements' own orders
+    a.m.stride = b.pool.cap;
+    a.m.KS = Ord<PM>::K;
+    a.m.vtx = b.vtx;
+    a.m.ev = b.pool.ev;
+    a.m.enb = b.pool.nb;
+    a.m.enbk = b.pool.nbk;
+    a.Cout = static_cast<Real *>(b.pool.C0);
+    a.Calt = static_cast<Real *>(b.pool.C1);
+    a.Uout = static_cast<Real *>(b.pool.U0);
+    a.Ualt = static_cast<Real *>(b.pool.U1);
+    bool listed = false;
+    (void)apply_element<PM, Real>(a, e, b.pool.pnew, b.pool.ep, I.p_lo, &listed);
 }
 
 template <int P, typename Real>
@@ -2065,13 +2144,41 @@ hipError_t launch_batch_clock(InstDesc *inst, const int *flags, int n, Sink &k)
     return emit(k, reinterpret_cast<const void *>(&k_batch_clock), dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), kargs);
 }
 
-hipError_t launch_relocate(const int *ev, const int *nb, const unsigned char *nbk, int ne, int stride,
-                           const PoolView &pool, int first, int vbase, hipStream_t s)
+hipError_t launch_relocate(const int *ev, const int *nb, const unsigned char *nbk, const signed char *ep, int ne,
+                           int stride, const PoolView &pool, int first, int vbase, hipStream_t s)
 {
     if (ne <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_relocate, dim3((ne + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, ev, nb, nbk, ne, stride, pool,
-                       first, vbase);
+    hipLaunchKernelGGL(k_relocate, dim3((ne + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, ev, nb, nbk, ep, ne, stride,
+                       pool, first, vbase);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_indicator(bool fp32, const BatchArgs &b, int grid, Sink &k)
+{
+    if (grid <= 0) return hipSuccess;
+    BatchArgs a = b;
+    void *kargs[] = {&a};
+    return emit(k, fp32 ? reinterpret_cast<const void *>(&k_batch_indicator<float>)
+                        : reinterpret_cast<const void *>(&k_batch_indicator<double>),
+                dim3(grid), dim3(BLOCK), kargs);
+}
+
+hipError_t launch_batch_apply(int pm, bool fp32, const BatchArgs &b, int grid, Sink &k)
+{
+    if (grid <= 0) return hipSuccess;
+    BatchArgs a = b;
+    void *kargs[] = {&a};
+    const void *fn = nullptr;
+    switch (pm) {
+    case 1: fn = fp32 ? reinterpret_cast<const void *>(&k_batch_apply<1, float>)
+                      : reinterpret_cast<const void *>(&k_batch_apply<1, double>); break;
+    case 2: fn = fp32 ? reinterpret_cast<const void *>(&k_batch_apply<2, float>)
+                      : reinterpret_cast<const void *>(&k_batch_apply<2, double>); break;
+    case 3: fn = fp32 ? reinterpret_cast<const void *>(&k_batch_apply<3, float>)
+                      : reinterpret_cast<const void *>(&k_batch_apply<3, double>); break;
+    default: return hipErrorInvalidValue;
+    }
+    return emit(k, fn, dim3(grid), dim3(BLOCK), kargs);
 }
 
 template <typename Real>

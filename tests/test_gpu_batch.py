@@ -173,3 +173,86 @@ def test_batch_admission_budget():
             b.admit(fp64, 1, 1.0)
     for c in ctxs:
         c.close()
+
+
+def mixed_members():
+    """Members with per-element orders beside uniform ones: a static random
+    order map (tidal family, orders 1-3), the dam break's every-32nd map
+    (p1-2), the tsunami with orders from the indicator (1-3), the dam break
+    with orders from the indicator (p0-1), and uniform p1 and p3 instances
+    sharing those members' pools."""
+    out = []
+    prob = I.config_c2(n=14, p=3, seed=31)
+    prob.p = np.random.default_rng(31).integers(1, 4, prob.mesh.ne).astype(np.int8)
+    out.append(("static random p1-3", prob, 21))
+    out.append(("dam break 1/32 p1-2", I.config_dambreak(n=16, p_lo=1, p_hi=2, every=32, dt_fixed=None), 17))
+    out.append(("tsunami adaptive p1-3", I.config_c3(n=18), 25))
+    out.append(("dam break adaptive p0-1", I.config_dambreak(n=16, p_lo=0, p_hi=1, dt_fixed=None, adapt_tau=1e-2), 14))
+    uni1 = I.config_instance(911, n_lo=300, n_hi=900)
+    uni1.p[:] = 1
+    uni1.p_max = uni1.p_base = 1
+    out.append(("uniform p1", uni1, 19))
+    uni3 = I.config_instance(912, n_lo=300, n_hi=900)
+    uni3.p[:] = 3
+    uni3.p_max = uni3.p_base = 3
+    out.append(("uniform p3", uni3, 12))
+    return out
+
+
+@pytest.mark.parametrize("precision", [swe.SWE_FP64, swe.SWE_FP32_WB])
+def test_batch_mixed_order_members(precision):
+    """Mixed-order members in one batch with uniform ones (members joining
+    mid-run, the tuner choosing kernels): each member's result matches the
+    oracle (FP64 state within 1e-12 relative L2 and identical order maps;
+    FP32 elevation within 1e-5 and maps agreeing on 99 % of the elements)
+    and is bitwise its result alone."""
+    cases = mixed_members()
+    refs, c0s = [], []
+
+    def oracle_run(args):
+        _, prob, n = args
+        orc = Oracle.from_problem(prob)
+        c0 = orc.project(prob.ic)
+        ref = orc.step(c0, n, prob.dt(), adapt=bool(prob.adapt), tau=prob.adapt_tau, p_lo=prob.p_base,
+                       p_hi=prob.p_max)
+        return c0, ref, orc.order()
+    with ThreadPoolExecutor(max_workers=len(cases)) as pool:
+        res = list(pool.map(oracle_run, cases))
+    alone = []
+    for (name, prob, n), (c0, _, _) in zip(cases, res):
+        with ctx_for(prob, precision, c0) as ctx:
+            ctx.step(n, prob.dt())
+            ctx.sync()
+            alone.append((ctx.state()[0], ctx.order()))
+    ctxs = [ctx_for(prob, precision, r[0]) for (_, prob, _), r in zip(cases, res)]
+    with swe.Batch(precision=precision, budget_bytes=4 << 30, max_instances=8) as b:
+        slots = [b.admit(c, n, prob.dt()) for c, (_, prob, n) in zip(ctxs[:3], cases[:3])]
+        b.tick(4)
+        slots += [b.admit(c, n, prob.dt()) for c, (_, prob, n) in zip(ctxs[3:], cases[3:])]
+        b.tune(reps=2)
+        used = {p: b.tile_config(p) for p in range(4)}
+        b.tick(40)
+        b.sync()
+        for s in slots:
+            left, _, failed = b.query(s)
+            assert left == 0 and not failed
+            b.retire(s)
+    say(f"mixed-order batch precision={precision}: kernels {used}")
+    for (name, prob, n), ctx, (_, ref, pref), (al, pal) in zip(cases, ctxs, res, alone):
+        got, _ = ctx.state()
+        pgot = ctx.order()
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        exi = np.linalg.norm((got - ref)[:, 0]) / np.linalg.norm(ref[:, 0])
+        agree = float(np.mean(pgot == pref))
+        hi = int((pref > prob.p_base).sum())
+        say(f"  {name}: ne={ctx.ne} steps={n} above base order {hi}, maps agree {agree:.4f}, equal alone "
+            f"{np.array_equal(got, al)}, vs oracle rel L2 {err:.2e}, xi {exi:.2e}")
+        assert np.array_equal(got, al) and np.array_equal(pgot, pal), name
+        if precision == swe.SWE_FP64:
+            assert np.array_equal(pgot, pref), name
+            assert err < 1e-12, name
+        else:
+            assert agree >= 0.99, name
+            assert exi < 1e-5, name
+        ctx.close()
+    assert not used[1][2] and not used[2][2] and not used[3][2]   # those classes hold per-element orders
