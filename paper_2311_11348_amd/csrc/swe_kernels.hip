@@ -754,29 +754,36 @@ __device__ __forceinline__ void finish_stage(const StageArgs<Real> &a, unsigned 
 constexpr unsigned EK_PAIR = 0, EK_EXT = 1, EK_LAND = 2, EK_OPEN = 3;
 
 // Waves per SIMD the shared-flux kernels are built for at least: what their
-// LDS allows (FP32 p = 2: 46 KB per 256-element block, three blocks per CU;
-// FP32 p = 3 and FP64 p = 2: 62 and 74 KB, two blocks; FP64 p = 3: 103 KB,
-// one block, whose registers then spill into accumulation registers rather
-// than scratch; p = 1 needs less).
+// LDS allows and their registers reach without spilling (FP32 p = 2: 32 KB
+// per 256-element block, four blocks per CU, 128 registers; FP32 p = 1:
+// 22 KB, five waves at 85 registers; FP32 p = 3 and FP64 p = 2: 53 and 63 KB,
+// two waves (three would spill); FP64 p = 1: 34 KB, three waves (four would
+// spill); FP64 p = 3: 105 KB, one block, whose registers then spill into
+// accumulation registers rather than scratch).
 template <int P, typename Real>
 constexpr int sh_waves()
 {
     constexpr bool dbl = std::is_same<Real, double>::value;
-    return (P <= 2 && !dbl) ? 3 : (P == 3 && dbl) ? 1 : 2;
+    return dbl ? (P == 1 ? 3 : P == 3 ? 1 : 2) : (P == 2 ? 4 : P == 3 ? 2 : 3);
 }
 
 // Per-block LDS.  The state copy C is read by the edge pass only; the
-// per-edge results F, W are written after it (every lane holds its items'
+// per-item results F, W are written after it (every lane holds its items'
 // results in registers across a barrier), so the two share the storage.
+// Results are stored per edge item (lane i writes column i: consecutive
+// words, no bank conflicts), and slot[k][l] tells element l which item
+// holds its local edge k (bit 15: l is the item's second side, which sees
+// the flux negated and reversed along the edge).
 template <int P, typename Real>
 struct ShLds {
     static constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
     Real R[3][K][NT];              // trace matrices
+    unsigned short slot[3][BLOCK]; // item of each (local edge, element)
     union {
         Real C[5 * K][BLOCK];      // xi, U, V, u, v modes of the block's elements
         struct {
-            Real F[3 * NT][3][BLOCK];  // flux modes (component, mode) per local edge and element
-            double W[NT][3][BLOCK];    // bathymetry part of the pressure flux, FP64
+            Real F[3 * NT][2 * BLOCK];  // flux modes (component, mode) per item
+            double W[NT][2 * BLOCK];    // bathymetry part of the pressure flux, FP64, per item
         } E;
     } U;
 };
@@ -949,10 +956,10 @@ __device__ __forceinline__ void sh_flux(const ShLds<P, Real> &S, const MeshView 
     }
 }
 
-// Hand an item's flux to its sides: as computed to the first, negated and
-// reversed along the edge to the second (a pair inside the block).
+// Store item i's flux in its column and point its sides' slots at it (the
+// second side of a pair inside the block marked by bit 15).
 template <int P, typename Real>
-__device__ __forceinline__ void sh_store(ShLds<P, Real> &S, unsigned w, const ShItem<P, Real> &r)
+__device__ __forceinline__ void sh_store(ShLds<P, Real> &S, int i, unsigned w, const ShItem<P, Real> &r)
 {
     constexpr int NT = Ord<P>::NT;
     const int la = (int)(w & 255u), ka = (int)((w >> 8) & 3u), lb = (int)((w >> 10) & 255u);
@@ -960,17 +967,11 @@ __device__ __forceinline__ void sh_store(ShLds<P, Real> &S, unsigned w, const Sh
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) S.U.E.F[j * NT + c][ka][la] = r.F[j][c];
-        S.U.E.W[c][ka][la] = r.W[c];
+        for (int j = 0; j < 3; ++j) S.U.E.F[j * NT + c][i] = r.F[j][c];
+        S.U.E.W[c][i] = r.W[c];
     }
-    if (((w >> 20) & 3u) == EK_PAIR) {
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j) S.U.E.F[j * NT + c][kb][lb] = (c & 1) ? r.F[j][c] : -r.F[j][c];
-            S.U.E.W[c][kb][lb] = (c & 1) ? -r.W[c] : r.W[c];
-        }
-    }
+    S.slot[ka][la] = (unsigned short)i;
+    if (((w >> 20) & 3u) == EK_PAIR) S.slot[kb][lb] = (unsigned short)(i | 0x8000);
 }
 
 // The passes over the block of elements [e0, e0 + BLOCK) (live below e_end),
@@ -1001,11 +1002,11 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
     const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
     const double g = a.ph.g;
 
-    // 1. state to registers and LDS; in FP32 also the geometry, whose
-    //    latency then hides behind the edge pass (in FP64 the registers it
-    //    would hold across that pass are not there: only the vertex ids are
-    //    loaded here)
-    constexpr bool early_geo = !std::is_same<Real, double>::value;
+    // 1. state to registers and LDS; at FP32 order 3 also the geometry, whose
+    //    latency then hides behind the edge pass (elsewhere the registers it
+    //    would hold across that pass cost a wave per SIMD: only the vertex ids
+    //    are loaded here, the vertices after the edge pass)
+    constexpr bool early_geo = !std::is_same<Real, double>::value && P == 3;
     Fields<P, Real> s;
     Geo G;
     double hbh[3];
@@ -1044,8 +1045,8 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
         sh_flux<P, Real>(S, m, bC, bU, bEv, bNb, e0, w1, xihat, g, r1);
     }
     __syncthreads();
-    if (it0 < n) sh_store<P, Real>(S, w0, r0);
-    if (it1 < n) sh_store<P, Real>(S, w1, r1);
+    if (it0 < n) sh_store<P, Real>(S, it0, w0, r0);
+    if (it1 < n) sh_store<P, Real>(S, it1, w1, r1);
     __syncthreads();
     if (!live) return;
     // base pass of the order-partitioned scheme: a listed element belongs to
@@ -1068,14 +1069,22 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
     for (int k = 0; k < 3; ++k) {
         const int ka = (k + 1) % 3, kb = (k + 2) % 3;
         const double dx = G.X[kb] - G.X[ka], dy = G.Y[kb] - G.Y[ka];
+        // the item of this edge; as its second side the flux comes negated and
+        // reversed along the edge (even Legendre modes change sign, odd ones not)
+        const unsigned sl = S.slot[k][l];
+        const int it = (int)(sl & 0x7fffu);
+        const bool second = (sl & 0x8000u) != 0u;
         Real FX[NT], FU[NT], FV[NT];
         double FWx[NT], FWy[NT];
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
-            FX[c] = sc * S.U.E.F[0 * NT + c][k][l];
-            FU[c] = sc * S.U.E.F[1 * NT + c][k][l];
-            FV[c] = sc * S.U.E.F[2 * NT + c][k][l];
-            const double FW = S.U.E.W[c][k][l] * dt_det;
+            const bool flip = second && !(c & 1);
+            const Real f0 = S.U.E.F[0 * NT + c][it], f1 = S.U.E.F[1 * NT + c][it], f2 = S.U.E.F[2 * NT + c][it];
+            FX[c] = sc * (flip ? -f0 : f0);
+            FU[c] = sc * (flip ? -f1 : f1);
+            FV[c] = sc * (flip ? -f2 : f2);
+            const double w = S.U.E.W[c][it];
+            const double FW = (second && (c & 1) ? -w : w) * dt_det;
             FWx[c] = FW * dy;
             FWy[c] = FW * -dx;
         }
