@@ -317,18 +317,19 @@ def run_uniform(prob, precision, steps, warmup):
             "compute": compute_roofline(p, word == 4, ne, launch_s)}
 
 
-def run_separated(prob, precision, steps, warmup, separate=1, chunk=50):
+def run_separated(prob, precision, steps, warmup, separate=1, chunk=50, hetero=0):
     """Order-separated scheme (separate=1: base + corrections joined by an
-    epilogue) or order-partitioned scheme (separate=2: base elements and each
-    order's listed elements on parallel branches), optionally adaptive.
-    DOF counts follow the order map, read between timed chunks."""
+    epilogue; hetero=1: the corrections on the host's cores) or
+    order-partitioned scheme (separate=2: base elements and each order's
+    listed elements on parallel branches), optionally adaptive.  DOF counts
+    follow the order map, read between timed chunks."""
     import numpy as np
     import torch
     from paper_2311_11348_amd import swe
     stream = torch.cuda.Stream()
     stream2 = torch.cuda.Stream()
     ctx = swe.context_for(prob, precision=precision, separate=separate, stream_base=stream.cuda_stream,
-                          stream_corr=stream2.cuda_stream)
+                          stream_corr=stream2.cuda_stream, hetero=hetero)
     ctx.set_state_fn(prob.ic)
     dt = prob.dt()
     ctx.step(warmup, dt)
@@ -376,6 +377,7 @@ DAMBREAK_PAPER_MS = {
                      "ARM-AGX CPU separated": 432.64},
 }
 DAMBREAK_TAU = 1e-2     # indicator threshold (m) of the dynamic setups
+DAMBREAK_HETERO_STEPS = 10   # timed steps of the heterogeneous rows (each stage waits for the host)
 DAMBREAK_DYN_STEPS = 400
 
 
@@ -402,6 +404,14 @@ def run_dambreak(steps, warmup, n=1024):
                 for sep, scheme in ((2, "partitioned"), (1, "separated")):
                     r = run_separated(prob, prec, steps, warmup, separate=sep)
                     row[f"{tag}_{scheme}"] = {"ms_per_stage": r["ms_per_step"] / 2, "value": r["value"]}
+                # the paper's heterogeneous run: the separated scheme's
+                # correction on the host's cores, the base pass on the GPU
+                print(f"bench: dambreak {name} {tag} heterogeneous", file=sys.stderr, flush=True)
+                r = run_separated(prob, prec, DAMBREAK_HETERO_STEPS, 2, separate=1, hetero=1,
+                                  chunk=DAMBREAK_HETERO_STEPS)
+                row[f"{tag}_hetero"] = {"ms_per_stage": r["ms_per_step"] / 2, "value": r["value"],
+                                        "host_threads": len(os.sched_getaffinity(0)),
+                                        "scheme": "separated; correction on the host's cores, base on the GPU"}
         row["paper_ms_per_stage"] = DAMBREAK_PAPER_MS[name]
         out[name] = row
     # dynamic orders: this library's indicator (threshold DAMBREAK_TAU), the

@@ -83,6 +83,16 @@ typedef struct {
                                graph per step (forcing clock on the device) for separated and
                                partitioned steps, plain launches for a fused step; 2 always
                                the graph; 0 always kernel-by-kernel launches */
+    int hetero;             /* 1: heterogeneous stages (the paper's CPU + GPU co-execution,
+                               Sec. "Performance results"): with separate = 1 and a static
+                               order map, the GPU runs the base pass over every element while
+                               the host's cores compute the listed elements' correction (the
+                               same element code, on host copies of the state that listed
+                               elements and their neighbours need, copied down and back each
+                               stage); the GPU joins both in the epilogue.  Steps are
+                               enqueued stage by stage and swe_step returns once the host part
+                               of its last stage is done.  0 (default): every stage on the GPU */
+    int host_threads;       /* host threads of the heterogeneous correction; 0: every usable core */
 } swe_config;
 
 /* Fill *cfg with defaults: FP64, p_base = p_max = 1, g = 9.81, no Coriolis,

@@ -16,7 +16,9 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <sched.h>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -70,6 +72,11 @@ struct swe_ctx {
     // one contiguous range (each group in Morton order)
     bool grouped = false;
     int64_t n_unlisted = 0;
+    int64_t halo_start = 0;               // separated grouping: first unlisted neighbour of a listed element
+    // heterogeneous stages: pinned host copies of the stage input state and
+    // of the correction, and the vertices in the device's layout
+    void *h_C = nullptr, *h_U = nullptr, *h_Lc = nullptr;
+    std::vector<double4> h_vtx;
     hipEvent_t ev_ready = nullptr, ev_corr = nullptr;
     swe_batch *batch = nullptr;           // resident in this batch, or null
     int slot = -1;
@@ -156,6 +163,11 @@ void free_mesh(swe_ctx *c)
     c->d_flag = nullptr; c->d_part = nullptr; c->d_mass = nullptr;
     c->d_inlist = nullptr; c->d_Lb = nullptr; c->d_Lc = nullptr; c->d_list = nullptr; c->d_cnt = nullptr;
     c->d_pnew = nullptr; c->d_I = nullptr;
+    void *h[] = {c->h_C, c->h_U, c->h_Lc};
+    for (void *q : h)
+        if (q) (void)hipHostFree(q);
+    c->h_C = c->h_U = c->h_Lc = nullptr;
+    c->h_vtx.clear();
     c->have_mesh = false;
 }
 
@@ -414,6 +426,94 @@ hipError_t enqueue_separated(Lanes &L, int mode, int in, int out, double tstage,
     return launch_epi_all(b, pm, c->fp32, mode, &a, nblk, lcap, L.a);
 }
 
+// Heterogeneous order-separated stage (a static order map in the separated
+// grouping: unlisted elements, their neighbours of listed elements, then the
+// listed elements of each order).  The GPU runs the base pass over every
+// element; meanwhile the stage's input state of the neighbour and listed
+// ranges comes down to the host, whose threads compute the listed elements'
+// correction with the GPU's element code; the correction goes back up and
+// the epilogue joins it on the GPU.
+template <typename Real>
+hipError_t host_mirrors(swe_ctx *c)
+{
+    if (c->h_C) return hipSuccess;
+    const size_t S = c->stride, K = c->K;
+    hipError_t e = hipHostMalloc(&c->h_C, sizeof(Real) * 3 * K * S, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&c->h_U, sizeof(Real) * 2 * K * S, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&c->h_Lc, sizeof(Real) * 3 * K * S, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    std::memset(c->h_C, 0, sizeof(Real) * 3 * K * S);
+    std::memset(c->h_U, 0, sizeof(Real) * 2 * K * S);
+    std::memset(c->h_Lc, 0, sizeof(Real) * 3 * K * S);
+    c->h_vtx.resize(c->nv);
+    for (int64_t i = 0; i < c->nv; ++i) c->h_vtx[i] = make_double4(c->vx[i], c->vy[i], c->hb[i], 0.0);
+    return hipSuccess;
+}
+
+template <typename Real>
+hipError_t enqueue_separated_hetero(Lanes &L, int mode, int in, int out, double tstage, double dt)
+{
+    swe_ctx *c = L.c;
+    const int b = c->cfg.p_base, pm = c->cfg.p_max;
+    const size_t w = sizeof(Real), S = c->stride, K = c->K;
+    hipError_t e = host_mirrors<Real>(c);
+    if (e != hipSuccess) return e;
+    StageArgs<Real> a = make_args<Real>(c);
+    a.mixed = 0;
+    a.Cin = static_cast<const Real *>(c->d_C[in]);
+    a.Uin = static_cast<const Real *>(c->d_U[in]);
+    a.Cn = static_cast<const Real *>(c->d_C[0]);
+    a.Cout = static_cast<Real *>(c->d_C[out]);
+    a.Uout = static_cast<Real *>(c->d_U[out]);
+    L.time(a, mode == MODE_STAGE2 ? 1 : 0, tstage, dt);
+    a.inlist = c->d_inlist;
+    a.Lb = static_cast<Real *>(c->d_Lb);
+    a.Lc = static_cast<Real *>(c->d_Lc);
+    // the correction stream waits for the previous stage, then brings the
+    // input state of the neighbour and listed ranges down
+    e = L.fork();
+    const int64_t h0 = c->halo_start, l0 = c->n_unlisted, ne = c->ne;
+    if (e == hipSuccess && ne > h0)
+        e = hipMemcpy2DAsync(static_cast<char *>(c->h_C) + w * h0, w * S, static_cast<const char *>(c->d_C[in]) + w * h0,
+                             w * S, w * (ne - h0), 3 * K, hipMemcpyDeviceToHost, c->s_corr);
+    if (e == hipSuccess && ne > h0)
+        e = hipMemcpy2DAsync(static_cast<char *>(c->h_U) + w * h0, w * S, static_cast<const char *>(c->d_U[in]) + w * h0,
+                             w * S, w * (ne - h0), 2 * K, hipMemcpyDeviceToHost, c->s_corr);
+    // the base pass over every element on the GPU meanwhile
+    if (e == hipSuccess) e = launch_base<Real>(L, mode, a, c->ne);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->s_corr);
+    if (e != hipSuccess) return e;
+    // the correction of the listed elements on the host's threads
+    StageArgs<Real> h = a;
+    h.m.vtx = c->h_vtx.data();
+    h.m.ev = c->ev.data();
+    h.m.enb = c->nb_host.data();
+    h.m.enbk = c->nbk_host.data();
+    h.m.ep = nullptr;
+    h.Cin = static_cast<const Real *>(c->h_C);
+    h.Uin = static_cast<const Real *>(c->h_U);
+    h.Lc = static_cast<Real *>(c->h_Lc);
+    h.src = nullptr;
+    int nt = c->cfg.host_threads;
+    if (nt <= 0) {
+        // every core this process may run on
+        cpu_set_t set;
+        CPU_ZERO(&set);
+        nt = sched_getaffinity(0, sizeof(set), &set) == 0 ? CPU_COUNT(&set) : 1;
+        nt = std::max(1, nt);
+    }
+    if (host_corr(b, pm, c->fp32, &h, dt, c->p.data(), (int)l0, (int)ne, nt) != 0) return hipErrorInvalidValue;
+    // back up, then the epilogue joins base part and correction
+    if (ne > l0)
+        e = hipMemcpy2DAsync(static_cast<char *>(c->d_Lc) + w * l0, w * S, static_cast<const char *>(c->h_Lc) + w * l0,
+                             w * S, w * (ne - l0), 3 * K, hipMemcpyHostToDevice, c->s_corr);
+    if (e == hipSuccess) e = L.join();
+    if (e != hipSuccess) return e;
+    a.list = c->d_list;
+    a.count = c->d_cnt;
+    return launch_epi_all(b, pm, c->fp32, mode, &a, list_blocks(c), (int)c->ne, L.a);
+}
+
 // Order-partitioned stage: the base kernel does every element of order
 // p_base whose neighbours are all of order p_base (branch A); each order's
 // listed elements get their full stage from a kernel of that order, all on
@@ -461,6 +561,9 @@ hipError_t enqueue_step(Lanes &L, double tn, double dt)
     if (separated(c) && c->cfg.separate == 2) {
         e = enqueue_partitioned<Real>(L, MODE_STAGE1, 0, 1, tn, dt);
         if (e == hipSuccess) e = enqueue_partitioned<Real>(L, MODE_STAGE2, 1, 0, tn + dt, dt);
+    } else if (separated(c) && c->cfg.hetero) {
+        e = enqueue_separated_hetero<Real>(L, MODE_STAGE1, 0, 1, tn, dt);
+        if (e == hipSuccess) e = enqueue_separated_hetero<Real>(L, MODE_STAGE2, 1, 0, tn + dt, dt);
     } else if (separated(c)) {
         e = enqueue_separated<Real>(L, MODE_STAGE1, 0, 1, tn, dt);
         if (e == hipSuccess) e = enqueue_separated<Real>(L, MODE_STAGE2, 1, 0, tn + dt, dt);
@@ -839,6 +942,7 @@ swe_status group_by_lists(swe_ctx *c)
     order.reserve(ne);
     for (const auto &g : grp) order.insert(order.end(), g.begin(), g.end());
     c->n_unlisted = (int64_t)(grp[0].size() + grp[1].size());
+    c->halo_start = (int64_t)grp[0].size();
     c->grouped = true;
     for (int64_t i = 0; i < ne; ++i)
         if (order[i] != (int)i) return relayout(c, order);
@@ -903,6 +1007,9 @@ swe_status swe_create(const swe_config *cfg, swe_ctx **out)
     if (!(cfg->g > 0.0) || cfg->friction < 0 || cfg->friction > 2) return SWE_EINVAL;
     if (cfg->adapt && !(cfg->adapt_tau > 0.0)) return SWE_EINVAL;
     if (cfg->separate < 0 || cfg->separate > 2) return SWE_EINVAL;
+    // heterogeneous stages: the order-separated scheme on a static order map
+    if (cfg->hetero < 0 || cfg->hetero > 1 || cfg->host_threads < 0) return SWE_EINVAL;
+    if (cfg->hetero && (cfg->separate != 1 || cfg->adapt || cfg->p_base >= cfg->p_max)) return SWE_EINVAL;
     // FP32 order-partitioned stepping with orders up to 3 (its full-order
     // kernels k_full<p, 3, float>) is switched off: one run of it aborted on
     // the device and no cause has been found in the source.  The
@@ -1302,9 +1409,13 @@ swe_status swe_step(swe_ctx *c, int64_t nsteps, double dt)
     if (nsteps == 0) return SWE_OK;
     if (nsteps > INT_MAX) return fail(c, SWE_EINVAL, "too many steps in one call");
     if (c->cfg.adapt) c->uniform = false;   // orders may differ from the first order update on
+    if (c->cfg.hetero && (!c->grouped || c->d_src))
+        return fail(c, SWE_EINVAL, "heterogeneous stages need a static order map (swe_set_order) and no extra source");
     // graphs pay off where a step has many dependent kernels (order-separated
-    // and order-partitioned steps); a fused step is two plain launches
-    const bool graph = c->ncon <= 4 && (c->cfg.step_graph == 2 || (c->cfg.step_graph == 1 && separated(c)));
+    // and order-partitioned steps); a fused step is two plain launches; a
+    // heterogeneous stage waits for the host in the middle: launches
+    const bool graph = c->ncon <= 4 && !c->cfg.hetero &&
+                       (c->cfg.step_graph == 2 || (c->cfg.step_graph == 1 && separated(c)));
     if (graph) {
         swe_status st = ensure_step_graph(c);
         if (st != SWE_OK) return st;

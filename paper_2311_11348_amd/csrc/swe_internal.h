@@ -158,6 +158,12 @@ hipError_t launch_stage_sh(int p, bool fp32, int mode, const void *args, const u
 hipError_t launch_full_all(int lo, int pn, bool fp32, int mode, const void *args, int nblk, int lcap, Sink &k);
 hipError_t launch_corr_all(int b, int pn, bool fp32, const void *args, double dt, int nblk, int lcap, Sink &k);
 hipError_t launch_epi_all(int b, int pn, bool fp32, int mode, const void *args, int nblk, int lcap, Sink &k);
+// The correction of the order-separated scheme for the listed elements
+// [e0, e1) on nthreads host threads (args: host copies of mesh, state and
+// Lc; order: host element orders); the same element code as the GPU's.
+// Returns 0, or -1 for an unsupported (b, pn).
+int host_corr(int b, int pn, bool fp32, const void *args, double dt, const signed char *order, int e0, int e1,
+              int nthreads);
 hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s);
 hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, int p_hi, double *I_out,
                             signed char *p_new, Sink &k);

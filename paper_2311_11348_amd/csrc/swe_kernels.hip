@@ -24,8 +24,11 @@
 #include "swe_internal.h"
 #include "swe_tables.h"
 
+#include <algorithm>
 #include <mutex>
+#include <thread>
 #include <type_traits>
+#include <vector>
 
 namespace swe {
 namespace {
@@ -85,8 +88,13 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return x * q + (x < r ? x : r) + i;
 }
 
+// The element code below is compiled for the host as well: the order-separated
+// scheme's correction can run on the CPU beside the GPU's base pass (the
+// heterogeneous stage).  Only the element-indexed loads and stores differ.
+#define SWE_HD __host__ __device__ __forceinline__
+
 template <typename T>
-__device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+SWE_HD T tmax(T a, T b) { return a > b ? a : b; }
 
 // Element-indexed arrays are read and written through buffer resources: a
 // uniform descriptor (base, byte size) in scalar registers, a uniform byte
@@ -103,27 +111,52 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, unsig
 
 template <typename T>
 struct Buf {
+#if defined(__HIP_DEVICE_COMPILE__)
     __amdgpu_buffer_rsrc_t r;
+#else
+    // on the host: the array and its size, with the same out-of-range
+    // behaviour (loads read 0, stores are dropped)
+    char *base;
+    unsigned size;
+#endif
     int slot_bytes;
-    __device__ __forceinline__ Buf(const T *p, int nslots, int stride)
+    SWE_HD Buf(const T *p, int nslots, int stride)
+#if defined(__HIP_DEVICE_COMPILE__)
         : r(make_rsrc(p, (unsigned)nslots * (unsigned)stride * (unsigned)sizeof(T))),
+#else
+        : base(reinterpret_cast<char *>(const_cast<T *>(p))),
+          size((unsigned)nslots * (unsigned)stride * (unsigned)sizeof(T)),
+#endif
           slot_bytes(stride * (int)sizeof(T)) {}
     // off = element index * sizeof(T)
-    __device__ __forceinline__ T ld(int slot, unsigned off) const
+    SWE_HD T ld(int slot, unsigned off) const
     {
+#if defined(__HIP_DEVICE_COMPILE__)
         if constexpr (sizeof(T) == 8)
             return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, slot * slot_bytes, 0));
         else
             return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, slot * slot_bytes, 0));
+#else
+        const unsigned at = off + (unsigned)(slot * slot_bytes);
+        if (!base || at + sizeof(T) > size) return T(0);
+        T v;
+        __builtin_memcpy(&v, base + at, sizeof(T));
+        return v;
+#endif
     }
-    __device__ __forceinline__ void st(int slot, unsigned off, T v) const
+    SWE_HD void st(int slot, unsigned off, T v) const
     {
+#if defined(__HIP_DEVICE_COMPILE__)
         if constexpr (sizeof(T) == 8)
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off,
                                                   slot * slot_bytes, 0);
         else
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off,
                                                   slot * slot_bytes, 0);
+#else
+        const unsigned at = off + (unsigned)(slot * slot_bytes);
+        if (base && at + sizeof(T) <= size) __builtin_memcpy(base + at, &v, sizeof(T));
+#endif
     }
 };
 
@@ -134,7 +167,7 @@ struct Geo {
 };
 
 // Geometry from the element's vertex ids (already loaded).
-__device__ __forceinline__ void geo_from_ids(const double4 *vtx, const int (&id3)[3], Geo &G)
+SWE_HD void geo_from_ids(const double4 *vtx, const int (&id3)[3], Geo &G)
 {
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
@@ -153,7 +186,7 @@ __device__ __forceinline__ void geo_from_ids(const double4 *vtx, const int (&id3
     G.b11 = a00 * id;
 }
 
-__device__ __forceinline__ void load_geo(const double4 *vtx, const Buf<int> &ev, unsigned offi, Geo &G)
+SWE_HD void load_geo(const double4 *vtx, const Buf<int> &ev, unsigned offi, Geo &G)
 {
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
@@ -179,7 +212,7 @@ struct Fields {
 };
 
 template <int P, typename Real>
-__device__ __forceinline__ void load_state(const Buf<Real> &C, const Buf<Real> &Uv, int KS, unsigned off,
+SWE_HD void load_state(const Buf<Real> &C, const Buf<Real> &Uv, int KS, unsigned off,
                                            Fields<P, Real> &s)
 {
     constexpr int K = Ord<P>::K;
@@ -195,7 +228,7 @@ __device__ __forceinline__ void load_state(const Buf<Real> &C, const Buf<Real> &
 
 // t_i = sum_j C[m][i][j] g_j with the zero pattern folded at compile time
 template <int K, typename T, typename S>
-__device__ __forceinline__ T crow(int m, int i, const S (&g)[K])
+SWE_HD T crow(int m, int i, const S (&g)[K])
 {
     T t = T(0);
 #pragma unroll
@@ -205,7 +238,7 @@ __device__ __forceinline__ T crow(int m, int i, const S (&g)[K])
 }
 
 template <int K>
-__device__ __forceinline__ constexpr bool crow_nonzero(int m, int i)
+SWE_HD constexpr bool crow_nonzero(int m, int i)
 {
     bool any = false;
     for (int j = 0; j < K; ++j) any = any || (TC[m][i][j] != 0.0);
@@ -222,7 +255,7 @@ struct Acc {
     static constexpr bool SPLIT = !std::is_same<Real, double>::value;
     Real L[3][K];
     double W[SPLIT ? 2 : 1][SPLIT ? K : 1];
-    __device__ __forceinline__ double &w(int j, int q)
+    SWE_HD double &w(int j, int q)
     {
         if constexpr (SPLIT) return W[j][q];
         else return L[1 + j][q];
@@ -232,7 +265,7 @@ struct Acc {
 // ------------------------------------------------------------ volume term
 // acc[j][q] += dt sum_k sum_m D[k][q][m] (Bi_kx F^j_x,m + Bi_ky F^j_y,m)
 template <int P, typename Real>
-__device__ __forceinline__ void volume_term(const Fields<P, Real> &s, const double (&hbh)[3],
+SWE_HD void volume_term(const Fields<P, Real> &s, const double (&hbh)[3],
                                             const Geo &G, double g, double dt, Acc<P, Real> &A)
 {
     constexpr int K = Ord<P>::K, KM = Ord<P>::KM;
@@ -321,7 +354,7 @@ __device__ __forceinline__ void volume_term(const Fields<P, Real> &s, const doub
 
 // ------------------------------------------------------------ source term
 template <int P, typename Real>
-__device__ __forceinline__ void source_term(const Fields<P, Real> &s, const Geo &G, const Physics &ph,
+SWE_HD void source_term(const Fields<P, Real> &s, const Geo &G, const Physics &ph,
                                             double dt, Acc<P, Real> &A)
 {
     constexpr int K = Ord<P>::K;
@@ -358,7 +391,7 @@ __device__ __forceinline__ void source_term(const Fields<P, Real> &s, const Geo 
 // ------------------------------------------------------------ edge terms
 // trace on a local edge in Legendre modes: t_a = sum_n f_n R[k][n][a]
 template <int P, typename Real>
-__device__ __forceinline__ void trace_own(int k, const Real (&f)[Ord<P>::K], Real (&t)[Ord<P>::NT])
+SWE_HD void trace_own(int k, const Real (&f)[Ord<P>::K], Real (&t)[Ord<P>::NT])
 {
     constexpr int K = Ord<P>::K, NT = Ord<P>::NT;
 #pragma unroll
@@ -373,7 +406,7 @@ __device__ __forceinline__ void trace_own(int k, const Real (&f)[Ord<P>::K], Rea
 
 // 1D product projected onto Legendre modes c <= P: out_c = sum_ab G[c][a][b] f_a g_b
 template <int NT, typename T>
-__device__ __forceinline__ T prod1(int c, const T (&f)[NT], const T (&g)[NT])
+SWE_HD T prod1(int c, const T (&f)[NT], const T (&g)[NT])
 {
     T acc = 0;
 #pragma unroll
@@ -396,7 +429,7 @@ __device__ __forceinline__ T prod1(int c, const T (&f)[NT], const T (&g)[NT])
 // expanded to NX = max(P, PN) + 1 Legendre modes; the flux is projected onto
 // the own test space (modes <= P).
 template <int P, int PN, typename Real>
-__device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const Buf<Real> &bC, const Buf<Real> &bU,
+SWE_HD void edge_terms(const MeshView &m, unsigned e, const Buf<Real> &bC, const Buf<Real> &bU,
                                            const Buf<int> &bNb,
                                            const Fields<P, Real> &s, const Geo &G, double g,
                                            double xihat, double dt,
@@ -579,7 +612,7 @@ __device__ __forceinline__ void edge_terms(const MeshView &m, unsigned e, const 
 // H_ij = sum_{n < K(max(deg i, deg j))} xi_n C[n][i][j] + sum_{n<3} hb_n C[n][i][j];
 // modes at or above Ke are masked to the identity (element order below P).
 template <int P, typename Real>
-__device__ __forceinline__ void solve_u(const Real (&xi)[Ord<P>::K], const Real (&U)[Ord<P>::K],
+SWE_HD void solve_u(const Real (&xi)[Ord<P>::K], const Real (&U)[Ord<P>::K],
                                         const Real (&V)[Ord<P>::K], const double (&hbh)[3], int Ke,
                                         Real (&u)[Ord<P>::K], Real (&v)[Ord<P>::K])
 {
@@ -647,7 +680,7 @@ __device__ __forceinline__ void solve_u(const Real (&xi)[Ord<P>::K], const Real 
     }
 }
 
-__device__ __forceinline__ void hb_modes(const Geo &G, double (&hbh)[3])
+SWE_HD void hb_modes(const Geo &G, double (&hbh)[3])
 {
 #pragma unroll
     for (int n = 0; n < 3; ++n) hbh[n] = TW[n][0] * G.h[0] + TW[n][1] * G.h[1] + TW[n][2] * G.h[2];
@@ -664,7 +697,7 @@ __device__ __forceinline__ void load_trace_table(Real (*sR)[KN][NX])
 }
 
 template <int P, typename Real>
-__device__ __forceinline__ void acc_init(Acc<P, Real> &A, const Fields<P, Real> &s, bool with_state)
+SWE_HD void acc_init(Acc<P, Real> &A, const Fields<P, Real> &s, bool with_state)
 {
 #pragma unroll
     for (int q = 0; q < Ord<P>::K; ++q) {
@@ -677,7 +710,7 @@ __device__ __forceinline__ void acc_init(Acc<P, Real> &A, const Fields<P, Real> 
 
 // acc += dt L(c) for one element of order P with neighbours of order <= PN
 template <int P, int PN, typename Real>
-__device__ __forceinline__ void element_rhs(const StageArgs<Real> &a, unsigned e, const Buf<Real> &bC,
+SWE_HD void element_rhs(const StageArgs<Real> &a, unsigned e, const Buf<Real> &bC,
                                             const Buf<Real> &bU, const Buf<int> &bNb,
                                             const Fields<P, Real> &s, const Geo &G, const double (&hbh)[3],
                                             double dt, const Real (*sR)[Ord<PN>::K][(P > PN ? P : PN) + 1],
@@ -1475,7 +1508,7 @@ k_full_all(StageArgs<Real> a, int lo, int nblk, int lcap)
 // K(B), the element's and its neighbours' first K(B) modes) in the rows below
 // K(B); the base part is evaluated first and kept, negated, in registers
 template <int P, int B, int PN, typename Real>
-__device__ __forceinline__ void corr_element(const StageArgs<Real> &a, unsigned e,
+SWE_HD void corr_element(const StageArgs<Real> &a, unsigned e,
                                              const Real (*sR)[Ord<PN>::K][PN + 1],
                                              const Real (*sRb)[Ord<B>::K][Ord<B>::NT], double xihat, double dt)
 {
@@ -1547,6 +1580,42 @@ k_corr_all(StageArgs<Real> a, double dt, int nblk, int lcap)
     case 2: if constexpr (B <= 2 && PN >= 2) corr_element<2, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
     case 3: if constexpr (B <= 3 && PN >= 3) corr_element<3, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
     }
+}
+
+// The same correction on the host (the heterogeneous stage): the listed
+// elements [e0, e1) of every order, split over nthreads CPU threads; the
+// arguments point at host copies of the mesh and of the stage's input state,
+// and the correction goes to a host copy of Lc.
+template <int B, int PN, typename Real>
+void host_corr_t(const StageArgs<Real> &a, double dt, const signed char *order, int e0, int e1, int nthreads)
+{
+    constexpr int KN = Ord<PN>::K, NX = PN + 1, KB = Ord<B>::K, NTB = Ord<B>::NT;
+    Real sR[3][KN][NX], sRb[3][KB][NTB];
+    for (int k = 0; k < 3; ++k) {
+        for (int n = 0; n < KN; ++n)
+            for (int c = 0; c < NX; ++c) sR[k][n][c] = Real(TR[k][n][c]);
+        for (int n = 0; n < KB; ++n)
+            for (int c = 0; c < NTB; ++c) sRb[k][n][c] = Real(TR[k][n][c]);
+    }
+    auto work = [&](int lo, int hi) {
+        for (int e = lo; e < hi; ++e) {
+            const unsigned ue = (unsigned)e;
+            switch (order[e]) {
+            case 0: if constexpr (B <= 0) corr_element<0, B, PN, Real>(a, ue, sR, sRb, a.xihat, dt); break;
+            case 1: if constexpr (B <= 1 && PN >= 1) corr_element<1, B, PN, Real>(a, ue, sR, sRb, a.xihat, dt); break;
+            case 2: if constexpr (B <= 2 && PN >= 2) corr_element<2, B, PN, Real>(a, ue, sR, sRb, a.xihat, dt); break;
+            case 3: if constexpr (B <= 3 && PN >= 3) corr_element<3, B, PN, Real>(a, ue, sR, sRb, a.xihat, dt); break;
+            }
+        }
+    };
+    const int n = e1 - e0;
+    if (n <= 0) return;
+    const int nt = std::max(1, std::min(nthreads, (n + 63) / 64));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t)
+        pool.emplace_back(work, e0 + (int)((int64_t)n * t / nt), e0 + (int)((int64_t)n * (t + 1) / nt));
+    work(e0, e0 + (int)((int64_t)n / nt));
+    for (auto &th : pool) th.join();
 }
 
 // epilogue of listed element e of order P (order-separated scheme): stage
@@ -2031,6 +2100,27 @@ hipError_t corr_all_t(int b, int pn, const void *args, double dt, int nblk, int 
     if (b == 1 && pn == 3) return corr_all_r<1, 3, Real>(args, dt, nblk, lcap, k);
     if (b == 2 && pn == 3) return corr_all_r<2, 3, Real>(args, dt, nblk, lcap, k);
     return hipErrorInvalidValue;
+}
+
+template <typename Real>
+int host_corr_r(int b, int pn, const void *args, double dt, const signed char *order, int e0, int e1, int nthreads)
+{
+    const StageArgs<Real> &a = *static_cast<const StageArgs<Real> *>(args);
+    if (b == 0 && pn == 1) host_corr_t<0, 1, Real>(a, dt, order, e0, e1, nthreads);
+    else if (b == 0 && pn == 2) host_corr_t<0, 2, Real>(a, dt, order, e0, e1, nthreads);
+    else if (b == 0 && pn == 3) host_corr_t<0, 3, Real>(a, dt, order, e0, e1, nthreads);
+    else if (b == 1 && pn == 2) host_corr_t<1, 2, Real>(a, dt, order, e0, e1, nthreads);
+    else if (b == 1 && pn == 3) host_corr_t<1, 3, Real>(a, dt, order, e0, e1, nthreads);
+    else if (b == 2 && pn == 3) host_corr_t<2, 3, Real>(a, dt, order, e0, e1, nthreads);
+    else return -1;
+    return 0;
+}
+
+int host_corr(int b, int pn, bool fp32, const void *args, double dt, const signed char *order, int e0, int e1,
+              int nthreads)
+{
+    return fp32 ? host_corr_r<float>(b, pn, args, dt, order, e0, e1, nthreads)
+                : host_corr_r<double>(b, pn, args, dt, order, e0, e1, nthreads);
 }
 
 hipError_t launch_corr_all(int b, int pn, bool fp32, const void *args, double dt, int nblk, int lcap, Sink &k)

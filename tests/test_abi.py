@@ -59,3 +59,17 @@ def test_switched_off_configuration_is_rejected():
     with pytest.raises(swe.SweError) as ei:
         swe.Context(cfg)
     assert ei.value.status == swe.SWE_EINVAL
+
+
+def test_heterogeneous_configuration_checks():
+    """Heterogeneous stages need the order-separated scheme with static
+    orders; other combinations are refused at creation, before any device
+    call (so this runs without a GPU)."""
+    import pytest
+    from paper_2311_11348_amd import swe
+    for kw in (dict(separate=2), dict(separate=0), dict(separate=1, adapt=1), dict(separate=1, p_base=2),
+               dict(separate=1, host_threads=-1)):
+        cfg = swe.Config(p_base=kw.pop("p_base", 1), p_max=2, hetero=1, **kw)
+        with pytest.raises(swe.SweError) as ei:
+            swe.Context(cfg)
+        assert ei.value.status == swe.SWE_EINVAL, kw
