@@ -254,23 +254,31 @@ StageArgs<Real> make_args(const swe_ctx *c)
 
 // Where the kernels of a step go: the context's two streams joined by
 // events, or two branches of a step graph under construction (graph set).
+// A step graph whose orders are re-chosen on the device is one chain (the
+// list kernels after the base pass of the same stage): its lists are short,
+// and a fork and a join cost more than the list kernel's own time (measured
+// on the adaptive tsunami; the static maps of the dam break keep the two
+// branches, where they overlap long lists with the base pass).
 struct Lanes {
     swe_ctx *c;
     Sink a, b;           // base work, correction work
-    bool graph = false;
+    bool graph = false, chain = false;
     explicit Lanes(swe_ctx *cc) : c(cc)
     {
         a.s = c->s_base;
         b.s = c->s_corr;
     }
-    Lanes(swe_ctx *cc, hipGraph_t g) : c(cc), graph(true)
+    Lanes(swe_ctx *cc, hipGraph_t g) : c(cc), graph(true), chain(cc->cfg.adapt != 0)
     {
         a.g = g;
         b.g = g;
     }
+    // where the correction (list) work goes
+    Sink &side() { return chain ? a : b; }
     // the correction branch starts after everything enqueued on the base branch so far
     hipError_t fork()
     {
+        if (chain) return hipSuccess;
         if (graph) {
             b.ndep = a.ndep;
             for (int i = 0; i < Sink::MAXDEP; ++i) b.dep[i] = a.dep[i];
@@ -282,6 +290,7 @@ struct Lanes {
     // base work enqueued next waits for the correction branch
     hipError_t join()
     {
+        if (chain) return hipSuccess;
         if (graph) return a.join(b) ? hipSuccess : hipErrorInvalidValue;
         const hipError_t e = hipEventRecord(c->ev_corr, c->s_corr);
         return e == hipSuccess ? hipStreamWaitEvent(c->s_base, c->ev_corr, 0) : e;
@@ -419,7 +428,7 @@ hipError_t enqueue_separated(Lanes &L, int mode, int in, int out, double tstage,
     a.list = c->d_list;
     a.count = c->d_cnt;
     const int nblk = list_blocks(c), lcap = (int)c->ne;
-    e = launch_corr_all(b, pm, c->fp32, &a, dt, nblk, lcap, L.b);
+    e = launch_corr_all(b, pm, c->fp32, &a, dt, nblk, lcap, L.side());
     if (e != hipSuccess) return e;
     e = L.join();
     if (e != hipSuccess) return e;
@@ -543,7 +552,7 @@ hipError_t enqueue_partitioned(Lanes &L, int mode, int in, int out, double tstag
     a.skip_listed = 0;
     a.list = c->d_list;
     a.count = c->d_cnt;
-    e = launch_full_all(b, pm, c->fp32, mode, &a, list_blocks(c), (int)c->ne, L.b);
+    e = launch_full_all(b, pm, c->fp32, mode, &a, list_blocks(c), (int)c->ne, L.side());
     if (e != hipSuccess) return e;
     return L.join();
 }

@@ -65,13 +65,6 @@ constexpr int waves_target()
                   : P <= 1 ? 2 : (std::is_same<Real, double>::value ? SWE_WAVES_FP64 : SWE_WAVES_FP32);
 }
 
-// Occupancy of the list kernels (corrections, full-order stages of listed elements)
-template <int P, typename Real>
-constexpr int list_waves()
-{
-    return (P >= 3 && !std::is_same<Real, double>::value) ? SWE_WAVES_FP32_P3 : 1;
-}
-
 template <int P>
 struct Ord {
     static constexpr int K = (P + 1) * (P + 2) / 2;   // modes of P^p
@@ -103,6 +96,8 @@ SWE_HD T tmax(T a, T b) { return a > b ? a : b; }
 // (which the host never issues) reads 0 instead of faulting.
 constexpr int RSRC_WORD3 = 0x00020000;   // raw 32-bit access, gfx9 family
 typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+// cache-policy operand of a buffer access: the non-temporal bit (gfx94x/gfx950)
+constexpr int CPOL_NT = 2;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, unsigned bytes)
 {
@@ -142,6 +137,21 @@ struct Buf {
         T v;
         __builtin_memcpy(&v, base + at, sizeof(T));
         return v;
+#endif
+    }
+    // a store that is not kept in the caches (the non-temporal policy bit):
+    // for results no block of the same launch reads back
+    SWE_HD void st_stream(int slot, unsigned off, T v) const
+    {
+#if defined(__HIP_DEVICE_COMPILE__)
+        if constexpr (sizeof(T) == 8)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off,
+                                                  slot * slot_bytes, CPOL_NT);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off,
+                                                  slot * slot_bytes, CPOL_NT);
+#else
+        st(slot, off, v);
 #endif
     }
     SWE_HD void st(int slot, unsigned off, T v) const
@@ -263,18 +273,19 @@ struct Acc {
 };
 
 // ------------------------------------------------------------ volume term
-// acc[j][q] += dt sum_k sum_m D[k][q][m] (Bi_kx F^j_x,m + Bi_ky F^j_y,m)
-template <int P, typename Real>
+// acc[j][q] += dt sum_k sum_m D[k][q][m] (Bi_kx F^j_x,m + Bi_ky F^j_y,m), over the
+// projected modes M0 <= m < M1 (all of them by default)
+template <int P, typename Real, int M0 = 0, int M1 = Ord<P>::KM>
 SWE_HD void volume_term(const Fields<P, Real> &s, const double (&hbh)[3],
                                             const Geo &G, double g, double dt, Acc<P, Real> &A)
 {
     constexpr int K = Ord<P>::K, KM = Ord<P>::KM;
-    if constexpr (KM > 0) {
+    if constexpr (KM > 0 && M0 < M1) {
         Real Fx[3][KM], Fy[3][KM];
         double FW[KM];
         const Real hg = Real(0.5 * g);
 #pragma unroll
-        for (int m = 0; m < KM; ++m) {
+        for (int m = M0; m < M1; ++m) {
             Real pUu = 0, pUv = 0, pVu = 0, pVv = 0, pxx = 0;
             double pxh = 0.0;
 #pragma unroll
@@ -308,7 +319,7 @@ SWE_HD void volume_term(const Fields<P, Real> &s, const double (&hbh)[3],
         for (int j = 0; j < 3; ++j) {
             Real G0[KM], G1[KM];
 #pragma unroll
-            for (int m = 0; m < KM; ++m) {
+            for (int m = M0; m < M1; ++m) {
                 G0[m] = fma(b00, Fx[j][m], b01 * Fy[j][m]);
                 G1[m] = fma(b10, Fx[j][m], b11 * Fy[j][m]);
             }
@@ -316,7 +327,7 @@ SWE_HD void volume_term(const Fields<P, Real> &s, const double (&hbh)[3],
             for (int q = 0; q < K; ++q) {
                 Real acc = A.L[j][q];
 #pragma unroll
-                for (int m = 0; m < KM; ++m) {
+                for (int m = M0; m < M1; ++m) {
                     if (TD[0][q][m] != 0.0) acc = fma(Real(TD[0][q][m]), G0[m], acc);
                     if (TD[1][q][m] != 0.0) acc = fma(Real(TD[1][q][m]), G1[m], acc);
                 }
@@ -326,7 +337,7 @@ SWE_HD void volume_term(const Fields<P, Real> &s, const double (&hbh)[3],
         // bathymetry part of the pressure: x-momentum uses Bi_kx, y-momentum Bi_ky
         double Wx[KM], Wy[KM], Zx[KM], Zy[KM];
 #pragma unroll
-        for (int m = 0; m < KM; ++m) {
+        for (int m = M0; m < M1; ++m) {
             Wx[m] = G.b00 * FW[m];
             Wy[m] = G.b01 * FW[m];
             Zx[m] = G.b10 * FW[m];
@@ -336,7 +347,7 @@ SWE_HD void volume_term(const Fields<P, Real> &s, const double (&hbh)[3],
         for (int q = 0; q < K; ++q) {
             double ax = A.w(0, q), ay = A.w(1, q);
 #pragma unroll
-            for (int m = 0; m < KM; ++m) {
+            for (int m = M0; m < M1; ++m) {
                 if (TD[0][q][m] != 0.0) {
                     ax = fma(TD[0][q][m], Wx[m], ax);
                     ay = fma(TD[0][q][m], Wy[m], ay);
@@ -428,13 +439,11 @@ SWE_HD T prod1(int c, const T (&f)[NT], const T (&g)[NT])
 // (their stored modes above their own order are zero).  Both traces are
 // expanded to NX = max(P, PN) + 1 Legendre modes; the flux is projected onto
 // the own test space (modes <= P).
-template <int P, int PN, typename Real>
-SWE_HD void edge_terms(const MeshView &m, unsigned e, const Buf<Real> &bC, const Buf<Real> &bU,
-                                           const Buf<int> &bNb,
-                                           const Fields<P, Real> &s, const Geo &G, double g,
-                                           double xihat, double dt,
-                                           const Real (*sR)[Ord<PN>::K][(P > PN ? P : PN) + 1],
-                                           Acc<P, Real> &A)
+// The edge term of local edge k (its flux lifted onto the element's modes).
+template <int P, int PN, typename Real, int k>
+SWE_HD void edge_one(const MeshView &m, unsigned e, const Buf<Real> &bC, const Buf<Real> &bU,
+                     const Buf<int> &bNb, const Fields<P, Real> &s, const Geo &G, double g, double xihat,
+                     double dt, const Real (*sR)[Ord<PN>::K][(P > PN ? P : PN) + 1], Acc<P, Real> &A)
 {
     constexpr int K = Ord<P>::K, NT = Ord<P>::NT, KN = Ord<PN>::K;
     constexpr int NX = (P > PN ? P : PN) + 1;
@@ -445,9 +454,8 @@ SWE_HD void edge_terms(const MeshView &m, unsigned e, const Buf<Real> &bC, const
     // With the edge vector's normal nu = |E| n (no square root), every flux
     // term carries |E| n or |E| lambda, and |E| / |det B| folds into dt / |det B|.
     const double dt_det = dt / G.det;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int ka = (k + 1) % 3, kb = (k + 2) % 3;
+    {
+        constexpr int ka = (k + 1) % 3, kb = (k + 2) % 3;
         const double dx = G.X[kb] - G.X[ka], dy = G.Y[kb] - G.Y[ka];
         const double len2 = dx * dx + dy * dy;
         const Real nx = Real(dy), ny = Real(-dx);          // |E| n
@@ -608,6 +616,19 @@ SWE_HD void edge_terms(const MeshView &m, unsigned e, const Buf<Real> &bC, const
     }
 }
 
+template <int P, int PN, typename Real>
+SWE_HD void edge_terms(const MeshView &m, unsigned e, const Buf<Real> &bC, const Buf<Real> &bU,
+                                           const Buf<int> &bNb,
+                                           const Fields<P, Real> &s, const Geo &G, double g,
+                                           double xihat, double dt,
+                                           const Real (*sR)[Ord<PN>::K][(P > PN ? P : PN) + 1],
+                                           Acc<P, Real> &A)
+{
+    edge_one<P, PN, Real, 0>(m, e, bC, bU, bNb, s, G, g, xihat, dt, sR, A);
+    edge_one<P, PN, Real, 1>(m, e, bC, bU, bNb, s, G, g, xihat, dt, sR, A);
+    edge_one<P, PN, Real, 2>(m, e, bC, bU, bNb, s, G, g, xihat, dt, sR, A);
+}
+
 // ------------------------------------------------------------ u H = q
 // H_ij = sum_{n < K(max(deg i, deg j))} xi_n C[n][i][j] + sum_{n<3} hb_n C[n][i][j];
 // modes at or above Ke are masked to the identity (element order below P).
@@ -763,13 +784,24 @@ __device__ __forceinline__ void finish_stage(const StageArgs<Real> &a, unsigned 
     solve_u<P, Real>(xn, Un, Vn, hbh, Ke, un, vn);
     Real chk = 0;
     const Buf<Real> bO(a.Cout, 3 * KS, stride), bV(a.Uout, 2 * KS, stride);
+    // FP64 results are streamed past the caches (measured: 4 % shorter FP64
+    // stages at p = 2, while the same policy lengthens FP32 stages by 4 %)
+    constexpr bool stream = sizeof(Real) == 8;
 #pragma unroll
     for (int q = 0; q < K; ++q) {
-        bO.st(0 * KS + q, off, xn[q]);
-        bO.st(1 * KS + q, off, Un[q]);
-        bO.st(2 * KS + q, off, Vn[q]);
-        bV.st(0 * KS + q, off, un[q]);
-        bV.st(1 * KS + q, off, vn[q]);
+        if constexpr (stream) {
+            bO.st_stream(0 * KS + q, off, xn[q]);
+            bO.st_stream(1 * KS + q, off, Un[q]);
+            bO.st_stream(2 * KS + q, off, Vn[q]);
+            bV.st_stream(0 * KS + q, off, un[q]);
+            bV.st_stream(1 * KS + q, off, vn[q]);
+        } else {
+            bO.st(0 * KS + q, off, xn[q]);
+            bO.st(1 * KS + q, off, Un[q]);
+            bO.st(2 * KS + q, off, Vn[q]);
+            bV.st(0 * KS + q, off, un[q]);
+            bV.st(1 * KS + q, off, vn[q]);
+        }
         chk += xn[q] + Un[q] + Vn[q] + un[q] + vn[q];
     }
     const double Hmean = SQRT2 * double(xn[0]) + (G.h[0] + G.h[1] + G.h[2]) * (1.0 / 3.0);
@@ -1429,14 +1461,26 @@ __global__ void __launch_bounds__(BLOCK) k_batch_clock(InstDesc *inst, const int
 }
 
 // ------------------------------------------------------------ listed elements, every order in one launch
-// The kernels of the listed elements take every order in one launch: block b
-// works on order lo + b / nblk (each block runs one order's code) and on
-// entry (b % nblk) * BLOCK + lane of that order's list (at a.list + p * lcap;
-// its length a.count[p]).  A step graph dispatches its nodes one after
-// another, microseconds apart, so one node per stage for all orders ends the
-// stage sooner than one node per order.
-__device__ __forceinline__ int list_order(int lo, int nblk) { return lo + (int)blockIdx.x / nblk; }
-__device__ __forceinline__ int list_entry(int nblk) { return ((int)blockIdx.x % nblk) * BLOCK + (int)threadIdx.x; }
+// The kernels of the listed elements take every order in one launch (each
+// block runs one order's code; order p's list at a.list + p * lcap, its
+// length a.count[p]).  A step graph dispatches its nodes one after another,
+// microseconds apart, so one node per stage for all orders ends the stage
+// sooner than one node per order.  Block b over the orders lo..PN takes
+// order lo + b % (PN - lo + 1) and the (b / (PN - lo + 1))-th run of BLOCK
+// list entries (of TEAM entries where a team takes them): the orders are
+// interleaved, so the blocks dispatched first hold the heads of every
+// order's list.  Lists re-chosen on the device are sized
+// for every element and are mostly empty; a block past its list's end leaves
+// before it loads anything else (the test is uniform over the block).
+template <int PN>
+__device__ __forceinline__ int list_order(int lo) { return lo + (int)blockIdx.x % (PN - lo + 1); }
+template <int PN>
+__device__ __forceinline__ int list_block(int lo) { return (int)blockIdx.x / (PN - lo + 1); }
+__device__ __forceinline__ int list_len(const int *count, int p, int lcap)
+{
+    const int n = count[p];
+    return n < lcap ? n : lcap;
+}
 
 // Element of entry i of order p's list, or -1 past the list's end.  The
 // count is capped at the list's capacity and an entry outside the mesh is
@@ -1451,7 +1495,111 @@ __device__ __forceinline__ int list_element(const StageArgs<Real> &a, int p, int
     return (e >= 0 && e < a.m.ne) ? e : -1;
 }
 
-// full stage of listed element e of order P (order-partitioned scheme)
+// ---- teams: the listed elements' work shared by the waves of a block
+// One thread's evaluation of an order-3 element is thousands of dependent
+// instructions, and the few such elements end the stage.  A team block takes
+// TEAM list entries, one per lane, and each of its four waves does one part
+// of every entry's right-hand side: wave 0 the volume and source terms, wave
+// 1 + k the term of local edge k.  Waves 1..3 leave their partial sums in
+// LDS; wave 0 adds them in edge order and finishes the element.
+// Teams take the short lists (at most TEAM_MAX entries), where the stage
+// waits on each element's latency, and every list of a kernel that reaches
+// order 3; a long list of a kernel up to order 2 keeps one element per
+// thread, which does less work in all.  (One thread per order-3 element needs
+// more registers than a lane has, and the one-thread code of the lower orders
+// beside the order-3 teams would cost those teams registers.)
+constexpr int TEAM = 64;
+constexpr int TEAM_ROLES = 4;
+constexpr int TEAM_MAX = 16384;
+
+template <int PN>
+__device__ __forceinline__ bool list_by_teams(int len) { return PN >= 3 || len <= TEAM_MAX; }
+
+template <int PN, typename Real>
+struct TeamLds {
+    static constexpr int K = Ord<PN>::K;
+    static constexpr bool SPLIT = !std::is_same<Real, double>::value;
+    Real L[TEAM_ROLES - 1][3][K][TEAM];
+    double W[TEAM_ROLES - 1][SPLIT ? 2 : 1][SPLIT ? K : 1][TEAM];
+};
+
+template <int P, int PN, typename Real>
+__device__ __forceinline__ void team_put(TeamLds<PN, Real> &X, int role, int lane, const Acc<P, Real> &A)
+{
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int q = 0; q < Ord<P>::K; ++q) X.L[role - 1][j][q][lane] = A.L[j][q];
+    if constexpr (Acc<P, Real>::SPLIT) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < Ord<P>::K; ++q) X.W[role - 1][j][q][lane] = A.W[j][q];
+    }
+}
+
+// wave 0's sums plus the edge waves' partial sums, in edge order; the FP64
+// bathymetry sums of the FP32 path are added to the momentum rows last
+template <int P, int PN, typename Real>
+__device__ __forceinline__ void team_sum(const TeamLds<PN, Real> &X, int lane, Acc<P, Real> &A)
+{
+#pragma unroll
+    for (int r = 0; r < TEAM_ROLES - 1; ++r) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int q = 0; q < Ord<P>::K; ++q) A.L[j][q] += X.L[r][j][q][lane];
+        if constexpr (Acc<P, Real>::SPLIT) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < Ord<P>::K; ++q) A.W[j][q] += X.W[r][j][q][lane];
+        }
+    }
+    if constexpr (Acc<P, Real>::SPLIT) {
+#pragma unroll
+        for (int q = 0; q < Ord<P>::K; ++q) {
+            A.L[1][q] += Real(A.W[0][q]);
+            A.L[2][q] += Real(A.W[1][q]);
+        }
+    }
+}
+
+// acc += dt * (extra right-hand side) (wave 0's part)
+template <int P, typename Real>
+__device__ __forceinline__ void team_src(const StageArgs<Real> &a, unsigned e, double dt, Acc<P, Real> &A)
+{
+    if (!a.src) return;
+    const Buf<Real> bS(a.src, 3 * a.m.KS, a.m.stride);
+    const Real rdt = Real(dt);
+    const unsigned off = e * (unsigned)sizeof(Real);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int q = 0; q < Ord<P>::K; ++q) A.L[j][q] = fma(rdt, bS.ld(j * a.m.KS + q, off), A.L[j][q]);
+}
+
+// one wave's part (role) of element e's right-hand side, added to A
+template <int P, int PN, typename Real>
+__device__ __forceinline__ void team_part(int role, const StageArgs<Real> &a, unsigned e, const Buf<Real> &bC,
+                                          const Buf<Real> &bU, const Buf<int> &bNb, const Fields<P, Real> &s,
+                                          const Geo &G, const double (&hbh)[3], double dt,
+                                          const Real (*sR)[Ord<PN>::K][(P > PN ? P : PN) + 1], double xihat,
+                                          Acc<P, Real> &A)
+{
+    switch (role) {
+    case 0:
+        volume_term<P, Real>(s, hbh, G, a.ph.g, dt, A);
+        source_term<P, Real>(s, G, a.ph, dt, A);
+        team_src<P, Real>(a, e, dt, A);
+        break;
+    case 1: edge_one<P, PN, Real, 0>(a.m, e, bC, bU, bNb, s, G, a.ph.g, xihat, dt, sR, A); break;
+    case 2: edge_one<P, PN, Real, 1>(a.m, e, bC, bU, bNb, s, G, a.ph.g, xihat, dt, sR, A); break;
+    default: edge_one<P, PN, Real, 2>(a.m, e, bC, bU, bNb, s, G, a.ph.g, xihat, dt, sR, A); break;
+    }
+}
+
+// full stage of listed element e of order P (order-partitioned scheme), one thread
 template <int P, int PN, typename Real, int MODE>
 __device__ __forceinline__ void full_element(const StageArgs<Real> &a, unsigned e,
                                              const Real (*sR)[Ord<PN>::K][PN + 1], double xihat, double dt)
@@ -1473,33 +1621,82 @@ __device__ __forceinline__ void full_element(const StageArgs<Real> &a, unsigned 
     finish_stage<P, Real, MODE>(a, e, G, hbh, Ord<P>::K, A.L, a.flag);
 }
 
+// the same by a team; live is false on lanes past the list's end, which only
+// meet the barrier
+template <int P, int PN, typename Real, int MODE>
+__device__ __forceinline__ void full_team(const StageArgs<Real> &a, int le, int role,
+                                          const Real (*sR)[Ord<PN>::K][PN + 1], TeamLds<PN, Real> &X,
+                                          double xihat, double dt)
+{
+    const MeshView &m = a.m;
+    const int KS = m.KS, stride = m.stride, lane = (int)threadIdx.x % TEAM;
+    const bool live = le >= 0;
+    const unsigned e = live ? (unsigned)le : 0u;
+    const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
+    const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
+    Geo G;
+    double hbh[3];
+    Acc<P, Real> A;
+    if (live) {
+        load_geo(m.vtx, bEv, e * 4u, G);
+        hb_modes(G, hbh);
+        Fields<P, Real> s;
+        load_state<P, Real>(bC, bU, KS, e * (unsigned)sizeof(Real), s);
+        acc_init<P, Real>(A, s, role == 0);
+        team_part<P, PN, Real>(role, a, e, bC, bU, bNb, s, G, hbh, dt, sR, xihat, A);
+        if (role > 0) team_put<P, PN, Real>(X, role, lane, A);
+    }
+    __syncthreads();
+    if (role == 0 && live) {
+        team_sum<P, PN, Real>(X, lane, A);
+        finish_stage<P, Real, MODE>(a, e, G, hbh, Ord<P>::K, A.L, a.flag);
+    }
+}
+
 template <int PN, typename Real, int MODE>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<PN, Real>(), 8)))
-k_full_all(StageArgs<Real> a, int lo, int nblk, int lcap)
+__global__ void __launch_bounds__(TEAM * TEAM_ROLES) __attribute__((amdgpu_waves_per_eu(1, 8)))
+k_full_all(StageArgs<Real> a, int lo, int lcap)
 {
     // beside the base kernel over all elements, these end the stage: their
     // waves issue first on a shared SIMD
     __builtin_amdgcn_s_setprio(2);
     constexpr int NX = PN + 1, KN = Ord<PN>::K;
     __shared__ Real sR[3][KN][NX];
-    load_trace_table<KN, NX, Real>(sR);
-    __syncthreads();
-    const int p = list_order(lo, nblk);
-    if (p > PN) return;
-    const int le = list_element(a, p, list_entry(nblk), lcap);
-    if (le < 0) return;
-    const unsigned e = (unsigned)le;
+    __shared__ TeamLds<PN, Real> X;
+    const int p = list_order<PN>(lo), len = list_len(a.count, p, lcap);
+    const bool team = list_by_teams<PN>(len);
+    int c = list_block<PN>(lo);
+    if (c * (team ? TEAM : BLOCK) >= len) return;
     double xihat = a.xihat, dt = a.dt;
     if (a.inst) {
-        if (!a.inst->run) return;   // the step's clock stopped (failure)
+        if (!a.inst->run) return;   // the step's clock stopped (failure); uniform over the block
         xihat = MODE == MODE_STAGE2 ? a.inst->xh[1] : a.inst->xh[0];
         dt = a.inst->dt;
     }
-    switch (p) {
-    case 0: full_element<0, PN, Real, MODE>(a, e, sR, xihat, dt); break;
-    case 1: if constexpr (PN >= 1) full_element<1, PN, Real, MODE>(a, e, sR, xihat, dt); break;
-    case 2: if constexpr (PN >= 2) full_element<2, PN, Real, MODE>(a, e, sR, xihat, dt); break;
-    case 3: if constexpr (PN >= 3) full_element<3, PN, Real, MODE>(a, e, sR, xihat, dt); break;
+    load_trace_table<KN, NX, Real>(sR);
+    __syncthreads();
+    if (team) {
+        // one run per block (the grid covers every run, see list_grid)
+        const int role = __builtin_amdgcn_readfirstlane((int)threadIdx.x / TEAM);
+        const int le = list_element(a, p, c * TEAM + (int)threadIdx.x % TEAM, lcap);
+        switch (p) {
+        case 0: full_team<0, PN, Real, MODE>(a, le, role, sR, X, xihat, dt); break;
+        case 1: if constexpr (PN >= 1) full_team<1, PN, Real, MODE>(a, le, role, sR, X, xihat, dt); break;
+        case 2: if constexpr (PN >= 2) full_team<2, PN, Real, MODE>(a, le, role, sR, X, xihat, dt); break;
+        case 3: if constexpr (PN >= 3) full_team<3, PN, Real, MODE>(a, le, role, sR, X, xihat, dt); break;
+        }
+        return;
+    }
+    // one element per thread
+    if constexpr (PN < 3) {
+        const int le = list_element(a, p, c * BLOCK + (int)threadIdx.x, lcap);
+        if (le < 0) return;
+        const unsigned e = (unsigned)le;
+        switch (p) {
+        case 0: full_element<0, PN, Real, MODE>(a, e, sR, xihat, dt); break;
+        case 1: if constexpr (PN >= 1) full_element<1, PN, Real, MODE>(a, e, sR, xihat, dt); break;
+        case 2: if constexpr (PN >= 2) full_element<2, PN, Real, MODE>(a, e, sR, xihat, dt); break;
+        }
     }
 }
 
@@ -1550,35 +1747,111 @@ SWE_HD void corr_element(const StageArgs<Real> &a, unsigned e,
         }
 }
 
+// correction of listed element e of order P by a team: each wave's part of
+// the full right-hand side minus its part of the base one (rows below K(B);
+// the base part reads the element's and its neighbours' first K(B) modes),
+// summed by wave 0, which stores dt times the correction
+template <int P, int B, int PN, typename Real>
+__device__ __forceinline__ void corr_team(const StageArgs<Real> &a, int le, int role,
+                                          const Real (*sR)[Ord<PN>::K][PN + 1],
+                                          const Real (*sRb)[Ord<B>::K][Ord<B>::NT], TeamLds<PN, Real> &X,
+                                          double xihat, double dt)
+{
+    constexpr int K = Ord<P>::K, KB = Ord<B>::K;
+    const MeshView &m = a.m;
+    const int KS = m.KS, stride = m.stride, lane = (int)threadIdx.x % TEAM;
+    const bool live = le >= 0;
+    const unsigned e = live ? (unsigned)le : 0u;
+    const unsigned off = e * (unsigned)sizeof(Real);
+    const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
+    const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
+    Acc<P, Real> A;
+    if (live) {
+        Geo G;
+        load_geo(m.vtx, bEv, e * 4u, G);
+        double hbh[3];
+        hb_modes(G, hbh);
+        Fields<P, Real> s;
+        load_state<P, Real>(bC, bU, KS, off, s);
+        {
+            Fields<B, Real> sb;
+#pragma unroll
+            for (int q = 0; q < KB; ++q) {
+                sb.xi[q] = s.xi[q]; sb.U[q] = s.U[q]; sb.V[q] = s.V[q]; sb.u[q] = s.u[q]; sb.v[q] = s.v[q];
+            }
+            Acc<B, Real> Ab;
+            acc_init<B, Real>(Ab, sb, false);
+            team_part<B, B, Real>(role, a, e, bC, bU, bNb, sb, G, hbh, dt, sRb, xihat, Ab);
+            acc_init<P, Real>(A, s, false);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int q = 0; q < KB; ++q) A.L[j][q] = -Ab.L[j][q];
+            if constexpr (Acc<P, Real>::SPLIT) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int q = 0; q < KB; ++q) A.W[j][q] = -Ab.W[j][q];
+            }
+        }
+        team_part<P, PN, Real>(role, a, e, bC, bU, bNb, s, G, hbh, dt, sR, xihat, A);
+        if (role > 0) team_put<P, PN, Real>(X, role, lane, A);
+    }
+    __syncthreads();
+    if (role == 0 && live) {
+        team_sum<P, PN, Real>(X, lane, A);
+        const Buf<Real> bL(a.Lc, 3 * KS, stride);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int q = 0; q < K; ++q) bL.st(j * KS + q, off, A.L[j][q]);
+    }
+}
+
 template <int B, int PN, typename Real>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(list_waves<PN, Real>(), 8)))
-k_corr_all(StageArgs<Real> a, double dt, int nblk, int lcap)
+__global__ void __launch_bounds__(TEAM * TEAM_ROLES) __attribute__((amdgpu_waves_per_eu(1, 8)))
+k_corr_all(StageArgs<Real> a, double dt, int lcap)
 {
     __builtin_amdgcn_s_setprio(2);   // as in k_full_all
     constexpr int KB = Ord<B>::K, NTB = Ord<B>::NT;
     constexpr int KN = Ord<PN>::K, NX = PN + 1;
     __shared__ Real sR[3][KN][NX];
     __shared__ Real sRb[3][KB][NTB];
-    load_trace_table<KN, NX, Real>(sR);
-    load_trace_table<KB, NTB, Real>(sRb);
-    __syncthreads();
-    const int p = list_order(B, nblk);
-    if (p > PN) return;
-    const int le = list_element(a, p, list_entry(nblk), lcap);
-    if (le < 0) return;
-    const unsigned e = (unsigned)le;
+    __shared__ TeamLds<PN, Real> X;
+    const int p = list_order<PN>(B), len = list_len(a.count, p, lcap);
+    const bool team = list_by_teams<PN>(len);
+    int c = list_block<PN>(B);
+    if (c * (team ? TEAM : BLOCK) >= len) return;
     double xihat = a.xihat;
     if (a.inst) {
         // the clock of a replayed step lives on the device
-        if (!a.inst->run) return;   // the step's clock stopped (failure)
+        if (!a.inst->run) return;   // the step's clock stopped (failure); uniform over the block
         xihat = a.inst->xh[a.stage];
         dt = a.inst->dt;
     }
-    switch (p) {
-    case 0: if constexpr (B <= 0) corr_element<0, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
-    case 1: if constexpr (B <= 1 && PN >= 1) corr_element<1, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
-    case 2: if constexpr (B <= 2 && PN >= 2) corr_element<2, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
-    case 3: if constexpr (B <= 3 && PN >= 3) corr_element<3, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
+    load_trace_table<KN, NX, Real>(sR);
+    load_trace_table<KB, NTB, Real>(sRb);
+    __syncthreads();
+    if (team) {   // as in k_full_all
+        const int role = __builtin_amdgcn_readfirstlane((int)threadIdx.x / TEAM);
+        const int le = list_element(a, p, c * TEAM + (int)threadIdx.x % TEAM, lcap);
+        switch (p) {
+        case 0: if constexpr (B <= 0) corr_team<0, B, PN, Real>(a, le, role, sR, sRb, X, xihat, dt); break;
+        case 1: if constexpr (B <= 1 && PN >= 1) corr_team<1, B, PN, Real>(a, le, role, sR, sRb, X, xihat, dt); break;
+        case 2: if constexpr (B <= 2 && PN >= 2) corr_team<2, B, PN, Real>(a, le, role, sR, sRb, X, xihat, dt); break;
+        case 3: if constexpr (B <= 3 && PN >= 3) corr_team<3, B, PN, Real>(a, le, role, sR, sRb, X, xihat, dt); break;
+        }
+        return;
+    }
+    if constexpr (PN < 3) {
+        const int le = list_element(a, p, c * BLOCK + (int)threadIdx.x, lcap);
+        if (le < 0) return;
+        const unsigned e = (unsigned)le;
+        switch (p) {
+        case 0: if constexpr (B <= 0) corr_element<0, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
+        case 1: if constexpr (B <= 1 && PN >= 1) corr_element<1, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
+        case 2: if constexpr (B <= 2 && PN >= 2) corr_element<2, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
+        }
     }
 }
 
@@ -1645,11 +1918,11 @@ __device__ __forceinline__ void epi_element(const StageArgs<Real> &a, unsigned e
 
 template <int PN, typename Real, int MODE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
-k_epi_all(StageArgs<Real> a, int KB, int lo, int nblk, int lcap)
+k_epi_all(StageArgs<Real> a, int KB, int lo, int lcap)
 {
-    const int p = list_order(lo, nblk);
-    if (p > PN) return;
-    const int le = list_element(a, p, list_entry(nblk), lcap);
+    const int p = list_order<PN>(lo), first = list_block<PN>(lo) * BLOCK;
+    if (first >= list_len(a.count, p, lcap)) return;
+    const int le = list_element(a, p, first + (int)threadIdx.x, lcap);
     if (le < 0) return;
     const unsigned e = (unsigned)le;
     if (a.inst && !a.inst->run) return;   // the step's clock stopped (failure)
@@ -2056,12 +2329,27 @@ hipError_t launch_stage(int p, bool fp32, int mode, bool sep, const void *args, 
     return launch_stage(p, fp32, mode, sep, args, k);
 }
 
+// Blocks per order of a list kernel whose longest possible list fills nblk
+// runs of BLOCK entries: a kernel that reaches order 3 takes every list in
+// TEAM-entry runs (4 nblk blocks); below order 3 a block takes a run of BLOCK
+// entries (nblk blocks) or, for a list of at most TEAM_MAX entries, a run of
+// TEAM entries (at most TEAM_MAX / TEAM blocks).  Lists re-chosen on the
+// device are mostly empty, and each block costs a dispatch even when it
+// finds nothing to do: no more blocks than these.
+int list_grid(int nblk, int pn)
+{
+    const int runs = nblk * (BLOCK / TEAM);
+    if (pn >= 3) return runs;
+    const int teams = runs < TEAM_MAX / TEAM ? runs : TEAM_MAX / TEAM;
+    return nblk > teams ? nblk : teams;
+}
+
 template <int PN, typename Real>
 hipError_t full_all_r(int mode, const void *args, int lo, int nblk, int lcap, Sink &s)
 {
     StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
-    void *kargs[] = {&a, &lo, &nblk, &lcap};
-    const dim3 g((PN - lo + 1) * nblk), b(BLOCK);
+    void *kargs[] = {&a, &lo, &lcap};
+    const dim3 g((PN - lo + 1) * list_grid(nblk, PN)), b(TEAM * TEAM_ROLES);
     return emit(s,
                 mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_full_all<PN, Real, MODE_STAGE1>)
                                     : reinterpret_cast<const void *>(&k_full_all<PN, Real, MODE_STAGE2>),
@@ -2085,9 +2373,9 @@ template <int B, int PN, typename Real>
 hipError_t corr_all_r(const void *args, double dt, int nblk, int lcap, Sink &s)
 {
     StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
-    void *kargs[] = {&a, &dt, &nblk, &lcap};
-    return emit(s, reinterpret_cast<const void *>(&k_corr_all<B, PN, Real>), dim3((PN - B + 1) * nblk), dim3(BLOCK),
-                kargs);
+    void *kargs[] = {&a, &dt, &lcap};
+    return emit(s, reinterpret_cast<const void *>(&k_corr_all<B, PN, Real>), dim3((PN - B + 1) * list_grid(nblk, PN)),
+                dim3(TEAM * TEAM_ROLES), kargs);
 }
 
 template <typename Real>
@@ -2133,7 +2421,7 @@ template <int PN, typename Real>
 hipError_t epi_all_r(int mode, int KB, const void *args, int lo, int nblk, int lcap, Sink &s)
 {
     StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
-    void *kargs[] = {&a, &KB, &lo, &nblk, &lcap};
+    void *kargs[] = {&a, &KB, &lo, &lcap};
     const dim3 g((PN - lo + 1) * nblk), b(BLOCK);
     return emit(s,
                 mode == MODE_STAGE1 ? reinterpret_cast<const void *>(&k_epi_all<PN, Real, MODE_STAGE1>)
