@@ -396,7 +396,9 @@ hipError_t enqueue_adapt(Lanes &L, double tn)
     a.Ualt = static_cast<Real *>(c->d_U[1]);
     a.inlist = c->d_inlist;
     a.listw = c->d_list;
-    return launch_apply_order(c->cfg.p_max, c->fp32, &a, c->d_pnew, c->d_p, c->cfg.p_base, (int)c->ne, L.a);
+    // a step graph advances its clock here, after the indicator read the step's start time
+    return launch_apply_order(c->cfg.p_max, c->fp32, &a, c->d_pnew, c->d_p, c->cfg.p_base, (int)c->ne,
+                              L.graph ? c->d_inst : nullptr, c->d_flag, L.a);
 }
 
 // Order-separated stage: base kernel over all elements (branch A) while the
@@ -584,7 +586,8 @@ hipError_t enqueue_step(Lanes &L, double tn, double dt)
 }
 
 // The step graph: the device clock (stage times, open-sea elevation, depth
-// check stop), then one step as above.  Rebuilt when what it launches changes.
+// check stop; an adaptive step's order update advances it), then one step as
+// above.  Rebuilt when what it launches changes.
 std::vector<long long> step_graph_key(const swe_ctx *c)
 {
     return {(long long)(intptr_t)c->d_C[0], (long long)(intptr_t)c->d_src, c->uniform ? 1 : 0,
@@ -602,7 +605,8 @@ hipError_t build_graph(swe_ctx *c, int nsteps, hipGraph_t *g_out, hipGraphExec_t
     if (e != hipSuccess) return e;
     Lanes L(c, g);
     for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
-        e = launch_batch_clock(c->d_inst, c->d_flag, 1, L.a);
+        // an adaptive step's order update advances the clock itself
+        if (!c->cfg.adapt) e = launch_batch_clock(c->d_inst, c->d_flag, 1, L.a);
         if (e == hipSuccess) e = c->fp32 ? enqueue_step<float>(L, 0.0, 0.0) : enqueue_step<double>(L, 0.0, 0.0);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(x_out, g, nullptr, nullptr, 0);

@@ -167,8 +167,10 @@ int host_corr(int b, int pn, bool fp32, const void *args, double dt, const signe
 hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s);
 hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, int p_hi, double *I_out,
                             signed char *p_new, Sink &k);
+// clock (or null): the instance whose step clock advances in the same launch
+// (a step graph's order update; see k_batch_clock), flag its failure flag
 hipError_t launch_apply_order(int pm, bool fp32, const void *args, const signed char *p_new, signed char *p_cur,
-                              int p_base, int lcap, Sink &k);
+                              int p_base, int lcap, InstDesc *clock, const int *flag, Sink &k);
 hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, int p_hi, double *I_out,
                             signed char *p_new, hipStream_t s);
 hipError_t launch_mass(const MeshView &m, bool fp32, const void *C, double *partial,

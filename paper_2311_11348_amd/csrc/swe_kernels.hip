@@ -1439,25 +1439,35 @@ __global__ void __launch_bounds__(BLOCK) k_relocate(const int *ev, const int *nb
 
 // Per-step clock of every resident instance: open-sea elevation at the two
 // stage times, then advance its time and step budget.
+// Open-sea elevation of an instance at time t (its forcing constituents).
+__device__ __forceinline__ double clock_xihat(const InstDesc &I, double t)
+{
+    double x = 0.0;
+    for (int c = 0; c < I.ncon; ++c) x += I.amp[c] * sin(I.omega[c] * t + I.phase[c]);
+    return x;
+}
+
+// The device clock of an instance for the step about to run: a failed
+// instance (non-positive depth or a non-finite value) or one whose step
+// budget is spent stops; otherwise the open-sea elevation at the step's two
+// stage times is set and the time advanced.
+__device__ __forceinline__ void clock_advance(InstDesc &I, int flag)
+{
+    const int run = I.active && I.steps_left > 0 && flag == 0;
+    I.run = run;
+    if (!run) return;
+    I.xh[0] = clock_xihat(I, I.t);
+    I.xh[1] = clock_xihat(I, I.t + I.dt);
+    I.t = I.t0 + (double)(I.steps_done + 1) * I.dt;
+    I.steps_done += 1;
+    I.steps_left -= 1;
+}
+
 __global__ void __launch_bounds__(BLOCK) k_batch_clock(InstDesc *inst, const int *flags, int n)
 {
     const int i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
-    InstDesc &I = inst[i];
-    // a failed instance (non-positive depth or a non-finite value) stops where it failed
-    const int run = I.active && I.steps_left > 0 && flags[i] == 0;
-    I.run = run;
-    if (!run) return;
-    double x1 = 0.0, x2 = 0.0;
-    for (int c = 0; c < I.ncon; ++c) {
-        x1 += I.amp[c] * sin(I.omega[c] * I.t + I.phase[c]);
-        x2 += I.amp[c] * sin(I.omega[c] * (I.t + I.dt) + I.phase[c]);
-    }
-    I.xh[0] = x1;
-    I.xh[1] = x2;
-    I.t = I.t0 + (double)(I.steps_done + 1) * I.dt;
-    I.steps_done += 1;
-    I.steps_left -= 1;
+    clock_advance(inst[i], flags[i]);
 }
 
 // ------------------------------------------------------------ listed elements, every order in one launch
@@ -1985,7 +1995,10 @@ __global__ void __launch_bounds__(BLOCK) k_indicator(StageArgs<Real> a, double t
     const unsigned e = blockIdx.x * BLOCK + threadIdx.x;
     if (e >= (unsigned)m.ne) return;
     const Buf<Real> bC(a.Cin, 3 * m.KS, m.stride);
-    indicator_element<Real>(m, bC, e, a.inst ? a.inst->xh[0] : a.xihat, tau, p_lo, p_hi, I_out, p_new);
+    // in a step graph the clock advances in the order update after this
+    // kernel, so the step's start time is still the clock's time
+    indicator_element<Real>(m, bC, e, a.inst ? clock_xihat(*a.inst, a.inst->t) : a.xihat, tau, p_lo, p_hi, I_out,
+                            p_new);
 }
 
 // Apply the new order of element e: drop modes above K(p_new) from every state
@@ -2050,9 +2063,12 @@ __device__ __forceinline__ int apply_element(const StageArgs<Real> &a, unsigned 
 // wave and order).
 template <int PM, typename Real>
 __global__ void __launch_bounds__(BLOCK) k_apply_order(StageArgs<Real> a, const signed char *p_new,
-                                                       signed char *p_cur, int p_base, int lcap)
+                                                       signed char *p_cur, int p_base, int lcap, InstDesc *clock,
+                                                       const int *flag)
 {
     const unsigned e = blockIdx.x * BLOCK + threadIdx.x;
+    // a step graph's clock (no other thread of this kernel reads the instance)
+    if (clock && e == 0) clock_advance(*clock, flag[0]);
     const bool live = e < (unsigned)a.m.ne;
     int pn = 0;
     bool listed = false;
@@ -2595,10 +2611,10 @@ hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, i
 
 template <typename Real>
 hipError_t apply_r(int pm, const void *args, const signed char *p_new, signed char *p_cur, int p_base, int lcap,
-                   Sink &s)
+                   InstDesc *clock, const int *flag, Sink &s)
 {
     StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
-    void *kargs[] = {&a, &p_new, &p_cur, &p_base, &lcap};
+    void *kargs[] = {&a, &p_new, &p_cur, &p_base, &lcap, &clock, &flag};
     const dim3 g((a.m.ne + BLOCK - 1) / BLOCK), b(BLOCK);
     switch (pm) {
     case 0: return emit(s, reinterpret_cast<const void *>(&k_apply_order<0, Real>), g, b, kargs);
@@ -2610,10 +2626,10 @@ hipError_t apply_r(int pm, const void *args, const signed char *p_new, signed ch
 }
 
 hipError_t launch_apply_order(int pm, bool fp32, const void *args, const signed char *p_new, signed char *p_cur,
-                              int p_base, int lcap, Sink &k)
+                              int p_base, int lcap, InstDesc *clock, const int *flag, Sink &k)
 {
-    return fp32 ? apply_r<float>(pm, args, p_new, p_cur, p_base, lcap, k)
-                : apply_r<double>(pm, args, p_new, p_cur, p_base, lcap, k);
+    return fp32 ? apply_r<float>(pm, args, p_new, p_cur, p_base, lcap, clock, flag, k)
+                : apply_r<double>(pm, args, p_new, p_cur, p_base, lcap, clock, flag, k);
 }
 
 __global__ void k_inst_set(InstDesc *inst, InstDesc v)
