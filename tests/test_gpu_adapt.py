@@ -25,6 +25,20 @@ def c3_small(n=24):
     return prob
 
 
+def oracle_adaptive(orc, c, steps, dt, tau, t0=0.0):
+    """The oracle's adaptive run, one step at a time; before each step the
+    indicator of the state the step decides on must not lie within rounding
+    of either threshold (tau, tau / 10), so that the GPU, computing it in
+    another order, must reach the same orders."""
+    for s in range(steps):
+        t = t0 + s * dt
+        ind = orc.indicator(t, c)
+        for thr in (tau, tau / 10):
+            assert np.min(np.abs(ind - thr)) / thr > 1e-9, (s, thr)
+        c = orc.step(c, 1, dt, t0=t, adapt=True, tau=tau, p_lo=1, p_hi=3)
+    return c
+
+
 def test_indicator_parity_fp64():
     prob = c3_small()
     orc = Oracle.from_problem(prob)
@@ -45,12 +59,8 @@ def test_adaptive_run_fp64(separate):
     c0 = orc.project(prob.ic)
     dt = prob.dt()
     steps = 30
-    ref = orc.step(c0, steps, dt, adapt=True, tau=prob.adapt_tau, p_lo=1, p_hi=3)
+    ref = oracle_adaptive(orc, c0, steps, dt, prob.adapt_tau)
     pref = orc.order()
-    # the thresholds must not be within rounding of any indicator value
-    I_last = orc.indicator(0.0, ref)
-    for thr in (prob.adapt_tau, prob.adapt_tau / 10):
-        assert np.min(np.abs(I_last - thr)) / thr > 1e-9
     with swe.context_for(prob, separate=separate) as ctx:
         ctx.set_state(c0)
         ctx.step(steps, dt)
@@ -99,9 +109,9 @@ def test_set_state_after_adaptive_steps(separate):
     c0 = orc.project(prob.ic)
     dt = prob.dt()
     n1, n2 = 12, 10
-    mid = orc.step(c0, n1, dt, adapt=True, tau=prob.adapt_tau, p_lo=1, p_hi=3)
+    mid = oracle_adaptive(orc, c0, n1, dt, prob.adapt_tau)
     pmid = orc.order()
-    ref = orc.step(mid, n2, dt, t0=n1 * dt, adapt=True, tau=prob.adapt_tau, p_lo=1, p_hi=3)
+    ref = oracle_adaptive(orc, mid, n2, dt, prob.adapt_tau, t0=n1 * dt)
     pref = orc.order()
     dirty = mid.copy()
     above = np.arange(10)[None, :] >= np.asarray(I.K_OF_P)[pmid][:, None]
