@@ -63,6 +63,8 @@ def lib():
         L.orc_basis.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp, dp]
         L.orc_basis_coeffs.argtypes = [dp]
         L.orc_neighbours.argtypes = [vp, ip, ip]
+        L.orc_depth_limit.argtypes = [vp, dp, C.c_double]
+        L.orc_set_depth_limit.argtypes = [vp, C.c_double]
         _lib = L
     return _lib
 
@@ -112,9 +114,12 @@ class Oracle:
 
     @classmethod
     def from_problem(cls, prob):
-        return cls(prob.mesh.vxy, prob.hb_vertex, prob.mesh.tri, prob.mesh.tag, prob.p_max,
-                   g=prob.g, f_coriolis=prob.f_coriolis, friction=prob.friction,
-                   friction_coef=prob.friction_coef, forcing=prob.forcing, order=prob.p)
+        o = cls(prob.mesh.vxy, prob.hb_vertex, prob.mesh.tri, prob.mesh.tag, prob.p_max,
+                g=prob.g, f_coriolis=prob.f_coriolis, friction=prob.friction,
+                friction_coef=prob.friction_coef, forcing=prob.forcing, order=prob.p)
+        if getattr(prob, "h_min", 0.0) > 0.0:
+            o.set_depth_limit(prob.h_min)
+        return o
 
     def __del__(self):
         try:
@@ -177,6 +182,17 @@ class Oracle:
 
     def mass(self, c):
         return float(self.L.orc_mass(self.h, _d(self._c(c))))
+
+    def set_depth_limit(self, h_min):
+        """Minimum depth control after every stage of ``step`` (0: off)."""
+        if self.L.orc_set_depth_limit(self.h, float(h_min)) != 0:
+            raise ValueError("h_min must be finite and >= 0")
+
+    def depth_limit(self, c, h_min):
+        """The minimum depth control applied once: (new state, elements changed)."""
+        c = self._c(c).copy()
+        n = self.L.orc_depth_limit(self.h, _d(c), float(h_min))
+        return c, int(n)
 
     def indicator(self, t, c):
         I = np.zeros(self.ne)

@@ -19,7 +19,10 @@
  *     depth expansion K(p,i,j) of Sec. "order separation", solved by LU with
  *     partial pivoting;
  *   - two-stage SSP Runge-Kutta in Shu-Osher form (Sec. "Quadrature-free DG
- *     formulation", time discretisation).
+ *     formulation", time discretisation);
+ *   - optionally, a minimum depth control after every stage (the paper lists
+ *     such a kernel among those of its code, Sec. "Performance results",
+ *     without defining it; the reading is stated at depth_limit_elem).
  * The method integrates products of polynomials exactly with precomputed
  * basis-product integrals.  The oracle instead evaluates every integral by
  * Gaussian quadrature that is exact for the polynomial degree of its
@@ -219,6 +222,7 @@ typedef struct {
     double amp[NCON_MAX], omega[NCON_MAX], phase[NCON_MAX];
     double *src;    /* optional [ne][3][K] */
     int exact_H;    /* diagnostics: use the untruncated depth in u H = q */
+    double h_min;   /* minimum depth control after every stage (0: off) */
     /* scratch */
     double *u;      /* [ne][2][K] */
     tri_rule el_rule;
@@ -660,6 +664,73 @@ static int depth_ok(const orc *o, const double *c)
 }
 
 /* ------------------------------------------------------------------ */
+/* Minimum depth control.  Reading of the paper's "minimum depth control */
+/* to avoid negative depths" (a kernel of its code, Sec. "Performance    */
+/* results"; not defined there): after every RK stage, an element whose  */
+/* total depth H = xi + h_b is below h_min at one of its check points    */
+/* (its three vertices and its three edge midpoints) has the deviation   */
+/* of H from its element mean scaled by                                  */
+/*   theta = (mean H - h_min) / (mean H - min_j H(x_j)),                 */
+/* or 0 when mean H <= h_min, which brings H up to h_min at the check    */
+/* points and keeps the mean (the mass); the momentum's deviation from   */
+/* its mean is scaled by the same theta.  h_b cannot change, so xi takes */
+/* the scaled deviation of H minus that of h_b:                          */
+/*   xi' = mean xi + theta (xi - mean xi) + (theta - 1)(h_b - mean h_b). */
+/* An element of order 0 has no mode to scale and is left alone.         */
+/* ------------------------------------------------------------------ */
+static int depth_limit_elem(const orc *o, int e, double *ce, double h_min)
+{
+    const int K = o->K, Ke = K_OF_P[o->p[e]];
+    if (Ke < 3) return 0;
+    const int *t = o->tri + 3 * e;
+    const double sd = sqrt(o->det[e]), area = 0.5 * o->det[e];
+    const double hbm = (o->hb[t[0]] + o->hb[t[1]] + o->hb[t[2]]) / 3.0;
+    const double Hm = ce[0] / sqrt(area) + hbm;
+    static const double px[6] = {0.0, 1.0, 0.0, 0.5, 0.0, 0.5};
+    static const double py[6] = {0.0, 0.0, 1.0, 0.5, 0.5, 0.0};
+    double Hlow = INFINITY, phi[KMAX];
+    for (int j = 0; j < 6; ++j) {
+        basis_eval(Ke, px[j], py[j], phi, NULL, NULL);
+        double xi = 0.0;
+        for (int n = 0; n < Ke; ++n) xi += ce[n] * phi[n];
+        const double H = xi / sd + hb_at(o, e, px[j], py[j]);
+        if (H < Hlow) Hlow = H;
+    }
+    if (!(Hlow < h_min)) return 0;
+    const double theta = Hm > h_min ? (Hm - h_min) / (Hm - Hlow) : 0.0;
+    /* modes of h_b - mean h_b: its L2 projection (h_b is linear, so exact) */
+    double bq[3] = {0.0, 0.0, 0.0};
+    const tri_rule *R = &o->el_rule;
+    for (int q = 0; q < R->n; ++q) {
+        basis_eval(3, R->x[q], R->y[q], phi, NULL, NULL);
+        const double f = (hb_at(o, e, R->x[q], R->y[q]) - hbm) * R->w[q] * o->det[e] / sd;
+        for (int n = 0; n < 3; ++n) bq[n] += f * phi[n];
+    }
+    for (int n = 1; n < Ke; ++n) {
+        ce[n] = theta * ce[n] + (n < 3 ? (theta - 1.0) * bq[n] : 0.0);
+        ce[K + n] *= theta;
+        ce[2 * K + n] *= theta;
+    }
+    return 1;
+}
+
+/* the control on every element; returns how many were changed */
+int orc_depth_limit(void *h, double *c, double h_min)
+{
+    orc *o = (orc *)h;
+    int n = 0;
+    for (int e = 0; e < o->ne; ++e) n += depth_limit_elem(o, e, c + (size_t)e * 3 * o->K, h_min);
+    return n;
+}
+
+int orc_set_depth_limit(void *h, double h_min)
+{
+    if (!(h_min >= 0.0) || !isfinite(h_min)) return -1;
+    ((orc *)h)->h_min = h_min;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* p-adaptivity stand-in: jumps of the P1 part of xi at edge midpoints */
 /* ------------------------------------------------------------------ */
 static double xi_p1_at(const orc *o, int e, const double *c, double x, double y)
@@ -734,9 +805,11 @@ int orc_step(void *h, int nsteps, double dt, double t0, double *c, int adapt, do
         if (adapt) orc_adapt(h, t, c, tau, p_lo, p_hi);
         if ((rc = orc_rhs(h, t, c, L))) break;
         for (size_t i = 0; i < n; ++i) c1[i] = c[i] + dt * L[i];
+        if (o->h_min > 0.0) orc_depth_limit(h, c1, o->h_min);
         if (!depth_ok(o, c1)) { rc = -4; break; }
         if ((rc = orc_rhs(h, t + dt, c1, L))) break;
         for (size_t i = 0; i < n; ++i) c[i] = 0.5 * c[i] + 0.5 * (c1[i] + dt * L[i]);
+        if (o->h_min > 0.0) orc_depth_limit(h, c, o->h_min);
         if (!depth_ok(o, c)) { rc = -4; break; }
         t = t0 + (s + 1) * dt;
     }

@@ -240,6 +240,7 @@ class Problem:
     adapt_tau: float = 1e-3
     bathy: Optional[Callable] = None
     dt_fixed: Optional[float] = None   # a prescribed step instead of the CFL rule
+    h_min: float = 0.0                 # minimum depth control after every stage (0: off)
 
     def dt(self) -> float:
         """Fixed step from the analytic initial state at the vertices and centroids.
