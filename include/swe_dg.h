@@ -93,6 +93,16 @@ typedef struct {
                                enqueued stage by stage and swe_step returns once the host part
                                of its last stage is done.  0 (default): every stage on the GPU */
     int host_threads;       /* host threads of the heterogeneous correction; 0: every usable core */
+    double h_min;           /* minimum depth control (m) after every RK stage of swe_step (the
+                               paper lists such a kernel, Sec. "Performance results", without a
+                               formula; this reading): an element whose total depth is below
+                               h_min at a vertex or an edge midpoint has its depth's deviation
+                               from the element mean scaled by theta = (mean - h_min) /
+                               (mean - lowest), or 0 when the mean is below h_min, keeping the
+                               mean (the mass); its momentum's deviation is scaled alike and its
+                               velocity solved again.  Order-0 elements are left alone.  0
+                               (default): off.  Not available in batches (swe_batch_admit
+                               refuses such a member) */
 } swe_config;
 
 /* Fill *cfg with defaults: FP64, p_base = p_max = 1, g = 9.81, no Coriolis,

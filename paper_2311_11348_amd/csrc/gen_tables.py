@@ -15,6 +15,8 @@ symbolically).  Here they are built in exact rational arithmetic:
 * G[c][a][b] = int_0^1 L_a L_b L_c               (1D products on an edge)
 * W[n][v]    = int_T lambda_v phi_n              (P1 bathymetry -> modes)
 * PMID[k][n] = phi_n(midpoint of edge k)         (P1 part at edge midpoints)
+* PCHK[j][n] = phi_n at the three vertices, then the three edge midpoints
+                                                (points of the minimum-depth control)
 * a 36-point collapsed Gauss rule with phi values, for projecting initial data.
 Local edge k joins reference vertices k+1 and k+2 (vertices (0,0), (1,0),
 (0,1)), parametrised by t from vertex k+1 to vertex k+2; L_a are the
@@ -167,7 +169,9 @@ def build():
     for k in range(3):
         t = restrict_point(k, F(1, 2))
         PMID.append([Exact(peval(psi[n], t), 1 / N[n]).to_double() for n in range(3)])
-    T.update(C=C, D=D, R=R, G=G, W=W, PMID=PMID)
+    pts = [VERT[v] for v in range(3)] + [restrict_point(k, F(1, 2)) for k in range(3)]
+    PCHK = [[Exact(peval(psi[n], pt), 1 / N[n]).to_double() for n in range(KMAX)] for pt in pts]
+    T.update(C=C, D=D, R=R, G=G, W=W, PMID=PMID, PCHK=PCHK)
     # projection rule: collapsed Gauss-Legendre 6x6 (degree 10), double precision is enough
     import numpy as np
     tg, wg = np.polynomial.legendre.leggauss(6)
@@ -230,6 +234,8 @@ def emit(T, path):
         "#define SWET_W " + nested(T["W"]),
         "// PMID[k][n] = phi_n at the midpoint of edge k",
         "#define SWET_PMID " + nested(T["PMID"]),
+        "// PCHK[j][n] = phi_n at reference vertex j (j < 3), at the midpoint of edge j - 3 (j >= 3)",
+        "#define SWET_PCHK " + nested(T["PCHK"]),
         "// 36-point collapsed Gauss rule (degree 10) for projecting point data",
         "#define SWET_NQP 36",
         "#define SWET_QX " + nested(T["QX"]),

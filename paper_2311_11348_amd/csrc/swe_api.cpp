@@ -559,6 +559,19 @@ hipError_t enqueue_partitioned(Lanes &L, int mode, int in, int out, double tstag
     return L.join();
 }
 
+// Minimum depth control over the stage output in buffer out (base branch,
+// after everything the stage joined on it).
+template <typename Real>
+hipError_t enqueue_depth_limit(Lanes &L, int out)
+{
+    swe_ctx *c = L.c;
+    StageArgs<Real> a = make_args<Real>(c);
+    a.Cout = static_cast<Real *>(c->d_C[out]);
+    a.Uout = static_cast<Real *>(c->d_U[out]);
+    if (L.graph) a.inst = c->d_inst;
+    return launch_depth_limit(c->cfg.p_max, c->fp32, &a, c->cfg.h_min, L.a);
+}
+
 // One SSP-RK2 step (order update first when adaptive).
 template <typename Real>
 hipError_t enqueue_step(Lanes &L, double tn, double dt)
@@ -569,18 +582,14 @@ hipError_t enqueue_step(Lanes &L, double tn, double dt)
         e = enqueue_adapt<Real>(L, tn);
         if (e != hipSuccess) return e;
     }
-    if (separated(c) && c->cfg.separate == 2) {
-        e = enqueue_partitioned<Real>(L, MODE_STAGE1, 0, 1, tn, dt);
-        if (e == hipSuccess) e = enqueue_partitioned<Real>(L, MODE_STAGE2, 1, 0, tn + dt, dt);
-    } else if (separated(c) && c->cfg.hetero) {
-        e = enqueue_separated_hetero<Real>(L, MODE_STAGE1, 0, 1, tn, dt);
-        if (e == hipSuccess) e = enqueue_separated_hetero<Real>(L, MODE_STAGE2, 1, 0, tn + dt, dt);
-    } else if (separated(c)) {
-        e = enqueue_separated<Real>(L, MODE_STAGE1, 0, 1, tn, dt);
-        if (e == hipSuccess) e = enqueue_separated<Real>(L, MODE_STAGE2, 1, 0, tn + dt, dt);
-    } else {
-        e = enqueue_stage<Real>(L, MODE_STAGE1, 0, 1, tn, dt, nullptr, nullptr);
-        if (e == hipSuccess) e = enqueue_stage<Real>(L, MODE_STAGE2, 1, 0, tn + dt, dt, c->d_C[0], nullptr);
+    for (int st = 0; st < 2 && e == hipSuccess; ++st) {
+        const int mode = st == 0 ? MODE_STAGE1 : MODE_STAGE2, in = st, out = 1 - st;
+        const double ts = tn + st * dt;
+        if (separated(c) && c->cfg.separate == 2) e = enqueue_partitioned<Real>(L, mode, in, out, ts, dt);
+        else if (separated(c) && c->cfg.hetero) e = enqueue_separated_hetero<Real>(L, mode, in, out, ts, dt);
+        else if (separated(c)) e = enqueue_separated<Real>(L, mode, in, out, ts, dt);
+        else e = enqueue_stage<Real>(L, mode, in, out, ts, dt, st ? c->d_C[0] : nullptr, nullptr);
+        if (e == hipSuccess && c->cfg.h_min > 0.0) e = enqueue_depth_limit<Real>(L, out);
     }
     return e;
 }
@@ -1023,6 +1032,7 @@ swe_status swe_create(const swe_config *cfg, swe_ctx **out)
     // heterogeneous stages: the order-separated scheme on a static order map
     if (cfg->hetero < 0 || cfg->hetero > 1 || cfg->host_threads < 0) return SWE_EINVAL;
     if (cfg->hetero && (cfg->separate != 1 || cfg->adapt || cfg->p_base >= cfg->p_max)) return SWE_EINVAL;
+    if (!(cfg->h_min >= 0.0) || !std::isfinite(cfg->h_min)) return SWE_EINVAL;
     // FP32 order-partitioned stepping with orders up to 3 (its full-order
     // kernels k_full<p, 3, float>) is switched off: one run of it aborted on
     // the device and no cause has been found in the source.  The
@@ -2165,6 +2175,7 @@ swe_status swe_batch_admit(swe_batch *b, swe_ctx *c, int64_t nsteps, double dt, 
     if (c->cfg.separate || c->d_src || c->failed)
         return bfail(b, SWE_EINVAL, "batch members run the fused scheme (separate = 0) and take no extra source");
     if (c->ncon > 4) return bfail(b, SWE_EINVAL, "batch members support at most 4 forcing constituents");
+    if (c->cfg.h_min > 0.0) return bfail(b, SWE_EINVAL, "batch members take no minimum depth control (h_min = 0)");
     int i = 0;
     while (i < b->cap && b->mem[i].ctx) ++i;
     if (i == b->cap) return bfail(b, SWE_ENOMEM, "no free slot");

@@ -165,6 +165,9 @@ hipError_t launch_epi_all(int b, int pn, bool fp32, int mode, const void *args, 
 int host_corr(int b, int pn, bool fp32, const void *args, double dt, const signed char *order, int e0, int e1,
               int nthreads);
 hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s);
+// minimum depth control over every element of the stage output (args.Cout,
+// args.Uout; per-element orders from args.m.ep, at most pm)
+hipError_t launch_depth_limit(int pm, bool fp32, const void *args, double h_min, Sink &k);
 hipError_t launch_indicator(bool fp32, const void *args, double tau, int p_lo, int p_hi, double *I_out,
                             signed char *p_new, Sink &k);
 // clock (or null): the instance whose step clock advances in the same launch

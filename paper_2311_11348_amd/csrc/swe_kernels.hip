@@ -39,6 +39,7 @@ constexpr double TR[3][10][4] = SWET_R;
 constexpr double TG[4][4][4] = SWET_G;
 constexpr double TW[3][3] = SWET_W;
 constexpr double TPMID[3][3] = SWET_PMID;
+constexpr double TCHK[6][10] = SWET_PCHK;
 constexpr int TDEG[10] = SWET_DEG;
 constexpr int KOFP[4] = SWET_K_OF_P;
 constexpr double SQRT2 = 1.41421356237309504880;
@@ -2151,6 +2152,80 @@ __global__ void __launch_bounds__(BLOCK) k_batch_apply(BatchArgs b)
     (void)apply_element<PM, Real>(a, e, b.pool.pnew, b.pool.ep, I.p_lo, &listed);
 }
 
+// ------------------------------------------------------------ minimum depth control
+// After a stage (the paper's minimum depth control, a kernel of its code that
+// it does not define; this is the reading): an element whose total depth
+// H = xi + h_b is below h_min at one of its vertices or edge midpoints has the
+// deviation of H from its element mean scaled by
+//   theta = (mean H - h_min) / (mean H - min H)   (0 when mean H <= h_min),
+// keeping the mean (the mass), and the momentum's deviation from its mean is
+// scaled by the same theta.  h_b is fixed, so xi takes the scaled deviation
+// of H minus that of h_b (its modes 1 and 2).  The element's velocity is then
+// solved again.  Order-0 elements have no mode to scale.
+template <int PM, typename Real>
+__global__ void __launch_bounds__(BLOCK) k_depth_limit(StageArgs<Real> a, double h_min)
+{
+    constexpr int K = Ord<PM>::K;
+    const MeshView &m = a.m;
+    const unsigned e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= (unsigned)m.ne) return;
+    if (a.inst && !a.inst->run) return;   // the step's clock stopped (failure)
+    const int p = m.ep ? (int)m.ep[e] : PM;
+    if (p < 1) return;
+    const int Ke = KOFP[p];
+    const int KS = m.KS, stride = m.stride;
+    const unsigned off = e * (unsigned)sizeof(Real);
+    const Buf<Real> bC(a.Cout, 3 * KS, stride);
+    Geo G;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) G.h[v] = m.vtx[(unsigned)Buf<int>(m.ev, 3, stride).ld(v, e * 4u)].z;
+    Real xi[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) xi[q] = q < Ke ? bC.ld(q, off) : Real(0);
+    const double hbm = (G.h[0] + G.h[1] + G.h[2]) * (1.0 / 3.0);
+    const double Hm = SQRT2 * double(xi[0]) + hbm;
+    // check points: vertex j < 3, the midpoint of edge j - 3 (it joins
+    // vertices j - 2 and j - 1, modulo 3) for j >= 3
+    double Hlow = HUGE_VAL;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        double x = 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) x = fma(TCHK[j][q], double(xi[q]), x);
+        const double hb = j < 3 ? G.h[j] : 0.5 * (G.h[(j - 2) % 3] + G.h[(j - 1) % 3]);
+        Hlow = fmin(Hlow, x + hb);
+    }
+    if (!(Hlow < h_min)) return;
+    const double theta = Hm > h_min ? (Hm - h_min) / (Hm - Hlow) : 0.0;
+    double hbh[3];
+    hb_modes(G, hbh);
+    const Buf<Real> bU(a.Uout, 2 * KS, stride);
+    Real U[K], V[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        U[q] = q < Ke ? bC.ld(KS + q, off) : Real(0);
+        V[q] = q < Ke ? bC.ld(2 * KS + q, off) : Real(0);
+    }
+#pragma unroll
+    for (int q = 1; q < K; ++q) {
+        if (q >= Ke) continue;
+        xi[q] = Real(q < 3 ? theta * double(xi[q]) + (theta - 1.0) * hbh[q] : theta * double(xi[q]));
+        U[q] = Real(theta * double(U[q]));
+        V[q] = Real(theta * double(V[q]));
+        bC.st(q, off, xi[q]);
+        bC.st(KS + q, off, U[q]);
+        bC.st(2 * KS + q, off, V[q]);
+    }
+    Real u[K], v[K];
+    solve_u<PM, Real>(xi, U, V, hbh, Ke, u, v);
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        if (q >= Ke) continue;
+        bU.st(q, off, u[q]);
+        bU.st(KS + q, off, v[q]);
+    }
+}
+
 template <int P, typename Real>
 __global__ void __launch_bounds__(BLOCK) k_usolve(StageArgs<Real> a)
 {
@@ -2462,6 +2537,26 @@ hipError_t launch_epi_all(int b, int pn, bool fp32, int mode, const void *args, 
 hipError_t launch_usolve(int p, bool fp32, const void *args, hipStream_t s)
 {
     return fp32 ? usolve_r<float>(p, args, s) : usolve_r<double>(p, args, s);
+}
+
+template <typename Real>
+hipError_t depth_limit_r(int pm, const void *args, double h_min, Sink &s)
+{
+    StageArgs<Real> a = *static_cast<const StageArgs<Real> *>(args);
+    void *kargs[] = {&a, &h_min};
+    const dim3 g((a.m.ne + BLOCK - 1) / BLOCK), b(BLOCK);
+    switch (pm) {
+    case 1: return emit(s, reinterpret_cast<const void *>(&k_depth_limit<1, Real>), g, b, kargs);
+    case 2: return emit(s, reinterpret_cast<const void *>(&k_depth_limit<2, Real>), g, b, kargs);
+    case 3: return emit(s, reinterpret_cast<const void *>(&k_depth_limit<3, Real>), g, b, kargs);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_depth_limit(int pm, bool fp32, const void *args, double h_min, Sink &k)
+{
+    if (pm < 1) return hipSuccess;   // order 0 has nothing to scale
+    return fp32 ? depth_limit_r<float>(pm, args, h_min, k) : depth_limit_r<double>(pm, args, h_min, k);
 }
 
 int mass_partials(int ne) { return (ne + BLOCK - 1) / BLOCK; }

@@ -277,6 +277,17 @@ def config_c1(n: int = 32, p: int = 1) -> Problem:
                     p, p, p, steps=100)
 
 
+def config_shallow(n: int = 24, p: int = 2, h_min: float = 0.25, seed: int = 8) -> Problem:
+    """Shallow water for the minimum depth control: bottom 1 m deep at x = 0
+    and 0.5 m at x = L, at rest with a Gaussian depression of the surface
+    (-0.6 m, width 15 km) in the middle, 0.15 m deep at its centre; all land,
+    jittered mesh."""
+    mesh = structured_mesh(n, jitter=0.2, seed=seed)
+    return _problem("shallow", mesh, bathy_shelf(deep=1.0, shallow=0.5),
+                    ic_gaussian(-0.6, 1.5e4, L_DOMAIN / 2, L_DOMAIN / 2), p, min(p, 1), p, steps=20,
+                    h_min=h_min)
+
+
 def config_c2(n: int = 512, p: int = 2, seed: int = 2) -> Problem:
     mesh = structured_mesh(n, jitter=0.2, seed=seed, open_west=True)
     return _problem("c2", mesh, bathy_sincos(), ic_rest(0.0), p, min(p, 1), p,

@@ -34,7 +34,8 @@ class swe_config(C.Structure):
                 ("g", C.c_double), ("f_coriolis", C.c_double), ("friction", C.c_int),
                 ("friction_coef", C.c_double), ("adapt", C.c_int), ("adapt_tau", C.c_double),
                 ("separate", C.c_int), ("stream_base", C.c_void_p), ("stream_corr", C.c_void_p),
-                ("step_graph", C.c_int), ("hetero", C.c_int), ("host_threads", C.c_int)]
+                ("step_graph", C.c_int), ("hetero", C.c_int), ("host_threads", C.c_int),
+                ("h_min", C.c_double)]
 
 
 _lib = None
@@ -126,12 +127,13 @@ class Config:
     step_graph: int = 1          # 1: graph for separated steps, 2: always, 0: never
     hetero: int = 0              # 1: correction on the host's cores beside the GPU base pass
     host_threads: int = 0        # threads of that correction (0: every usable core)
+    h_min: float = 0.0           # minimum depth control after every stage (0: off)
 
     def to_c(self) -> swe_config:
         c = swe_config()
         lib().swe_config_default(C.byref(c))
         for k in ("precision", "p_base", "p_max", "g", "f_coriolis", "friction", "friction_coef",
-                  "adapt", "adapt_tau", "separate", "step_graph", "hetero", "host_threads"):
+                  "adapt", "adapt_tau", "separate", "step_graph", "hetero", "host_threads", "h_min"):
             setattr(c, k, getattr(self, k))
         c.stream_base = self.stream_base
         c.stream_corr = self.stream_corr
@@ -278,13 +280,14 @@ class Context:
 
 
 def context_for(problem, precision=SWE_FP64, separate=0, stream_base=None, stream_corr=None,
-                step_graph=1, hetero=0, host_threads=0) -> Context:
+                step_graph=1, hetero=0, host_threads=0, h_min=None) -> Context:
     """Build a context from an ``inputs.Problem`` (mesh, bathymetry, forcing, orders)."""
     cfg = Config(precision=precision, p_base=problem.p_base, p_max=problem.p_max, g=problem.g,
                  f_coriolis=problem.f_coriolis, friction=problem.friction,
                  friction_coef=problem.friction_coef, adapt=problem.adapt,
                  adapt_tau=problem.adapt_tau, separate=separate, stream_base=stream_base,
-                 stream_corr=stream_corr, step_graph=step_graph, hetero=hetero, host_threads=host_threads)
+                 stream_corr=stream_corr, step_graph=step_graph, hetero=hetero, host_threads=host_threads,
+                 h_min=getattr(problem, "h_min", 0.0) if h_min is None else h_min)
     ctx = Context(cfg)
     ctx.set_mesh(problem.mesh.vxy, problem.mesh.tri, problem.mesh.tag)
     ctx.set_bathymetry(problem.hb_vertex)

@@ -73,3 +73,14 @@ def test_heterogeneous_configuration_checks():
         with pytest.raises(swe.SweError) as ei:
             swe.Context(cfg)
         assert ei.value.status == swe.SWE_EINVAL, kw
+
+
+def test_depth_control_configuration_checks():
+    """The minimum depth control takes a finite h_min >= 0; anything else is
+    refused at creation, before any device call."""
+    import pytest
+    from paper_2311_11348_amd import swe
+    for h_min in (-0.1, float("nan"), float("inf")):
+        with pytest.raises(swe.SweError) as ei:
+            swe.Context(swe.Config(p_max=2, h_min=h_min))
+        assert ei.value.status == swe.SWE_EINVAL, h_min
