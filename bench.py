@@ -1,7 +1,7 @@
 """Throughput of the DG shallow-water hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload default|tidal|tsunami|static32|dambreak|batched|served]
+                    [--workload default|tidal|tsunami|static32|dambreak|batched|served|shallow]
 
 default: the tidal headline below (value, roofline, compute roofline, the
   FP64 path beside it, the oracle on the host), with the tsunami, batched and
@@ -33,6 +33,10 @@ batched: 64 independent instances (seeds 4000+i), log-uniform 16k-500k
   elements, p in {1,2,3}, tidal or hump, random smooth bathymetry, 300 steps
   each; FP32 and FP64 batched against the plain FP64 solver run one instance
   at a time; reports DOF-updates/s and solves/s.
+shallow: the minimum depth control: 512x512x2 jittered mesh (seed 8), bottom
+  1 m -> 0.5 m, a -0.6 m Gaussian depression in the middle (0.15 m deep at
+  its centre), uniform p = 2, FP32 and FP64 steps with the control
+  (h_min = 0.25 m, acting around the depression) and without it.
 served: Poisson arrivals (20 req/s for 120 s, seed 5), 8k-260k elements,
   p in {1,2,3}, 200-2000 steps; continuous batching with admission by
   footprint; reports solves/s with p50/p99 latency, then the capacity of
@@ -604,6 +608,37 @@ def tidal_leg(args, I, swe):
                       "roofline": r64["roofline"], "compute": r64["compute"]})
 
 
+def shallow_leg(n, steps, warmup, I, swe):
+    """Uniform p = 2 steps on the shallow depression with and without the
+    minimum depth control (FP32 and FP64): time per stage and the control's
+    share of it."""
+    import torch
+    prob = I.config_shallow(n=n, p=2)
+    print(f"bench: shallow {prob.mesh.ne} elements", file=sys.stderr, flush=True)
+    dof = 3 * K_OF_P[2] * prob.mesh.ne
+    out = {}
+    for prec, name in ((swe.SWE_FP32_WB, "fp32"), (swe.SWE_FP64, "fp64")):
+        row = {}
+        for h_min in (prob.h_min, 0.0):
+            stream = torch.cuda.Stream()
+            ctx = swe.context_for(prob, precision=prec, stream_base=stream.cuda_stream, h_min=h_min)
+            ctx.set_state_fn(prob.ic)
+            dt = prob.dt()
+            ctx.step(warmup, dt)
+            ctx.sync()
+            torch.cuda.synchronize()
+            ms = timed_steps(ctx, stream, steps, dt)
+            ctx.close()
+            row["control" if h_min > 0 else "no_control"] = {"us_per_stage": ms * 1e3 / (2 * steps),
+                                                             "value": dof * 2 * steps / (ms * 1e-3)}
+        row["control_share"] = 1.0 - row["no_control"]["us_per_stage"] / row["control"]["us_per_stage"]
+        out[name] = row
+    return {"value": out["fp32"]["control"]["value"], "ms_per_step": 2 * out["fp32"]["control"]["us_per_stage"] / 1e3,
+            "dtype": "f32 (f64 bathymetry terms)", "h_min": prob.h_min, **out,
+            "config": f"shallow: {n}x{n}x2 jittered, bottom 1 -> 0.5 m, -0.6 m depression, p=2, "
+                      f"minimum depth control h_min = {prob.h_min} m"}
+
+
 def tsunami_leg(n, steps, warmup, I, swe):
     """The p-adaptive workload: order-partitioned FP64 and order-separated FP32."""
     prob = I.config_c3(n=n)
@@ -654,7 +689,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", choices=["default", "tidal", "tsunami", "static32", "dambreak", "batched",
-                                           "served"], default="default",
+                                           "served", "shallow"], default="default",
                     help="default: the tidal headline with the tsunami, batched and (shortened) served "
                          "workloads as extra keys; tidal: the headline alone")
     ap.add_argument("--instances", type=int, default=64)
@@ -708,6 +743,11 @@ def main() -> int:
             out["batched"] = guarded("batched", lambda: run_batched(args.instances, max(args.steps, 20), 2))
             out["served"] = guarded("served", lambda: served_leg(args.served_duration, args.rate,
                                                                  args.capacity_requests, args.tick_steps, swe))
+    elif args.workload == "shallow":
+        n = args.n or 512
+        r = shallow_leg(n, args.steps, args.warmup, I, swe)
+        out.update(value=r.pop("value"), ms_per_step=r.pop("ms_per_step"), dtype=r.pop("dtype"),
+                   config={"workload": r.pop("config"), "elements": 2 * n * n}, **r)
     elif args.workload == "tsunami":
         n = args.n or 256
         r = tsunami_leg(n, args.steps, args.warmup, I, swe)
