@@ -151,6 +151,7 @@ def host_description() -> dict:
 KERNEL_SOURCES = ("paper_2311_11348_amd/csrc/swe_kernels.hip", "paper_2311_11348_amd/csrc/swe_internal.h",
                   "paper_2311_11348_amd/csrc/swe_tables.h", "paper_2311_11348_amd/build.py")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_p2_tidal512_traffic.txt")
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched64_traffic.txt")
 
 
 def kernel_source_hash() -> str:
@@ -163,21 +164,25 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernels):
-    """HBM bytes per launch of the given kernels from the committed PMC summary
-    (FETCH_SIZE and WRITE_SIZE runs, each scaled by what the same counter reads
-    for a copy kernel of known size), averaged over the kernels; None when the
-    summary is missing or the kernel sources changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _traffic_counts(path):
+    """key = value lines of a committed PMC summary, or None when it is
+    missing or was taken on other kernel sources."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if "=" in line and not line.lstrip().startswith("#"):
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("source_hash") != kernel_source_hash():
         return None
+    return kv
+
+
+def _scaled_bytes(kv, kernels):
+    """HBM bytes per dispatch of each kernel (FETCH_SIZE and WRITE_SIZE, each
+    scaled by what the same counter reads for a copy of known size)."""
     fs = float(kv["copy_bytes"]) / (float(kv["copy_fetch_kib"]) * 1024.0)
     ws = float(kv["copy_bytes"]) / (float(kv["copy_write_kib"]) * 1024.0)
     vals = []
@@ -186,7 +191,26 @@ def measured_traffic(kernels):
         if f is None or w is None:
             return None
         vals.append(float(f) * 1024.0 * fs + float(w) * 1024.0 * ws)
-    return sum(vals) / len(vals)
+    return vals
+
+
+def measured_traffic(kernels):
+    """HBM bytes per launch of the given kernels from the committed PMC summary
+    (FETCH_SIZE and WRITE_SIZE runs, each scaled by what the same counter reads
+    for a copy kernel of known size), averaged over the kernels; None when the
+    summary is missing or the kernel sources changed since it was taken."""
+    kv = _traffic_counts(TRAFFIC_FILE)
+    vals = _scaled_bytes(kv, kernels) if kv else None
+    return sum(vals) / len(vals) if vals else None
+
+
+def measured_batch_traffic(kernels):
+    """HBM bytes of one batch step: the sum over the step's stage launches
+    (the given kernels, one launch each per step), from the batched PMC
+    summary; None when missing, stale, or a kernel is not in it."""
+    kv = _traffic_counts(BATCH_TRAFFIC_FILE)
+    vals = _scaled_bytes(kv, kernels) if kv else None
+    return sum(vals) if vals else None
 
 
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 3) -> None:
@@ -534,12 +558,18 @@ def run_batched(count, steps, warmup):
                 "ms_per_step": ms / steps, "hbm_gbs": word_bytes[word] / (ms * 1e-3) / 1e9}
     kinds = {p: ("shared edge fluxes, 256-element tiles" if t[2] else f"element gather, {t[0]}-element tiles")
              for p, t in tiles.items() if k[p] > 0}
+    # HBM bytes of one FP32 step: both stage launches of every order class
+    names = [f"k_batch_stage_sh<{p}, float, {m}>" if tiles[p][2] else f"k_batch_stage<{p}, float, {m}, {tiles[p][0]}>"
+             for p in sorted(kinds) for m in (1, 2)]
+    step_bytes = measured_batch_traffic(names)
     kernel = "; ".join(f"p{p}: k_batch_stage{'_sh' if tiles[p][2] else ''}<{p},float> ({kinds[p]})"
                        for p in sorted(kinds))
     return {"value": upd / (ms32 * 1e-3), "ms_per_step": ms32 / steps,
             "solves_per_s": leg(ms32, 4)["solves_per_s"],
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                         "frac": ach / HBM_PEAK_GBS,
+                         "traffic": step_bytes / (ms32 / steps * 1e-3) / 1e9 if step_bytes else None,
+                         "traffic_bytes_per_step": step_bytes,
                          "kernel": kernel + " + k_batch_clock, whole step (one launch per order class and stage)"},
             "fp32_batched": leg(ms32, 4), "fp64_batched": leg(ms64, 8), "plain_fp64": leg(msp, 8),
             "speedup_solves_vs_plain_fp64": msp / ms32,
