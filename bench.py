@@ -410,16 +410,18 @@ DAMBREAK_HETERO_STEPS = 10   # timed steps of the heterogeneous rows (each stage
 DAMBREAK_DYN_STEPS = 400
 
 
-def run_dambreak(steps, warmup, n=1024):
+def run_dambreak(steps, warmup, n=1024, only=None):
     """The radial dam break: uniform orders on the fused stage kernel, the
     statically adaptive 1/32 setups on the order-partitioned and
-    order-separated schemes; FP64 and FP32."""
+    order-separated schemes; FP64 and FP32 (``only``: that setup alone)."""
     import numpy as np
     from paper_2311_11348_amd import inputs as I
     from paper_2311_11348_amd import swe
     out = {}
     setups = [("p0", 0, 0, 0), ("p1", 1, 1, 0), ("p2", 2, 2, 0), ("p0-1 1/32", 0, 1, 32), ("p1-2 1/32", 1, 2, 32)]
     for name, lo, hi, every in setups:
+        if only is not None and name != only:
+            continue
         prob = I.config_dambreak(n=n, p_lo=lo, p_hi=hi, every=every)
         dof = 3 * sum(K_OF_P[q] * c for q, c in enumerate(np.bincount(prob.p, minlength=4)))
         row = {"dof_per_stage": int(dof)}
@@ -446,6 +448,8 @@ def run_dambreak(steps, warmup, n=1024):
     # dynamic orders: this library's indicator (threshold DAMBREAK_TAU), the
     # CFL step, DAMBREAK_DYN_STEPS timed steps from the start of the run
     for name, lo, hi in (("p0-1 dynamic", 0, 1), ("p1-2 dynamic", 1, 2)):
+        if only is not None and name != only:
+            continue
         prob = I.config_dambreak(n=n, p_lo=lo, p_hi=hi, dt_fixed=None, adapt_tau=DAMBREAK_TAU)
         row = {"tau_m": DAMBREAK_TAU, "dt_s": prob.dt(), "timed_steps": DAMBREAK_DYN_STEPS}
         for prec, tag in ((swe.SWE_FP64, "fp64"), (swe.SWE_FP32_WB, "fp32")):
@@ -734,6 +738,8 @@ def main() -> int:
     ap.add_argument("--p", type=int, default=2)
     ap.add_argument("--served-duration", type=float, default=30.0,
                     help="length of the request trace of the default line's served leg (s)")
+    ap.add_argument("--setup", default=None,
+                    help="dambreak workload: run this setup alone (e.g. 'p1-2 1/32', 'p0-1 dynamic')")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="default workload without the extra legs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -789,13 +795,14 @@ def main() -> int:
     elif args.workload == "dambreak":
         steps = args.steps if args.steps != 500 else 100
         n = args.n or 1024
-        rows = run_dambreak(steps, args.warmup, n=n)
-        head = rows["p1-2 1/32"]["fp64_partitioned"]
-        best_ms = min(rows["p1-2 1/32"]["paper_ms_per_stage"].values())
+        rows = run_dambreak(steps, args.warmup, n=n, only=args.setup)
+        key = args.setup or "p1-2 1/32"
+        head = rows[key].get("fp64_partitioned") or rows[key].get("fp64")
+        best_ms = min(rows[key]["paper_ms_per_stage"].values()) if "paper_ms_per_stage" in rows[key] else None
         out.update(steps=steps, value=head["value"], ms_per_step=2 * head["ms_per_stage"], dtype="f64",
-                   vs_baseline=best_ms / head["ms_per_stage"] if n == 1024 else None,
-                   baseline={"what": "the paper's fastest time per stage for static 1/32 p1-2 on 2,097,152 "
-                                     "triangles (AMD-RTX, CPU, separated), on its own hardware", "ms": best_ms},
+                   vs_baseline=best_ms / head["ms_per_stage"] if n == 1024 and key == "p1-2 1/32" else None,
+                   baseline={"what": f"the paper's fastest time per stage for {key} on 2,097,152 triangles, "
+                                     "on its own hardware", "ms": best_ms},
                    config={"workload": f"dambreak: {n}x{n}x2 jittered triangulation of [0,5]^2, "
                                        f"{2 * n * n} elements, g=1, h_b=0.5 m, linear friction, dt=1e-5 s; "
                                        "headline: every 32nd element p=2, base p=1, order-partitioned, FP64",
