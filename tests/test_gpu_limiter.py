@@ -1,6 +1,7 @@
 """Minimum depth control on the GPU (after every RK stage; the reading is
 stated at `swe_config.h_min`): a shallow depression where the control acts
-on tens of elements every stage, in every stepping scheme, against the
+on tens of elements every stage, in every stepping scheme (the
+heterogeneous one included), against the
 oracle with the same control (FP64 within 1e-12 relative L2, FP32 elevation
 within 1e-5).  The control changes the run (it is not a no-op here) and
 batches refuse members that ask for it."""
@@ -35,7 +36,7 @@ def case(name):
     return prob, 2 if name.startswith("partitioned") else 1
 
 
-CASES = [("uniform p2", swe.SWE_FP64), ("uniform p2", swe.SWE_FP32_WB),
+CASES = [("uniform p2", swe.SWE_FP64), ("uniform p2", swe.SWE_FP32_WB), ("heterogeneous p1-2", swe.SWE_FP64),
          ("separated p1-2", swe.SWE_FP64), ("separated p1-2", swe.SWE_FP32_WB),
          ("partitioned p1-3", swe.SWE_FP64), ("partitioned p1-2", swe.SWE_FP32_WB),
          ("adaptive p1-3", swe.SWE_FP64)]
@@ -53,7 +54,8 @@ def test_depth_control_matches_oracle(name, precision):
         ref = orc.step(c0, steps, dt, adapt=True, tau=prob.adapt_tau, p_lo=1, p_hi=3)
     else:
         ref = orc.step(c0, steps, dt)
-    with swe.context_for(prob, precision=precision, separate=separate) as ctx:
+    hetero = dict(hetero=1, host_threads=4) if name.startswith("heterogeneous") else {}
+    with swe.context_for(prob, precision=precision, separate=separate, **hetero) as ctx:
         ctx.set_state(c0)
         ctx.step(7, dt)
         ctx.step(steps - 7, dt)
