@@ -842,6 +842,17 @@ swe_status build_items(swe_ctx *c)
                         items.push_back((unsigned)(ei - e0) | ((unsigned)k << 8) | ((unsigned)lb << 10) |
                                         ((unsigned)kb << 18) | (kd << 20));
                     }
+            // outside neighbours in the order of their index: consecutive
+            // lanes then read nearby elements, which share cache lines
+            // (1 % shorter FP64 stages at p = 2; FP32 unchanged)
+            auto first = items.begin() + ioff[(size_t)bi];
+            auto ext0 = std::find_if(first, items.end(), [](unsigned it) { return (it >> 20) == 1; });
+            auto ext1 = std::find_if(ext0, items.end(), [](unsigned it) { return (it >> 20) != 1; });
+            std::stable_sort(ext0, ext1, [&](unsigned x, unsigned y) {
+                const int nx = c->nb_host[(size_t)((x >> 8) & 3) * S + e0 + (x & 0xff)];
+                const int ny = c->nb_host[(size_t)((y >> 8) & 3) * S + e0 + (y & 0xff)];
+                return nx < ny;
+            });
         }
         ioff[(size_t)nblk] = (int)items.size();
         // the kernel takes at most two items per lane; a block with more
