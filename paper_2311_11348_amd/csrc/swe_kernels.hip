@@ -90,6 +90,31 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 template <typename T>
 SWE_HD T tmax(T a, T b) { return a > b ? a : b; }
 
+// FP32 reciprocal and square root by the hardware's single-instruction
+// approximations (about 1 ulp) instead of the correctly rounded sequences
+// (ten and more instructions each).  Used on FP32 data only, where the
+// argument is a positive, well-scaled quantity: the pivots of the depth
+// matrix H, the squared wave speed of the penalty, the squared velocity of
+// the quadratic friction.  The host build (the heterogeneous stage) rounds
+// correctly.
+SWE_HD float rcp_approx(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+SWE_HD float sqrt_approx(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return std::sqrt(x);
+#endif
+}
+
 // Element-indexed arrays are read and written through buffer resources: a
 // uniform descriptor (base, byte size) in scalar registers, a uniform byte
 // offset per (component, mode) slot and one 32-bit lane offset, so no load
@@ -174,6 +199,7 @@ struct Buf {
 struct Geo {
     double b00, b01, b10, b11;   // inverse Jacobian: d(xh)/dx, d(xh)/dy, d(yh)/dx, d(yh)/dy
     double det;                  // |det B_e| = 2 area
+    double idet;                 // 1 / |det B_e|
     double X[3], Y[3], h[3];     // vertices and depths
 };
 
@@ -191,6 +217,7 @@ SWE_HD void geo_from_ids(const double4 *vtx, const int (&id3)[3], Geo &G)
     const double a10 = G.Y[1] - G.Y[0], a11 = G.Y[2] - G.Y[0];
     G.det = a00 * a11 - a01 * a10;
     const double id = 1.0 / G.det;
+    G.idet = id;
     G.b00 = a11 * id;
     G.b01 = -a01 * id;
     G.b10 = -a10 * id;
@@ -210,6 +237,7 @@ SWE_HD void load_geo(const double4 *vtx, const Buf<int> &ev, unsigned offi, Geo 
     const double a10 = G.Y[1] - G.Y[0], a11 = G.Y[2] - G.Y[0];
     G.det = a00 * a11 - a01 * a10;
     const double id = 1.0 / G.det;
+    G.idet = id;
     G.b00 = a11 * id;
     G.b01 = -a01 * id;
     G.b10 = -a10 * id;
@@ -378,7 +406,10 @@ SWE_HD void source_term(const Fields<P, Real> &s, const Geo &G, const Physics &p
     if (ph.friction == 2) {
         // |constant part of u| = sqrt(2) |(u_0, v_0)| in reference-scaled modes
         const Real um = s.u[0], vm = s.v[0];
-        tau = Real(ph.fric * dt * SQRT2) * sqrt(um * um + vm * vm);
+        if constexpr (std::is_same<Real, double>::value)
+            tau = Real(ph.fric * dt * SQRT2) * sqrt(um * um + vm * vm);
+        else
+            tau = Real(ph.fric * dt * SQRT2) * sqrt_approx(um * um + vm * vm);
     } else if (ph.friction == 1) {
         tau = Real(ph.fric * dt);
     }
@@ -454,7 +485,7 @@ SWE_HD void edge_one(const MeshView &m, unsigned e, const Buf<Real> &bC, const B
     const Real ubm = Real(SQRT2) * s.u[0], vbm = Real(SQRT2) * s.v[0];
     // With the edge vector's normal nu = |E| n (no square root), every flux
     // term carries |E| n or |E| lambda, and |E| / |det B| folds into dt / |det B|.
-    const double dt_det = dt / G.det;
+    const double dt_det = dt * G.idet;
     {
         constexpr int ka = (k + 1) % 3, kb = (k + 2) % 3;
         const double dx = G.X[kb] - G.X[ka], dy = G.Y[kb] - G.Y[ka];
@@ -531,7 +562,11 @@ SWE_HD void edge_one(const MeshView &m, unsigned e, const Buf<Real> &bC, const B
             unbp = fabs(fma(Real(SQRT2) * u0, nx, Real(SQRT2) * v0 * ny));
         } else if (nb == NB_LAND) {
             // mirror: xi+ = xi-, normal parts of q and u change sign
-            const Real m2 = Real(-2.0 / len2);
+            Real m2;
+        if constexpr (std::is_same<Real, double>::value)
+            m2 = -2.0 / len2;
+        else
+            m2 = -2.0f * rcp_approx(float(len2));
 #pragma unroll
             for (int a = 0; a < NX; ++a) {
                 txp[a] = txm[a];
@@ -560,7 +595,7 @@ SWE_HD void edge_one(const MeshView &m, unsigned e, const Buf<Real> &bC, const B
         if constexpr (std::is_same<Real, double>::value)
             lam = tmax(unbm, unbp) + sqrt(g * (tmax(xbm, xbp) + hmid) * len2);
         else
-            lam = tmax(unbm, unbp) + Real(sqrt(g * (double(tmax(xbm, xbp)) + hmid) * len2));
+            lam = tmax(unbm, unbp) + sqrt_approx(float(g * (double(tmax(xbm, xbp)) + hmid) * len2));
         const Real sc = Real(dt_det);
         const Real hg = Real(0.5 * g);
         Real FX[NT], FU[NT], FV[NT];
@@ -666,7 +701,10 @@ SWE_HD void solve_u(const Real (&xi)[Ord<P>::K], const Real (&U)[Ord<P>::K],
 #pragma unroll
         for (int k = 0; k < j; ++k) djj = fma(-M[j][k] * d[k], M[j][k], djj);
         d[j] = djj;
-        id[j] = Real(1) / djj;
+        if constexpr (std::is_same<Real, double>::value)
+            id[j] = 1.0 / djj;
+        else
+            id[j] = rcp_approx(djj);
 #pragma unroll
         for (int i = j + 1; i < K; ++i) {
             Real sij = M[i][j];
@@ -966,7 +1004,11 @@ __device__ __forceinline__ void sh_flux(const ShLds<P, Real> &S, const MeshView 
         unbp = fabs(fma(Real(SQRT2) * u0, nx, Real(SQRT2) * v0 * ny));
     } else if (kind == EK_LAND) {
         // mirror: xi+ = xi-, normal parts of q and u change sign
-        const Real m2 = Real(-2.0 / len2);
+        Real m2;
+        if constexpr (std::is_same<Real, double>::value)
+            m2 = -2.0 / len2;
+        else
+            m2 = -2.0f * rcp_approx(float(len2));
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
             tp[0][c] = tm[0][c];
@@ -995,7 +1037,7 @@ __device__ __forceinline__ void sh_flux(const ShLds<P, Real> &S, const MeshView 
     if constexpr (std::is_same<Real, double>::value)
         lam = tmax(unbm, unbp) + sqrt(g * (tmax(xbm, xbp) + hmid) * len2);
     else
-        lam = tmax(unbm, unbp) + Real(sqrt(g * (double(tmax(xbm, xbp)) + hmid) * len2));
+        lam = tmax(unbm, unbp) + sqrt_approx(float(g * (double(tmax(xbm, xbp)) + hmid) * len2));
     const Real hg = Real(0.5 * g);
     Real (&F)[3][NT] = out.F;
     double (&Wf)[NT] = out.W;
@@ -1129,7 +1171,7 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
     acc_init<P, Real>(A, s, MODE != MODE_RHS);
     volume_term<P, Real>(s, hbh, G, g, dt, A);
     source_term<P, Real>(s, G, a.ph, dt, A);
-    const double dt_det = dt / G.det;
+    const double dt_det = dt * G.idet;
     const Real sc = Real(dt_det);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
