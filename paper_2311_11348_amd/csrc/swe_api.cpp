@@ -812,47 +812,57 @@ swe_status build_items(swe_ctx *c)
         const int S = c->stride;
         // edge items per block of BLOCK elements, grouped by kind: pairs of
         // elements of the block (once, from the lower index), neighbours
-        // outside the block, land edges, open edges
+        // outside the block, land edges, open edges.  Item j goes to lane
+        // j % BLOCK, so each run of 64 items is one wave's: where the block
+        // still fits in 2 BLOCK slots, every kind starts at a multiple of 64
+        // (empty slots before it), and no wave computes two kinds' traces.
         const int64_t nblk = (ne + BLOCK - 1) / BLOCK;
         std::vector<unsigned> items;
         std::vector<int> ioff((size_t)nblk + 1, 0);
         items.reserve((size_t)ne * 2);
+        std::vector<unsigned> group[4];
         for (int64_t bi = 0; bi < nblk; ++bi) {
             ioff[(size_t)bi] = (int)items.size();
             const int64_t e0 = bi * BLOCK, e1 = std::min<int64_t>(e0 + BLOCK, ne);
-            for (unsigned kind = 0; kind < 4; ++kind)
-                for (int64_t ei = e0; ei < e1; ++ei)
-                    for (int k = 0; k < 3; ++k) {
-                        const int n = c->nb_host[(size_t)k * S + ei];
-                        unsigned kd;
-                        int lb = 0, kb = 0;
-                        if (n >= 0 && n / BLOCK == bi) {
-                            if (n < ei) continue;      // the pair is taken from the lower index
-                            kd = 0;
-                            lb = (int)(n - e0);
-                            kb = (c->nbk_host[ei] >> (2 * k)) & 3;
-                        } else if (n >= 0) {
-                            kd = 1;
-                        } else if (n == NB_LAND) {
-                            kd = 2;
-                        } else {
-                            kd = 3;
-                        }
-                        if (kd != kind) continue;
-                        items.push_back((unsigned)(ei - e0) | ((unsigned)k << 8) | ((unsigned)lb << 10) |
-                                        ((unsigned)kb << 18) | (kd << 20));
+            for (auto &gk : group) gk.clear();
+            for (int64_t ei = e0; ei < e1; ++ei)
+                for (int k = 0; k < 3; ++k) {
+                    const int n = c->nb_host[(size_t)k * S + ei];
+                    unsigned kd;
+                    int lb = 0, kb = 0;
+                    if (n >= 0 && n / BLOCK == bi) {
+                        if (n < ei) continue;      // the pair is taken from the lower index
+                        kd = 0;
+                        lb = (int)(n - e0);
+                        kb = (c->nbk_host[ei] >> (2 * k)) & 3;
+                    } else if (n >= 0) {
+                        kd = 1;
+                    } else if (n == NB_LAND) {
+                        kd = 2;
+                    } else {
+                        kd = 3;
                     }
+                    group[kd].push_back((unsigned)(ei - e0) | ((unsigned)k << 8) | ((unsigned)lb << 10) |
+                                        ((unsigned)kb << 18) | (kd << 20));
+                }
             // outside neighbours in the order of their index: consecutive
             // lanes then read nearby elements, which share cache lines
             // (1 % shorter FP64 stages at p = 2; FP32 unchanged)
-            auto first = items.begin() + ioff[(size_t)bi];
-            auto ext0 = std::find_if(first, items.end(), [](unsigned it) { return (it >> 20) == 1; });
-            auto ext1 = std::find_if(ext0, items.end(), [](unsigned it) { return (it >> 20) != 1; });
-            std::stable_sort(ext0, ext1, [&](unsigned x, unsigned y) {
+            std::stable_sort(group[1].begin(), group[1].end(), [&](unsigned x, unsigned y) {
                 const int nx = c->nb_host[(size_t)((x >> 8) & 3) * S + e0 + (x & 0xff)];
                 const int ny = c->nb_host[(size_t)((y >> 8) & 3) * S + e0 + (y & 0xff)];
                 return nx < ny;
             });
+            size_t padded = 0;
+            for (int kd = 0; kd < 4; ++kd)
+                if (!group[kd].empty()) padded = (padded + 63) / 64 * 64 + group[kd].size();
+            const bool align = padded <= (size_t)(2 * BLOCK);
+            const size_t b0 = items.size();
+            for (int kd = 0; kd < 4; ++kd) {
+                if (group[kd].empty()) continue;
+                while (align && (items.size() - b0) % 64 != 0) items.push_back(ITEM_PAD);
+                items.insert(items.end(), group[kd].begin(), group[kd].end());
+            }
         }
         ioff[(size_t)nblk] = (int)items.size();
         // the kernel takes at most two items per lane; a block with more

@@ -15,6 +15,10 @@ constexpr int NCON_MAX = 16;
 constexpr int NB_LAND = -1;
 constexpr int NB_OPEN = -2;
 
+// An empty slot in a block's list of edge items of the shared-flux kernels
+// (it aligns the next kind of item to a wave of 64 lanes).
+constexpr unsigned ITEM_PAD = 0xffffffffu;
+
 enum StageMode { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE2 = 2 };
 
 struct Physics {

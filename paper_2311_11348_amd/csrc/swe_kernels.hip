@@ -596,7 +596,8 @@ SWE_HD void edge_one(const MeshView &m, unsigned e, const Buf<Real> &bC, const B
             lam = tmax(unbm, unbp) + sqrt(g * (tmax(xbm, xbp) + hmid) * len2);
         else
             lam = tmax(unbm, unbp) + sqrt_approx(float(g * (double(tmax(xbm, xbp)) + hmid) * len2));
-        const Real sc = Real(dt_det);
+        // the flux's factor 1/2 rides on the scale (exact: a power of two)
+        const Real sc = Real(0.5 * dt_det);
         const Real hg = Real(0.5 * g);
         Real FX[NT], FU[NT], FV[NT];
         double FW[NT];
@@ -608,11 +609,11 @@ SWE_HD void edge_one(const MeshView &m, unsigned e, const Buf<Real> &bC, const B
             const Real pb = hg * (prod1<NX, Real>(c, txm, txm) + prod1<NX, Real>(c, txp, txp));
             const Real mU = prod1<NX, Real>(c, tUm, unm) + prod1<NX, Real>(c, tUp, unp);
             const Real mV = prod1<NX, Real>(c, tVm, unm) + prod1<NX, Real>(c, tVp, unp);
-            Real fx = Real(0.5) * (qnm[c] + qnp[c] + lam * (txm[c] - txp[c]));
+            Real fx = qnm[c] + qnp[c] + lam * (txm[c] - txp[c]);
             if (nb == NB_LAND) fx = 0;   // q.n = 0: no mass flux through land
             FX[c] = sc * fx;
-            FU[c] = sc * (Real(0.5) * (mU + pb * nx + lam * (tUm[c] - tUp[c])));
-            FV[c] = sc * (Real(0.5) * (mV + pb * ny + lam * (tVm[c] - tVp[c])));
+            FU[c] = sc * (mU + pb * nx + lam * (tUm[c] - tUp[c]));
+            FV[c] = sc * (mV + pb * ny + lam * (tVm[c] - tVp[c]));
             // bathymetry part of the pressure, (P- + P+)/2 = g (xi- + xi+) h_b / 2
             double w = 0.0;
 #pragma unroll
@@ -929,8 +930,10 @@ __device__ __forceinline__ void load_trace_lds(ShLds<P, Real> &S)
     }
 }
 
-// The Lax-Friedrichs flux of one edge item, in the first side's orientation
-// and unscaled by dt / |det B| (the edge pass of the shared-flux kernels).
+// The Lax-Friedrichs flux of one edge item, in the first side's orientation,
+// times two (its factor 1/2 is applied with dt / |det B| at the lift) and
+// unscaled by dt / |det B| (the edge pass of the shared-flux kernels); the
+// FP64 bathymetry part W is complete.
 template <int P, typename Real>
 __device__ __forceinline__ void sh_flux(const ShLds<P, Real> &S, const MeshView &m, const Buf<Real> &bC,
                                         const Buf<Real> &bU, const Buf<int> &bEv, const Buf<int> &bNb, unsigned e0,
@@ -1046,11 +1049,11 @@ __device__ __forceinline__ void sh_flux(const ShLds<P, Real> &S, const MeshView 
         const Real pb = hg * (prod1<NT, Real>(c, tm[0], tm[0]) + prod1<NT, Real>(c, tp[0], tp[0]));
         const Real mU = prod1<NT, Real>(c, tm[1], unm) + prod1<NT, Real>(c, tp[1], unp);
         const Real mV = prod1<NT, Real>(c, tm[2], unm) + prod1<NT, Real>(c, tp[2], unp);
-        Real fx = Real(0.5) * (qnm[c] + qnp[c] + lam * (tm[0][c] - tp[0][c]));
+        Real fx = qnm[c] + qnp[c] + lam * (tm[0][c] - tp[0][c]);
         if (kind == EK_LAND) fx = 0;   // q.n = 0: no mass flux through land
         F[0][c] = fx;
-        F[1][c] = Real(0.5) * (mU + pb * nx + lam * (tm[1][c] - tp[1][c]));
-        F[2][c] = Real(0.5) * (mV + pb * ny + lam * (tm[2][c] - tp[2][c]));
+        F[1][c] = mU + pb * nx + lam * (tm[1][c] - tp[1][c]);
+        F[2][c] = mV + pb * ny + lam * (tm[2][c] - tp[2][c]);
         // bathymetry part of the pressure, (P- + P+)/2 = g (xi- + xi+) h_b / 2
         double wv = 0.0;
 #pragma unroll
@@ -1083,7 +1086,8 @@ __device__ __forceinline__ void sh_store(ShLds<P, Real> &S, int i, unsigned w, c
 }
 
 // The passes over the block of elements [e0, e0 + BLOCK) (live below e_end),
-// whose edge items are items[0, nitems), nitems <= 2 BLOCK.  Every thread of
+// whose edge items are items[0, nitems), nitems <= 2 BLOCK (ITEM_PAD slots
+// among them are empty).  Every thread of
 // the block calls it (it holds three block barriers); the trace tables in S
 // are loaded before (the first barrier orders them before their first use).
 //   1. each lane (one element) loads its state into registers and copies it
@@ -1142,19 +1146,13 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
     // 2. the fluxes of this lane's (at most two) edge items
     const int n = nitems < 2 * BLOCK ? nitems : 2 * BLOCK;
     const int it0 = (int)l, it1 = (int)l + BLOCK;
-    unsigned w0 = 0u, w1 = 0u;
+    const unsigned w0 = it0 < n ? items[it0] : ITEM_PAD, w1 = it1 < n ? items[it1] : ITEM_PAD;
     ShItem<P, Real> r0, r1;
-    if (it0 < n) {
-        w0 = items[it0];
-        sh_flux<P, Real>(S, m, bC, bU, bEv, bNb, e0, w0, xihat, g, r0);
-    }
-    if (it1 < n) {
-        w1 = items[it1];
-        sh_flux<P, Real>(S, m, bC, bU, bEv, bNb, e0, w1, xihat, g, r1);
-    }
+    if (w0 != ITEM_PAD) sh_flux<P, Real>(S, m, bC, bU, bEv, bNb, e0, w0, xihat, g, r0);
+    if (w1 != ITEM_PAD) sh_flux<P, Real>(S, m, bC, bU, bEv, bNb, e0, w1, xihat, g, r1);
     __syncthreads();
-    if (it0 < n) sh_store<P, Real>(S, it0, w0, r0);
-    if (it1 < n) sh_store<P, Real>(S, it1, w1, r1);
+    if (w0 != ITEM_PAD) sh_store<P, Real>(S, it0, w0, r0);
+    if (w1 != ITEM_PAD) sh_store<P, Real>(S, it1, w1, r1);
     __syncthreads();
     if (!live) return;
     // base pass of the order-partitioned scheme: a listed element belongs to
@@ -1172,7 +1170,8 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
     volume_term<P, Real>(s, hbh, G, g, dt, A);
     source_term<P, Real>(s, G, a.ph, dt, A);
     const double dt_det = dt * G.idet;
-    const Real sc = Real(dt_det);
+    // the stored fluxes lack their factor 1/2: the scale carries it (exact)
+    const Real sc = Real(0.5 * dt_det);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int ka = (k + 1) % 3, kb = (k + 2) % 3;
