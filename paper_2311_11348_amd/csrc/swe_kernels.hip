@@ -675,6 +675,13 @@ SWE_HD void solve_u(const Real (&xi)[Ord<P>::K], const Real (&U)[Ord<P>::K],
                                         Real (&u)[Ord<P>::K], Real (&v)[Ord<P>::K])
 {
     constexpr int K = Ord<P>::K;
+    constexpr bool dbl = std::is_same<Real, double>::value;
+    // FP32: the total depth's modes H_n = xi_n + hb_n formed once (hb is
+    // linear: modes 0-2), H is needed to FP32's relative accuracy only;
+    // FP64: the bathymetry part summed on its own
+    Real Hm[K];
+#pragma unroll
+    for (int n = 0; n < K; ++n) Hm[n] = (!dbl && n < 3) ? xi[n] + Real(hbh[n < 3 ? n : 0]) : xi[n];
     Real M[K][K];
 #pragma unroll
     for (int i = 0; i < K; ++i)
@@ -685,12 +692,14 @@ SWE_HD void solve_u(const Real (&xi)[Ord<P>::K], const Real (&U)[Ord<P>::K],
             Real acc = 0;
 #pragma unroll
             for (int n = 0; n < kt; ++n)
-                if (TC[n][i][j] != 0.0) acc = fma(Real(TC[n][i][j]), xi[n], acc);
-            double hbp = 0.0;
+                if (TC[n][i][j] != 0.0) acc = fma(Real(TC[n][i][j]), Hm[n], acc);
+            if constexpr (dbl) {
+                double hbp = 0.0;
 #pragma unroll
-            for (int n = 0; n < 3; ++n)
-                if (TC[n][i][j] != 0.0) hbp = fma(TC[n][i][j], hbh[n], hbp);
-            acc += Real(hbp);
+                for (int n = 0; n < 3; ++n)
+                    if (TC[n][i][j] != 0.0) hbp = fma(TC[n][i][j], hbh[n], hbp);
+                acc += Real(hbp);
+            }
             if (i >= Ke || j >= Ke) acc = (i == j) ? Real(1) : Real(0);
             M[i][j] = acc;
         }
