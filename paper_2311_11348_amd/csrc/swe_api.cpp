@@ -403,7 +403,8 @@ hipError_t enqueue_adapt(Lanes &L, double tn)
 
 // Order-separated stage: base kernel over all elements (branch A) while the
 // corrections of the listed elements run on branch B; the epilogue of the
-// listed elements joins both on branch A.
+// listed elements joins both on branch A.  In one chain (adaptive step
+// graphs) the corrections follow the base pass and do the join themselves.
 template <typename Real>
 hipError_t enqueue_separated(Lanes &L, int mode, int in, int out, double tstage, double dt)
 {
@@ -430,8 +431,12 @@ hipError_t enqueue_separated(Lanes &L, int mode, int in, int out, double tstage,
     a.list = c->d_list;
     a.count = c->d_cnt;
     const int nblk = list_blocks(c), lcap = (int)c->ne;
+    // one chain: the corrections run after the base pass, so they join the
+    // base parts and finish the listed elements' stage themselves (the sum
+    // the epilogue would form, bit for bit), one dependent launch less
+    if (L.chain) a.finish = mode;
     e = launch_corr_all(b, pm, c->fp32, &a, dt, nblk, lcap, L.side());
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || L.chain) return e;
     e = L.join();
     if (e != hipSuccess) return e;
     return launch_epi_all(b, pm, c->fp32, mode, &a, nblk, lcap, L.a);

@@ -63,6 +63,9 @@ struct StageArgs {
     unsigned char *inlist;         // [stride] 1 if the element has a correction
     Real *Lb;            // [3][K(p_base)][stride] base partial stage values of listed elements
     Real *Lc;            // [3][KS][stride] dt * correction of listed elements
+    int finish;          // correction kernel: 0 leaves dt * correction in Lc for the
+                         // epilogue; MODE_STAGE1 / MODE_STAGE2 joins it with the base
+                         // part in Lb and finishes the listed element's stage itself
     const int *list;     // listed elements of one order
     const int *count;    // device-side length of list
     int *listw;          // [4][lcap] lists being rebuilt by the order update

@@ -1765,21 +1765,21 @@ k_full_all(StageArgs<Real> a, int lo, int lcap)
 // times the full right-hand side, minus dt times the base part (rows below
 // K(B), the element's and its neighbours' first K(B) modes) in the rows below
 // K(B); the base part is evaluated first and kept, negated, in registers
+// dt times the correction of listed element e of order P: its full
+// right-hand side minus its base one (rows below K(B); the base part reads
+// the element's and its neighbours' first K(B) modes); G and hbh are loaded
 template <int P, int B, int PN, typename Real>
-SWE_HD void corr_element(const StageArgs<Real> &a, unsigned e,
-                                             const Real (*sR)[Ord<PN>::K][PN + 1],
-                                             const Real (*sRb)[Ord<B>::K][Ord<B>::NT], double xihat, double dt)
+SWE_HD void corr_value(const StageArgs<Real> &a, unsigned e, const Real (*sR)[Ord<PN>::K][PN + 1],
+                       const Real (*sRb)[Ord<B>::K][Ord<B>::NT], double xihat, double dt, Geo &G,
+                       double (&hbh)[3], Real (&C)[3][Ord<P>::K])
 {
     constexpr int K = Ord<P>::K, KB = Ord<B>::K;
     const MeshView &m = a.m;
     const int KS = m.KS, stride = m.stride;
     const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
     const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
-    const Buf<Real> bL(a.Lc, 3 * KS, stride);
     const unsigned off = e * (unsigned)sizeof(Real);
-    Geo G;
     load_geo(m.vtx, bEv, e * 4u, G);
-    double hbh[3];
     hb_modes(G, hbh);
     Real minus_base[3][KB];
     {
@@ -1804,8 +1804,50 @@ SWE_HD void corr_element(const StageArgs<Real> &a, unsigned e,
         for (int q = 0; q < K; ++q) {
             Real v = A.L[j][q];
             if (q < KB) v += minus_base[j][q];
-            bL.st(j * KS + q, off, v);
+            C[j][q] = v;
         }
+}
+
+// the correction of listed element e stored in Lc (for the epilogue)
+template <int P, int B, int PN, typename Real>
+SWE_HD void corr_element(const StageArgs<Real> &a, unsigned e,
+                                             const Real (*sR)[Ord<PN>::K][PN + 1],
+                                             const Real (*sRb)[Ord<B>::K][Ord<B>::NT], double xihat, double dt)
+{
+    constexpr int K = Ord<P>::K;
+    const int KS = a.m.KS, stride = a.m.stride;
+    const Buf<Real> bL(a.Lc, 3 * KS, stride);
+    const unsigned off = e * (unsigned)sizeof(Real);
+    Geo G;
+    double hbh[3];
+    Real C[3][K];
+    corr_value<P, B, PN, Real>(a, e, sR, sRb, xihat, dt, G, hbh, C);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int q = 0; q < K; ++q) bL.st(j * KS + q, off, C[j][q]);
+}
+
+// The epilogue joined into the correction kernel (a.finish set: the base
+// pass has run before it, not beside it): stage value = (the base partial
+// value in Lb, or c for modes >= K(B)) + the correction C, the same sum the
+// epilogue forms, then the listed element's stage finished
+template <int P, int B, typename Real>
+__device__ __forceinline__ void join_finish(const StageArgs<Real> &a, unsigned e, const Geo &G,
+                                            const double (&hbh)[3], Real (&C)[3][Ord<P>::K])
+{
+    constexpr int K = Ord<P>::K, KB = Ord<B>::K;
+    const int KS = a.m.KS, stride = a.m.stride;
+    const Buf<Real> bC(a.Cin, 3 * KS, stride), bB(a.Lb, 3 * KB, stride);
+    const unsigned off = e * (unsigned)sizeof(Real);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int q = 0; q < K; ++q) C[j][q] = (q < KB ? bB.ld(j * KB + q, off) : bC.ld(j * KS + q, off)) + C[j][q];
+    if (a.finish == MODE_STAGE2)
+        finish_stage<P, Real, MODE_STAGE2>(a, e, G, hbh, K, C, a.flag);
+    else
+        finish_stage<P, Real, MODE_STAGE1>(a, e, G, hbh, K, C, a.flag);
 }
 
 // correction of listed element e of order P by a team: each wave's part of
@@ -1827,10 +1869,10 @@ __device__ __forceinline__ void corr_team(const StageArgs<Real> &a, int le, int 
     const Buf<Real> bC(a.Cin, 3 * KS, stride), bU(a.Uin, 2 * KS, stride);
     const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
     Acc<P, Real> A;
+    Geo G;
+    double hbh[3];
     if (live) {
-        Geo G;
         load_geo(m.vtx, bEv, e * 4u, G);
-        double hbh[3];
         hb_modes(G, hbh);
         Fields<P, Real> s;
         load_state<P, Real>(bC, bU, KS, off, s);
@@ -1861,12 +1903,34 @@ __device__ __forceinline__ void corr_team(const StageArgs<Real> &a, int le, int 
     __syncthreads();
     if (role == 0 && live) {
         team_sum<P, PN, Real>(X, lane, A);
+        if (a.finish) {
+            join_finish<P, B, Real>(a, e, G, hbh, A.L);
+            return;
+        }
         const Buf<Real> bL(a.Lc, 3 * KS, stride);
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int q = 0; q < K; ++q) bL.st(j * KS + q, off, A.L[j][q]);
     }
+}
+
+// correction of listed element e by one thread: stored for the epilogue, or
+// joined with the base part and the stage finished (a.finish)
+template <int P, int B, int PN, typename Real>
+__device__ __forceinline__ void corr_thread(const StageArgs<Real> &a, unsigned e,
+                                            const Real (*sR)[Ord<PN>::K][PN + 1],
+                                            const Real (*sRb)[Ord<B>::K][Ord<B>::NT], double xihat, double dt)
+{
+    if (!a.finish) {
+        corr_element<P, B, PN, Real>(a, e, sR, sRb, xihat, dt);
+        return;
+    }
+    Geo G;
+    double hbh[3];
+    Real C[3][Ord<P>::K];
+    corr_value<P, B, PN, Real>(a, e, sR, sRb, xihat, dt, G, hbh, C);
+    join_finish<P, B, Real>(a, e, G, hbh, C);
 }
 
 template <int B, int PN, typename Real>
@@ -1909,9 +1973,9 @@ k_corr_all(StageArgs<Real> a, double dt, int lcap)
         if (le < 0) return;
         const unsigned e = (unsigned)le;
         switch (p) {
-        case 0: if constexpr (B <= 0) corr_element<0, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
-        case 1: if constexpr (B <= 1 && PN >= 1) corr_element<1, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
-        case 2: if constexpr (B <= 2 && PN >= 2) corr_element<2, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
+        case 0: if constexpr (B <= 0) corr_thread<0, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
+        case 1: if constexpr (B <= 1 && PN >= 1) corr_thread<1, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
+        case 2: if constexpr (B <= 2 && PN >= 2) corr_thread<2, B, PN, Real>(a, e, sR, sRb, xihat, dt); break;
         }
     }
 }
