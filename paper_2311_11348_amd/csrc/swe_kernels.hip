@@ -881,6 +881,16 @@ constexpr int sh_waves()
     return dbl ? (P == 1 ? 3 : P == 3 ? 1 : 2) : (P == 2 ? 4 : P == 3 ? 2 : 3);
 }
 
+// The batch form at FP32 order 3 loads the geometry after the edge pass and
+// runs three waves per SIMD (168 registers, no spill; its LDS, 53 KB per
+// block, allows three blocks per CU); the single-instance form, which also
+// carries the separated scheme's base-pass paths, would spill there.
+template <int P, typename Real>
+constexpr bool batch_sh_fp32p3()
+{
+    return !std::is_same<Real, double>::value && P == 3;
+}
+
 // Per-block LDS.  The state copy C is read by the edge pass only; the
 // per-item results F, W are written after it (every lane holds its items'
 // results in registers across a barrier), so the two share the storage.
@@ -1108,7 +1118,7 @@ __device__ __forceinline__ void sh_store(ShLds<P, Real> &S, int i, unsigned w, c
 //      each stored for its first side and, for a pair, for the second;
 //   3. each lane adds its volume and source terms, lifts its three edge
 //      fluxes with its own geometry and finishes the stage.
-template <int P, typename Real, int MODE>
+template <int P, typename Real, int MODE, bool EARLY_GEO = !std::is_same<Real, double>::value && P == 3>
 __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArgs<Real> &a, unsigned e0,
                                                unsigned e_end, const unsigned *items, int nitems, double xihat,
                                                double dt, int *flag)
@@ -1123,11 +1133,11 @@ __device__ __forceinline__ void stage_sh_block(ShLds<P, Real> &S, const StageArg
     const Buf<int> bEv(m.ev, 3, stride), bNb(m.enb, 3, stride);
     const double g = a.ph.g;
 
-    // 1. state to registers and LDS; at FP32 order 3 also the geometry, whose
-    //    latency then hides behind the edge pass (elsewhere the registers it
-    //    would hold across that pass cost a wave per SIMD: only the vertex ids
-    //    are loaded here, the vertices after the edge pass)
-    constexpr bool early_geo = !std::is_same<Real, double>::value && P == 3;
+    // 1. state to registers and LDS; at FP32 order 3 (two waves per SIMD) also
+    //    the geometry, whose latency then hides behind the edge pass (elsewhere
+    //    the registers it would hold across that pass cost a wave per SIMD:
+    //    only the vertex ids are loaded here, the vertices after the edge pass)
+    constexpr bool early_geo = EARLY_GEO;
     Fields<P, Real> s;
     Geo G;
     double hbh[3];
@@ -1421,7 +1431,8 @@ k_batch_stage(BatchArgs b)
 // starts on a multiple of 256 within its instance, so the instance's edge
 // items of that block (local indices) serve it unchanged.
 template <int P, typename Real, int MODE>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sh_waves<P, Real>(), 8)))
+__global__ void __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(batch_sh_fp32p3<P, Real>() ? 3 : sh_waves<P, Real>(), 8)))
 k_batch_stage_sh(BatchArgs b)
 {
     __shared__ ShLds<P, Real> S;
@@ -1454,9 +1465,10 @@ k_batch_stage_sh(BatchArgs b)
     a.mixed = 0;
     a.ph = I.ph;
     const unsigned e0 = (unsigned)tile.y;
-    stage_sh_block<P, Real, MODE>(S, a, e0, (unsigned)(I.first + I.ne), b.pool.items + 3u * e0,
-                                  b.pool.nitems[e0 / BLOCK], MODE == MODE_STAGE1 ? I.xh[0] : I.xh[1], I.dt,
-                                  b.flags + tile.x);
+    // the batch form loads the geometry after the edge pass at every order
+    stage_sh_block<P, Real, MODE, false>(S, a, e0, (unsigned)(I.first + I.ne), b.pool.items + 3u * e0,
+                                         b.pool.nitems[e0 / BLOCK], MODE == MODE_STAGE1 ? I.xh[0] : I.xh[1], I.dt,
+                                         b.flags + tile.x);
 }
 
 // Copy an instance's edge items (blocks of 256 elements, item_off[nblk + 1])
