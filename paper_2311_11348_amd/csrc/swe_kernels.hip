@@ -1883,11 +1883,31 @@ __device__ __forceinline__ void corr_team(const StageArgs<Real> &a, int le, int 
     Acc<P, Real> A;
     Geo G;
     double hbh[3];
+    // wave 0 of a kernel that finishes the stage (a.finish) fetches what the
+    // join needs before its volume work, so the loads overlap it: the base
+    // part (c itself above K(B)) and, in the second stage, c^n
+    const bool join = role == 0 && a.finish;
+    Real Jb[3][K], Jn[3][K];
     if (live) {
         load_geo(m.vtx, bEv, e * 4u, G);
         hb_modes(G, hbh);
         Fields<P, Real> s;
         load_state<P, Real>(bC, bU, KS, off, s);
+        if (join) {
+            const Buf<Real> bB(a.Lb, 3 * KB, stride), bN(a.Cn, 3 * KS, stride);
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                Jb[0][q] = q < KB ? bB.ld(0 * KB + q, off) : s.xi[q];
+                Jb[1][q] = q < KB ? bB.ld(1 * KB + q, off) : s.U[q];
+                Jb[2][q] = q < KB ? bB.ld(2 * KB + q, off) : s.V[q];
+            }
+            if (a.finish == MODE_STAGE2) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int q = 0; q < K; ++q) Jn[j][q] = bN.ld(j * KS + q, off);
+            }
+        }
         {
             Fields<B, Real> sb;
 #pragma unroll
@@ -1915,8 +1935,20 @@ __device__ __forceinline__ void corr_team(const StageArgs<Real> &a, int le, int 
     __syncthreads();
     if (role == 0 && live) {
         team_sum<P, PN, Real>(X, lane, A);
-        if (a.finish) {
-            join_finish<P, B, Real>(a, e, G, hbh, A.L);
+        if (join) {
+            // the epilogue's sum and, in the second stage, the RK combine, in
+            // the expressions of join_finish and finish_stage (bit for bit)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int q = 0; q < K; ++q) A.L[j][q] = Jb[j][q] + A.L[j][q];
+            if (a.finish == MODE_STAGE2) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int q = 0; q < K; ++q) A.L[j][q] = Real(0.5) * Jn[j][q] + Real(0.5) * A.L[j][q];
+            }
+            finish_stage<P, Real, MODE_STAGE1>(a, e, G, hbh, K, A.L, a.flag);
             return;
         }
         const Buf<Real> bL(a.Lc, 3 * KS, stride);
