@@ -21,6 +21,17 @@
 // Jacobian, the edge normals and |E|/|det B_e| enter.  Terms carrying the
 // bathymetry (well-balancing: g xi h_b in the flux, g xi grad h_b in the
 // source) are always accumulated in FP64.
+//
+// Kernel families below: the element-gather stage above (k_stage); the
+// shared-flux stage (k_stage_sh, stage_sh_block), where each edge flux
+// inside a block of 256 elements is computed once from host-built edge
+// items and handed to both sides through LDS; the listed elements of the
+// order-separated and order-partitioned schemes (k_corr_all, k_full_all,
+// k_epi_all), by teams of four waves per 64 entries or one element per
+// thread, with the correction kernel doing the epilogue's join itself when
+// it runs after the base pass in one chain; the order update (k_indicator,
+// k_apply_order); the batch forms of the stage and order update; the
+// minimum depth control; the FP64 mass reduction.
 #include "swe_internal.h"
 #include "swe_tables.h"
 
